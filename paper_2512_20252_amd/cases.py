@@ -1,0 +1,80 @@
+"""Workload descriptions and seeded synthetic inputs.
+
+This module holds parameter values and random draws only; none of the
+method's arithmetic lives here, so the HIP library and the CPU oracle can
+both consume its outputs without sharing any computation.
+
+A case is a plain dict: grid (dim, n, lo, hi, outer), velocity grid (vn, vlo,
+vhi, rule), geometry (geometry, center, size, aoa), physics (Kn, Ma, Pr,
+gamma, alpha, Tw) and numerics (cfl, omega_vhs, a_vhs, flags).
+"""
+import numpy as np
+
+BASE = dict(Pr=2.0 / 3.0, gamma=5.0 / 3.0, alpha=1.0, Tw=1.0, cfl=0.5, omega_vhs=0.81, a_vhs=1.0,
+            outer="freestream", rule="midpoint", geometry="none", center=(0.0, 0.0, 0.0),
+            size=(0.0, 0.0, 0.0), aoa=0.0, flags=())
+
+
+def case(**kw):
+    c = dict(BASE)
+    c.update(kw)
+    return c
+
+
+def cylinder_small():
+    """2D cylinder, plain FP64: [-1,1]^2 on 32x32, R=0.3, 16x16 trapezoid
+    velocity grid on [-5,5]^2, Ma 0.5, Kn 0.1, diffuse wall at T_inf."""
+    return case(dim=2, n=(32, 32), lo=(-1.0, -1.0), hi=(1.0, 1.0), vn=(16, 16), vlo=(-5.0, -5.0),
+                vhi=(5.0, 5.0), rule="trapezoid", geometry="circle", size=(0.3, 0.0, 0.0),
+                Kn=0.1, Ma=0.5)
+
+
+def cylinder_256(Kn=0.1, Ma=0.3, n=256, vn=48):
+    """2D cylinder: [-8,8]^2 on 256x256, R=0.5, 48x48 midpoint velocity grid
+    on [-6,6]^2 (the throughput workload)."""
+    return case(dim=2, n=(n, n), lo=(-8.0, -8.0), hi=(8.0, 8.0), vn=(vn, vn), vlo=(-6.0, -6.0),
+                vhi=(6.0, 6.0), geometry="circle", size=(0.5, 0.0, 0.0), Kn=Kn, Ma=Ma)
+
+
+CYLINDER_256_SWEEP = [(Kn, Ma) for Kn in (0.01, 0.1, 1.0) for Ma in (0.3, 2.0)]
+
+
+def hypersonic_bodies(seed=0, nx=512, ny=384, vn=64):
+    """2D ellipse and symmetric 4-digit airfoil at Ma 5, Kn 0.05, alpha 0.8 on
+    [-3,7]x[-3.75,3.75]; thickness t~U(0.08,0.2), angle of attack ~U(0,8 deg)
+    and ellipse aspect ~U(1,4) drawn in that order from the seed."""
+    rng = np.random.default_rng(seed)
+    t = float(rng.uniform(0.08, 0.2))
+    aoa = float(np.deg2rad(rng.uniform(0.0, 8.0)))
+    aspect = float(rng.uniform(1.0, 4.0))
+    common = dict(dim=2, n=(nx, ny), lo=(-3.0, -3.75), hi=(7.0, 3.75), vn=(vn, vn), vlo=(-10.0, -10.0),
+                  vhi=(10.0, 10.0), Kn=0.05, Ma=5.0, alpha=0.8)
+    airfoil = case(geometry="airfoil", center=(0.0, 0.0, 0.0), size=(1.0, t, 0.0), aoa=aoa, **common)
+    ellipse = case(geometry="ellipse", center=(0.5, 0.0, 0.0), size=(0.5, 0.5 / aspect, 0.0), aoa=aoa, **common)
+    return airfoil, ellipse
+
+
+def sphere(n=96, vn=24):
+    """3D sphere R=0.5 in [-4,4]^3, full distribution on a vn^3 midpoint grid
+    on [-6,6]^3, Kn 0.1, Ma 1.5, diffuse wall at T_inf."""
+    return case(dim=3, n=(n, n, n), lo=(-4.0, -4.0, -4.0), hi=(4.0, 4.0, 4.0), vn=(vn, vn, vn),
+                vlo=(-6.0, -6.0, -6.0), vhi=(6.0, 6.0, 6.0), geometry="sphere", size=(0.5, 0.0, 0.0),
+                Kn=0.1, Ma=1.5)
+
+
+def n_cells(c):
+    return int(np.prod(c["n"][: c["dim"]]))
+
+
+def n_vel(c):
+    return int(np.prod(c["vn"][: c["dim"]]))
+
+
+def noise(c, seed=0):
+    """Uniform(-1,1) perturbation fields, one per distribution array (h then b
+    in 2D; f in 3D), each of shape (cells, velocity nodes) in C order, drawn
+    from numpy's default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    shape = (n_cells(c), n_vel(c))
+    na = 2 if c["dim"] == 2 else 1
+    return tuple(rng.uniform(-1.0, 1.0, size=shape) for _ in range(na))
