@@ -23,6 +23,7 @@
  * reduced distributions); in 3D there is one array f.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -488,8 +489,23 @@ static void maxwellian(const or_state *s, double rho, const double U[3], double 
 
 static double seg_root(const or_state *s, const double xg[3], const double xd[3], int a)
 {
-    /* bisection on phi along the axis segment from the ghost centre (phi<0)
-     * to the donor centre (phi>=0) */
+    const or_case *c = &s->c;
+    if (c->gkind == OR_G_CIRCLE || c->gkind == OR_G_SPHERE) {
+        /* crossing of the axis line with the circle / sphere in closed form:
+         * (t - c_a)^2 = R^2 - sum_{b != a} (x_b - c_b)^2, on the donor side.
+         * Bisection on phi cannot place a grazing crossing better than about
+         * sqrt(ulp(R^2)) because x^2 + rest rounds to rest there. */
+        double rest = 0.0;
+        for (int b = 0; b < s->D; ++b)
+            if (b != a) rest += (xg[b] - c->gcen[b]) * (xg[b] - c->gcen[b]);
+        double h = c->gsize[0] * c->gsize[0] - rest;
+        double sgn = xd[a] > xg[a] ? 1.0 : -1.0;
+        double t = c->gcen[a] + sgn * sqrt(h > 0.0 ? h : 0.0);
+        double lo = xg[a] < xd[a] ? xg[a] : xd[a], hi = xg[a] < xd[a] ? xd[a] : xg[a];
+        return t < lo ? lo : (t > hi ? hi : t);
+    }
+    /* other shapes: bisection on phi along the axis segment from the ghost
+     * centre (phi<0) to the donor centre (phi>=0) */
     double lo = xg[a], hi = xd[a];
     double x[3] = {xg[0], xg[1], xg[2]};
     for (int it = 0; it < 400; ++it) {
@@ -1204,6 +1220,18 @@ void or_freestream(void *h, double *f0, double *f1)
 }
 
 double or_mu0(void *h) { return ((or_state *)h)->mu0; }
+
+/* threads the OpenMP loops of the oracle use */
+int or_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
 
 /* integer index sets: cell solid flags; per pair gc, dc, ac, axis, sign, ns,
  * then 26 surface-cell indices (-1 padded); per pair velocity classes */

@@ -72,6 +72,8 @@ def lib():
         L.or_freestream.argtypes = [vp, dp, dp]
         L.or_mu0.argtypes = [vp]
         L.or_mu0.restype = ctypes.c_double
+        L.or_threads.argtypes = []
+        L.or_threads.restype = ctypes.c_int
         L.or_index_sets.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_uint8)]
         L.or_pair_geometry.argtypes = [vp, dp, dp]
@@ -121,6 +123,11 @@ def _case_struct(case):
         fl |= FLAGS[f]
     c.flags = fl
     return c
+
+
+def threads():
+    """OpenMP threads the oracle's cell loops run on."""
+    return int(lib().or_threads())
 
 
 class Oracle:
