@@ -1,0 +1,147 @@
+"""Throughput of the immersed-boundary Shakhov-DVM step on one MI355X.
+
+One step = ghost construction for every ghost-donor pair, upwind MUSCL
+fluxes, Shakhov relaxation and forward Euler update of every fluid cell and
+velocity node, and the moments of the new state.  The workload is the 2D
+cylinder at full size: [-8,8]^2 on 256x256 cells, radius 0.5, 48x48 midpoint
+velocity grid on [-6,6]^2, Kn 0.1, Ma 0.3, freestream Maxwellian with seeded
+1e-3 perturbation (synthetic input of the shape of the paper's cylinder
+cases).
+
+Prints one JSON line: cell-velocity updates/s of the FP64 step, the
+roofline of the update kernel (algorithmic HBM bytes per launch over its
+HIP-event duration), the FP32-storage form's rate and C_D difference, and
+the CPU oracle timed on this host over one step of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+B_ALG = {(2, "f64"): 32, (2, "f32"): 16, (3, "f64"): 16, (3, "f32"): 8}
+
+
+def _kernel_sha():
+    with open(os.path.join(ROOT, "paper_2512_20252_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic(workload, precision, launches_bytes):
+    """HBM bytes per update launch from committed rocprofv3 counter runs,
+    or None when they are missing or were taken on a different kernel."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha") != _kernel_sha():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(case, precision, steps, warmup, seed=0, profile=True):
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    s = ibdvm.Solver(case, precision=precision)
+    s.init_freestream(cases.noise(case, seed), 1e-3)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    if profile:
+        s.profile(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    s.step(steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    prof = s.profile_read() if profile else None
+    _, cd, _, _ = s.surface_forces()
+    out = {"ms": ms, "prof": prof, "cd": cd, "nfluid": s.nfluid, "NV": s.NV, "dim": s.dim}
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, seed=0):
+    from oracle import oracle as oracle_mod
+    from paper_2512_20252_amd import cases
+
+    o = oracle_mod.Oracle(case)
+    o.init_freestream(cases.noise(case, seed), 1e-3)
+    t = time.perf_counter()
+    o.step(1)
+    dt = time.perf_counter() - t
+    return {"value": o.nfluid * o.NV / dt, "unit": "cell*vel updates/s", "cores": oracle_mod.threads(),
+            "kind": "oracle", "sample": "1 step of the same 256x256 x 48x48 workload (all fluid cells), "
+                                        "OpenMP over cells, sequential velocity sums", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(the step shards by velocity range across GPUs in design, not in code)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2512_20252_amd import cases
+
+    case = cases.cylinder_256(Kn=0.1, Ma=0.3)
+    workload = "cylinder_256x256_v48x48"
+    r64 = run_gpu(case, "f64", args.steps, args.warmup)
+    upd = r64["nfluid"] * r64["NV"]
+    value = upd * args.steps / (r64["ms"] * 1e-3)
+    prof = r64["prof"]
+    avg_ms = prof["update_ms"] / max(prof["update_launches"], 1)
+    bytes_launch = upd * B_ALG[(r64["dim"], "f64")]
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    traffic = _traffic(workload, "f64", bytes_launch)
+    line = {
+        "metric": "cell*vel updates/s & %HBM peak, FP32-store vs FP64 at fixed C_D err; p50/p99",
+        "value": value,
+        "unit": "cell*vel updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
+                               "Kn 0.1, Ma 0.3, Shakhov, diffuse wall, FP64",
+                   "cells": 65536, "fluid_cells": r64["nfluid"], "velocity_nodes": r64["NV"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
+                     "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
+                     "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1)},
+    }
+    if not args.no_f32:
+        r32 = run_gpu(case, "f32", args.steps, args.warmup)
+        v32 = upd * args.steps / (r32["ms"] * 1e-3)
+        avg32 = r32["prof"]["update_ms"] / max(r32["prof"]["update_launches"], 1)
+        line["precision_form"] = {"dtype": "f32 storage, f64 moments/equilibrium/wall", "value": v32,
+                                  "ratio_vs_f64": v32 / value, "dCD_vs_f64": abs(r32["cd"] - r64["cd"]),
+                                  "CD_f64": r64["cd"], "update_avg_launch_ms": avg32,
+                                  "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

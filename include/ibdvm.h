@@ -1,0 +1,228 @@
+/*
+ * ibdvm.h -- C ABI of the MI355X immersed-boundary discrete-velocity step.
+ *
+ * The library advances the discrete velocity model of the Shakhov equation
+ * (arXiv 2512.20252, Section 2.2 semi-discrete form with the forward Euler
+ * march of Section 4) on a uniform Cartesian grid with a ghost-cell immersed
+ * boundary (Section 3.2: upwind-weighted compact interpolation, Maxwell
+ * gas-surface interaction of Section 2.3, velocity-space cut-cell correction
+ * of Section 3.2.3).  2D problems use the reduced distributions h, b of
+ * Section 4; 3D problems carry the full distribution f.
+ *
+ * Units follow Section 4: lengths in the coordinate unit (Kn is relative to
+ * it), velocities in sqrt(2 R T_inf), rho_inf = T_inf = 1, p = rho T / 2,
+ * freestream velocity (Ma sqrt(gamma/2), 0, 0).
+ *
+ * Memory and ownership
+ *   - All device memory is the caller's: one device buffer of at least
+ *     ibdvm_footprint() bytes passed in ibdvm_opts.workspace.  The library
+ *     never allocates device memory; ibdvm_destroy frees only the host-side
+ *     context.
+ *   - The caller owns the HIP stream (ibdvm_opts.stream, a hipStream_t; NULL
+ *     is the null stream).  ibdvm_step only enqueues work on it.
+ *   - Host arrays passed in are read before the call returns; host arrays
+ *     passed out are written before the call returns.
+ *   - Array layouts: cell c = i + n0*(j + n1*l) (x fastest); velocity node
+ *     k = ix + N0*(iy + N1*iz); distributions [cell][node], node innermost.
+ *
+ * Errors
+ *   - Every entry point returns an ibdvm_status; no exception crosses the ABI.
+ *     ibdvm_last_error() returns a thread-local message for the last failure.
+ *   - A context whose device health word reports NaN, rho <= 0 or T <= 0
+ *     returns IBDVM_E_UNSTABLE at the next synchronising call and then
+ *     IBDVM_E_STATE for every compute call until it is destroyed.
+ *   - One context is used by one host thread at a time; distinct contexts
+ *     are independent.
+ */
+#ifndef IBDVM_H
+#define IBDVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ibdvm_ctx ibdvm_ctx;
+
+typedef enum {
+    IBDVM_OK = 0,
+    IBDVM_E_INVALID_ARG = 1, /* a parameter is out of range or a pointer is NULL */
+    IBDVM_E_GEOMETRY = 2,    /* body too close to the outer boundary (< 3 cells) */
+    IBDVM_E_NO_MEMORY = 3,   /* workspace smaller than ibdvm_footprint() */
+    IBDVM_E_DEVICE = 4,      /* a HIP runtime call failed */
+    IBDVM_E_UNSTABLE = 5,    /* the device health word reported NaN, rho<=0 or T<=0 */
+    IBDVM_E_UNSUPPORTED = 6, /* combination not implemented */
+    IBDVM_E_STATE = 7        /* context unusable (host-only or previously unstable) */
+} ibdvm_status;
+
+enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1 };
+enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1 };
+enum {
+    IBDVM_GEOM_NONE = 0,
+    IBDVM_GEOM_CIRCLE = 1,  /* 2D, size[0] = radius */
+    IBDVM_GEOM_ELLIPSE = 2, /* 2D, size[0], size[1] = semi-axes, rotated by aoa about the centre */
+    IBDVM_GEOM_AIRFOIL = 3, /* 2D, centre = leading edge, size[0] = chord, size[1] = thickness ratio */
+    IBDVM_GEOM_SPHERE = 4   /* 3D, size[0] = radius */
+};
+enum { IBDVM_F64 = 0, IBDVM_F32_STORE = 1 };
+enum {
+    IBDVM_FLAG_NO_CUTCELL = 1u << 0, /* ablation: classify velocity cells by node sign only */
+    IBDVM_FLAG_NO_UPWIND = 1u << 1,  /* ablation: uniform weights 1/N_S in the ghost interpolation */
+    IBDVM_FLAG_HOST_ONLY = 1u << 8   /* build the geometry tables only; no device work */
+};
+
+/* uniform cell-centred Cartesian grid; dim 2 or 3, n[a] >= 4 */
+typedef struct {
+    int32_t dim;
+    int32_t n[3];
+    double lo[3], hi[3];
+    int32_t outer_bc;
+} ibdvm_grid;
+
+/* tensor velocity grid (Section 2.2 quadrature): midpoint nodes at
+ * lo + (i + 1/2) h with h = (hi - lo)/N, or trapezoid nodes lo + i h with
+ * h = (hi - lo)/(N - 1) and half weights at the ends; the box must be
+ * symmetric about 0 */
+typedef struct {
+    int32_t n[3];
+    double lo[3], hi[3];
+    int32_t rule;
+} ibdvm_vgrid;
+
+typedef struct {
+    int32_t kind;
+    double center[3];
+    double size[3];
+    double aoa_rad;
+} ibdvm_geometry;
+
+typedef struct {
+    int32_t precision;      /* IBDVM_F64 or IBDVM_F32_STORE */
+    double cfl;             /* time-step safety factor in (0, 1] */
+    double omega_vhs;       /* viscosity exponent (0.81 for argon, Section 4) */
+    double a_vhs;           /* VSS/VHS alpha in the reference viscosity (1.0) */
+    uint32_t flags;         /* IBDVM_FLAG_* */
+    void *workspace;        /* device buffer, >= ibdvm_footprint() bytes, 256-byte aligned */
+    size_t workspace_bytes;
+    void *stream;           /* hipStream_t */
+} ibdvm_opts;
+
+/* one wall point per ghost-donor pair: intersect point, unit normal (into the
+ * gas), wall density rho_w and wall pressure p_w = sum w xi_n^2 f*_w */
+typedef struct {
+    double xw[3];
+    double nw[3];
+    double rho_w;
+    double p_w;
+} ibdvm_wall_point;
+
+/* Bytes of device workspace a problem needs (state double buffer, per-cell
+ * moments, geometry tables, per-pair buffers).  Host only; builds the
+ * geometry to count pairs. */
+ibdvm_status ibdvm_footprint(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, const ibdvm_geometry *geom,
+                             const ibdvm_opts *opts, size_t *bytes);
+
+/* Build a solve (Sections 3.2.1-3.2.3 for the geometry, Section 4 for the
+ * constants): validates Kn > 0, Ma >= 0, Pr > 0, gamma > 1, 0 <= alpha <= 1,
+ * T_w > 0; classifies cells, builds ghost-donor pairs, surface-cell lists
+ * and cut-cell sets, uploads the tables into the workspace on the stream and
+ * sets the state to the freestream Maxwellian.  With IBDVM_FLAG_HOST_ONLY
+ * only the host tables are built (workspace may be NULL). */
+ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, const ibdvm_geometry *geom, double Kn,
+                          double Ma, double Pr, double gamma, double alpha, double T_w, const ibdvm_opts *opts,
+                          ibdvm_ctx **out);
+
+/* Frees the host context (not the workspace). */
+void ibdvm_destroy(ibdvm_ctx *ctx);
+
+/* Sizes: out[0..6] = dim, cells, velocity nodes, arrays per cell (2: h,b;
+ * 1: f), pairs, fluid cells, ghost cells. */
+ibdvm_status ibdvm_info(const ibdvm_ctx *ctx, int64_t out[7]);
+
+/* State := freestream Maxwellian times (1 + amp * u), u given per (cell,
+ * node) for each array (host, [cells][nodes] doubles); NULL arrays mean no
+ * perturbation.  Synchronises. */
+ibdvm_status ibdvm_init_freestream(ibdvm_ctx *ctx, const double *u0, const double *u1, double amp);
+
+/* State := caller arrays (host doubles, [cells][nodes]; f1 ignored in 3D);
+ * rounded to the storage precision.  Synchronises. */
+ibdvm_status ibdvm_set_state(ibdvm_ctx *ctx, const double *f0, const double *f1);
+
+/* Copies the state to host doubles.  Synchronises. */
+ibdvm_status ibdvm_get_state(ibdvm_ctx *ctx, double *f0, double *f1);
+
+/* Enqueues nsteps forward-Euler steps on the context stream: ghost-cell
+ * construction (Section 3.2), upwind MUSCL fluxes (Section 2.2) and Shakhov
+ * relaxation with moments of the new state, time step
+ * cfl / (sum_a max|xi_a|/dx_a + 1/tau_min). */
+ibdvm_status ibdvm_step(ibdvm_ctx *ctx, int32_t nsteps);
+
+/* Per-cell moments of the current state (Section 2.1): out[cell][8] =
+ * rho, U0, U1, U2, T, q0, q1, q2 (NaN in solid cells).  out_is_device != 0:
+ * out is a device pointer and the copy is enqueued on the stream; otherwise
+ * host memory, and the call synchronises. */
+ibdvm_status ibdvm_moments(ibdvm_ctx *ctx, double *out, int32_t out_is_device);
+
+/* Force on the body from the momentum flux through the immersed-boundary
+ * faces, drag and lift coefficients (reference length 2R for circle and
+ * ellipse (major axis), chord for the airfoil, pi R^2 for the sphere) and up
+ * to cap wall points.  Runs the ghost construction on the current state.
+ * Synchronises. */
+ibdvm_status ibdvm_surface_forces(ibdvm_ctx *ctx, double force[3], double *C_D, double *C_L, ibdvm_wall_point *pts,
+                                  int32_t cap, int32_t *n_pts);
+
+/* Time step of the last step, simulated time and step count.  Synchronises. */
+ibdvm_status ibdvm_clock(ibdvm_ctx *ctx, double *dt, double *time, int64_t *step);
+
+/* Geometry index sets (host copies; valid on host-only contexts):
+ * solid[cells] (1 = centre inside the body); pairs[npairs][32] =
+ * ghost, donor, auxiliary (-1: none), axis, sign, N_S, 26 surface cells
+ * (-1 padded); cls[npairs][nodes] = 0 incident, 1 reflected, 2 cut with node
+ * on the incident side, 3 cut with node on the reflected side.  Any output
+ * pointer may be NULL. */
+ibdvm_status ibdvm_index_sets(const ibdvm_ctx *ctx, uint8_t *solid, int32_t *pairs, uint8_t *cls);
+
+/* Geometry FP64 tables (host copies): g9[npairs][9] = x_w, n_w, x_sp;
+ * wg[npairs][nodes] = incident-side measure of each velocity dual cell. */
+ibdvm_status ibdvm_pair_geometry(const ibdvm_ctx *ctx, double *g9, double *wg);
+
+/* Runs the ghost construction on the current state and copies per-pair
+ * buffers to host: ghost values and ghost-side face values
+ * [arrays][npairs][nodes] and rho_w[npairs].  Synchronises. */
+ibdvm_status ibdvm_wall_state(ibdvm_ctx *ctx, double *ghost, double *face, double *rho_w);
+
+/* Advances several contexts that share one stream by nsteps each, interleaving
+ * their launches step by step (serving form).  Results equal those of
+ * advancing each context alone. */
+ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps);
+
+/* Tile of the 2D update kernel: V velocity nodes per lane (1, 2; 4 with
+ * FP32 storage), TX grid columns per workgroup (4 or 8) and LY rows marched
+ * per workgroup.  The tile fixes the order of the velocity sums, so results
+ * are bit-identical only between runs with the same tile.  2D only. */
+ibdvm_status ibdvm_set_tile(ibdvm_ctx *ctx, int32_t V, int32_t TX, int32_t LY);
+ibdvm_status ibdvm_get_tile(const ibdvm_ctx *ctx, int32_t out[3]);
+
+/* Autotuner: times reps launches of the update kernel for every supported
+ * tile on the current state (without advancing it), keeps the fastest and
+ * returns it in out (may be NULL).  Synchronises.  2D only. */
+ibdvm_status ibdvm_autotune(ibdvm_ctx *ctx, int32_t reps, int32_t out[3]);
+
+/* Kernel timing with HIP events (tracing aid).  While enabled, every
+ * update launch and every ghost-fill / moment-finish launch of this context
+ * is bracketed by a pair of events on the context stream.
+ * ibdvm_profile_read synchronises, returns the summed durations in
+ * milliseconds (ms[0] update kernel, ms[1] ghost-fill kernel) and launch
+ * counts, and clears the record.  Disabling also clears it. */
+ibdvm_status ibdvm_profile(ibdvm_ctx *ctx, int32_t enable);
+ibdvm_status ibdvm_profile_read(ibdvm_ctx *ctx, double ms[2], int64_t counts[2]);
+
+/* Thread-local message describing the last failure on this thread. */
+const char *ibdvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,72 @@
+// device.hpp -- layout of the tables the HIP kernels read (library-internal).
+#pragma once
+#include <cstdint>
+
+namespace ibdvm {
+
+// per-cell flags: solid; any stencil neighbour (+-1, +-2 along an axis) solid
+// or outside the grid; and one bit per face neighbour that is solid
+// (x-, x+, y-, y+, z-, z+)
+enum CellFlag : uint8_t { CF_SOLID = 1, CF_NEAR = 2, CF_XM = 4, CF_XP = 8, CF_YM = 16, CF_YP = 32, CF_ZM = 64, CF_ZP = 128 };
+
+// per-(cell, velocity chunk) partial moments of the new state, relative to
+// the reference velocity U of the old state: m0, m1[D], m2, m3[D], M2[D(D+1)/2]
+constexpr int kPartialWords2 = 9;
+constexpr int kPartialWords3 = 14;
+constexpr int kPartialStride = 16;
+// per-cell parameter words: U[3], A, 1/T, s[3], T/2, 1/tau, rho, T, q[3], tau
+constexpr int kCellWords = 16;
+enum CellWord { CW_U = 0, CW_A = 3, CW_INVT = 4, CW_S = 5, CW_TH = 8, CW_INVTAU = 9, CW_RHO = 10, CW_T = 11, CW_Q = 12, CW_TAU = 15 };
+
+constexpr int kChunk = 64;  // velocity nodes per wavefront
+constexpr int kMaxVn = 128;
+
+struct DPair {
+    int gc, dc, ac, axis, sign, ns;
+    int sc[26];
+    int snb[26][3][2];
+    double ygc, ydc, yac, yw, ysp, yface;
+    double den;  // sum over reflected measure of omega^s xi_n Hw
+    double dS;   // face area
+    double nw[3];
+    double r[26][3];
+    double rh[26][3];
+};
+
+struct Ctrl {
+    unsigned long long tau_bits[2];
+    double dt;
+    double time;
+    long long step;
+    unsigned int health;
+    unsigned int pad;
+};
+
+struct Dev {
+    int D, NA, NV, nchunk, Nc, npairs, outer;
+    unsigned flags;
+    int n[3], vn[3];
+    int stride[3], pad1;
+    double dx[3], inv_dx[3];
+    double adv, cfl, mu0, omega, Pr, Tw, alpha, shk;  // shk = 4(1-Pr)/5
+    double Aw;                                         // wall Maxwellian prefactor (pi T_w)^(-D/2)
+    const double *xi[3];
+    const double *xa;  // per-axis nodes [3][kMaxVn]
+    const double *w;
+    const double *fs[2];
+    const double *hw;
+    void *f[2][2];  // [buffer][array]
+    double *cellp;
+    double *part;
+    const uint8_t *cflag;
+    const int *pnb;
+    const DPair *pairs;
+    const uint8_t *cls;
+    const double *wg;
+    double *ghost[2], *face[2], *fiw[2], *fsp[2];
+    double *rhow;
+    double *pforce;
+    Ctrl *ctrl;
+};
+
+}  // namespace ibdvm

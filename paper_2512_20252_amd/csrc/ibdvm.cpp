@@ -1,0 +1,874 @@
+// ibdvm.cpp -- C ABI of the immersed-boundary Shakhov-DVM library: context,
+// workspace layout inside the caller's device buffer, table upload and the
+// per-step launch sequence.  Declarations and argument conventions are in
+// include/ibdvm.h.
+#include "ibdvm.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "geometry.hpp"
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+ibdvm_status fail(ibdvm_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct Layout {
+    size_t f[2][2], cellp, part, xi, xa, w, fs, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
+    size_t total;
+    size_t state_bytes;  // one array of one buffer
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + std::max<size_t>(bytes, 1));
+        return o;
+    };
+    const size_t es = precision == IBDVM_F32_STORE ? 4 : 8;
+    const size_t nf = (size_t)g.Nc * g.NV;
+    const size_t np = g.pairs.size();
+    const int nchunk = (g.NV + ibdvm::kChunk - 1) / ibdvm::kChunk;
+    L.state_bytes = nf * es;
+    for (int b = 0; b < 2; ++b)
+        for (int A = 0; A < 2; ++A) L.f[b][A] = A < NA ? take(nf * es) : 0;
+    L.cellp = take((size_t)g.Nc * ibdvm::kCellWords * 8);
+    L.part = take((size_t)g.Nc * nchunk * ibdvm::kPartialStride * 8);
+    L.xi = take((size_t)3 * g.NV * 8);
+    L.xa = take((size_t)3 * ibdvm::kMaxVn * 8);
+    L.w = take((size_t)g.NV * 8);
+    L.fs = take((size_t)2 * g.NV * 8);
+    L.hw = take((size_t)g.NV * 8);
+    L.cflag = take((size_t)g.Nc);
+    L.pnb = take((size_t)g.Nc * 6 * 4);
+    L.pairs = take(np * sizeof(ibdvm::DPair));
+    L.cls = take(np * g.NV);
+    L.wg = take(np * g.NV * 8);
+    L.ghost = take((size_t)NA * np * g.NV * 8);
+    L.face = take((size_t)NA * np * g.NV * 8);
+    L.fiw = take((size_t)NA * np * g.NV * 8);
+    L.fsp = take((size_t)NA * np * g.NV * 8);
+    L.rhow = take(np * 8);
+    L.pforce = take(np * 4 * 8);
+    L.ctrl = take(sizeof(ibdvm::Ctrl));
+    L.total = off;
+    return L;
+}
+
+ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm_geometry *geom, const ibdvm_opts *opts,
+                      ibdvm::Problem &p)
+{
+    if (!grid || !vg || !geom || !opts) return fail(IBDVM_E_INVALID_ARG, "null argument");
+    if (grid->dim != 2 && grid->dim != 3) return fail(IBDVM_E_INVALID_ARG, "dim must be 2 or 3");
+    p = ibdvm::Problem{};
+    p.dim = grid->dim;
+    for (int a = 0; a < 3; ++a) {
+        bool used = a < grid->dim;
+        p.n[a] = used ? grid->n[a] : 1;
+        p.lo[a] = used ? grid->lo[a] : 0.0;
+        p.hi[a] = used ? grid->hi[a] : 1.0;
+        p.vn[a] = used ? vg->n[a] : 1;
+        p.vlo[a] = used ? vg->lo[a] : 0.0;
+        p.vhi[a] = used ? vg->hi[a] : 0.0;
+        p.gcen[a] = geom->center[a];
+        p.gsize[a] = geom->size[a];
+        if (!used) continue;
+        if (grid->n[a] < 4) return fail(IBDVM_E_INVALID_ARG, "grid needs at least 4 cells per axis");
+        if (!(grid->hi[a] > grid->lo[a])) return fail(IBDVM_E_INVALID_ARG, "grid box is empty");
+        if (vg->n[a] < 2 || vg->n[a] > ibdvm::kMaxVn) return fail(IBDVM_E_INVALID_ARG, "velocity nodes per axis must be in [2, 128]");
+        if (!(vg->hi[a] > 0.0) || vg->lo[a] != -vg->hi[a])
+            return fail(IBDVM_E_INVALID_ARG, "velocity box must be symmetric about 0");
+    }
+    if (grid->outer_bc != IBDVM_OUTER_FREESTREAM && grid->outer_bc != IBDVM_OUTER_PERIODIC)
+        return fail(IBDVM_E_INVALID_ARG, "unknown outer boundary condition");
+    p.outer = grid->outer_bc;
+    if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID) return fail(IBDVM_E_INVALID_ARG, "unknown quadrature rule");
+    p.rule = vg->rule;
+    int k = geom->kind;
+    bool ok2 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_CIRCLE || k == IBDVM_GEOM_ELLIPSE || k == IBDVM_GEOM_AIRFOIL;
+    bool ok3 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_SPHERE;
+    if ((grid->dim == 2 && !ok2) || (grid->dim == 3 && !ok3)) return fail(IBDVM_E_INVALID_ARG, "geometry kind does not match dim");
+    if (k != IBDVM_GEOM_NONE && !(geom->size[0] > 0.0)) return fail(IBDVM_E_INVALID_ARG, "geometry size must be positive");
+    if ((k == IBDVM_GEOM_ELLIPSE || k == IBDVM_GEOM_AIRFOIL) && !(geom->size[1] > 0.0))
+        return fail(IBDVM_E_INVALID_ARG, "geometry size[1] must be positive");
+    p.gkind = k;
+    p.aoa = geom->aoa_rad;
+    p.flags = opts->flags;
+    if (opts->precision != IBDVM_F64 && opts->precision != IBDVM_F32_STORE) return fail(IBDVM_E_INVALID_ARG, "unknown precision");
+    if (!(opts->cfl > 0.0 && opts->cfl <= 1.0)) return fail(IBDVM_E_INVALID_ARG, "cfl must be in (0, 1]");
+    if (!(opts->omega_vhs > 0.0 && opts->omega_vhs < 2.5) || !(opts->a_vhs > 0.0))
+        return fail(IBDVM_E_INVALID_ARG, "viscosity law parameters out of range");
+    return IBDVM_OK;
+}
+
+#define HIP_CHECK(expr)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return fail(IBDVM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct ibdvm_ctx {
+    ibdvm::Problem prob;
+    ibdvm::Geometry geo;
+    double Kn = 0, Ma = 0, Pr = 0, gam = 0, alpha = 1, Tw = 1, cfl = 0.5, omega = 0.81, avhs = 1.0;
+    int precision = 0;
+    int NA = 2;
+    bool host_only = false;
+    bool broken = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    Layout L{};
+    ibdvm::Dev dev{};
+    int cur = 0;
+    long long step = 0;
+    bool pending = false;
+    double Uinf = 0, mu0 = 0, Lref = 1;
+    ibdvm::Tile tile{1, 8, 64};
+    bool profiling = false;
+    std::vector<hipEvent_t> ev[2];  // start/stop pairs per kernel kind
+    ~ibdvm_ctx()
+    {
+        for (auto &v : ev)
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+ibdvm_status sync_and_check(ibdvm_ctx *c)
+{
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    unsigned health = 0;
+    HIP_CHECK(hipMemcpy(&health, c->ws + c->L.ctrl + offsetof(ibdvm::Ctrl, health), sizeof(health), hipMemcpyDeviceToHost));
+    if (health) {
+        c->broken = true;
+        return fail(IBDVM_E_UNSTABLE, "non-physical state (NaN, rho <= 0 or T <= 0)");
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status require_device(const ibdvm_ctx *c)
+{
+    if (!c) return fail(IBDVM_E_INVALID_ARG, "null context");
+    if (c->host_only) return fail(IBDVM_E_STATE, "host-only context has no device state");
+    if (c->broken) return fail(IBDVM_E_STATE, "context became unstable; destroy it");
+    return IBDVM_OK;
+}
+
+// moments of the current state by direct summation, tau_min into its slot
+ibdvm_status refresh_moments(ibdvm_ctx *c)
+{
+    HIP_CHECK(ibdvm::launch_moments_direct(c->dev, c->precision, c->cur, (int)(c->step & 1), c->stream));
+    c->pending = false;
+    return IBDVM_OK;
+}
+
+ibdvm_status reset_clock(ibdvm_ctx *c)
+{
+    ibdvm::Ctrl ctrl{};
+    ctrl.tau_bits[0] = ctrl.tau_bits[1] = 0x7ff0000000000000ull;
+    HIP_CHECK(hipMemcpyAsync(c->ws + c->L.ctrl, &ctrl, sizeof(ctrl), hipMemcpyHostToDevice, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->step = 0;
+    c->cur = 0;
+    return IBDVM_OK;
+}
+
+// moves host arrays [cells][nodes] into buffer `cur` in chunks staged through
+// the other buffer (free while the state is being replaced)
+ibdvm_status upload_state(ibdvm_ctx *c, const double *src[2], const double *noise[2], double amp)
+{
+    const long long NV = c->geo.NV, Nc = c->geo.Nc;
+    const int other = c->cur ^ 1;
+    char *stage = c->ws + c->L.f[other][0];
+    size_t stage_bytes = c->L.state_bytes * c->NA;
+    long long chunk_cells = std::max<long long>(1, (long long)(stage_bytes / (NV * 8)));
+    for (int A = 0; A < c->NA; ++A) {
+        for (long long c0 = 0; c0 < Nc; c0 += chunk_cells) {
+            long long nc = std::min(chunk_cells, Nc - c0);
+            long long n = nc * NV, off = c0 * NV;
+            const double *h = src ? src[A] : noise[A];
+            if (h) {
+                HIP_CHECK(hipMemcpyAsync(stage, h + off, n * 8, hipMemcpyHostToDevice, c->stream));
+            }
+            if (src)
+                HIP_CHECK(ibdvm::launch_state_set(c->dev, c->precision, c->cur, A, (const double *)stage, off, n, c->stream));
+            else
+                HIP_CHECK(ibdvm::launch_state_freestream(c->dev, c->precision, c->cur, A, h ? (const double *)stage : nullptr,
+                                                          amp, off, n, c->stream));
+            HIP_CHECK(hipStreamSynchronize(c->stream));
+        }
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status mark(ibdvm_ctx *c, int kind)
+{
+    if (!c->profiling) return IBDVM_OK;
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    HIP_CHECK(hipEventRecord(e, c->stream));
+    c->ev[kind].push_back(e);
+    return IBDVM_OK;
+}
+
+ibdvm_status one_step(ibdvm_ctx *c)
+{
+    const int slot = (int)(c->step & 1);
+    ibdvm_status st;
+    if ((st = mark(c, 1))) return st;
+    HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, true, c->pending, c->stream));
+    if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
+    if (c->prob.dim == 2)
+        HIP_CHECK(ibdvm::launch_update2d(c->dev, c->precision, c->cur, slot, c->tile, c->stream));
+    else
+        HIP_CHECK(ibdvm::launch_update(c->dev, c->precision, c->cur, slot, c->stream));
+    if ((st = mark(c, 0))) return st;
+    c->cur ^= 1;
+    c->step += 1;
+    c->pending = true;
+    return IBDVM_OK;
+}
+
+ibdvm_status finish_pending(ibdvm_ctx *c)
+{
+    if (!c->pending) return IBDVM_OK;
+    HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), false, true, c->stream));
+    c->pending = false;
+    return IBDVM_OK;
+}
+
+ibdvm_status build(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm_geometry *geom, const ibdvm_opts *opts,
+                   ibdvm_ctx &c)
+{
+    ibdvm_status st = validate(grid, vg, geom, opts, c.prob);
+    if (st) return st;
+    std::string err;
+    int code = ibdvm::build_geometry(c.prob, c.geo, err);
+    if (code) return fail((ibdvm_status)code, err);
+    c.NA = c.prob.dim == 2 ? 2 : 1;
+    c.precision = opts->precision;
+    c.L = make_layout(c.geo, c.NA, c.precision);
+    return IBDVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ibdvm_last_error(void) { return g_err.c_str(); }
+
+ibdvm_status ibdvm_footprint(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, const ibdvm_geometry *geom,
+                             const ibdvm_opts *opts, size_t *bytes)
+{
+    if (!bytes) return fail(IBDVM_E_INVALID_ARG, "null output");
+    ibdvm_ctx c;
+    ibdvm_status st = build(grid, vgrid, geom, opts, c);
+    if (st) return st;
+    *bytes = c.L.total;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, const ibdvm_geometry *geom, double Kn,
+                          double Ma, double Pr, double gamma, double alpha, double T_w, const ibdvm_opts *opts,
+                          ibdvm_ctx **out)
+{
+    if (!out) return fail(IBDVM_E_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (!(Kn > 0.0) || !(Ma >= 0.0) || !(Pr > 0.0) || !(gamma > 1.0) || !(alpha >= 0.0 && alpha <= 1.0) || !(T_w > 0.0))
+        return fail(IBDVM_E_INVALID_ARG, "physical parameter out of range");
+    ibdvm_ctx *c = new ibdvm_ctx();
+    ibdvm_status st = build(grid, vgrid, geom, opts, *c);
+    if (st) {
+        delete c;
+        return st;
+    }
+    c->Kn = Kn;
+    c->Ma = Ma;
+    c->Pr = Pr;
+    c->gam = gamma;
+    c->alpha = alpha;
+    c->Tw = T_w;
+    c->cfl = opts->cfl;
+    c->omega = opts->omega_vhs;
+    c->avhs = opts->a_vhs;
+    c->host_only = (opts->flags & IBDVM_FLAG_HOST_ONLY) != 0;
+    const double al = c->avhs, om = c->omega;
+    c->mu0 = 5.0 * (al + 1.0) * (al + 2.0) * std::sqrt(kPi) / (4.0 * al * (5.0 - 2.0 * om) * (7.0 - 2.0 * om)) * Kn;
+    c->Uinf = Ma * std::sqrt(gamma / 2.0);
+    switch (c->prob.gkind) {
+    case IBDVM_GEOM_CIRCLE:
+    case IBDVM_GEOM_ELLIPSE:
+        c->Lref = 2.0 * c->prob.gsize[0];
+        break;
+    case IBDVM_GEOM_AIRFOIL:
+        c->Lref = c->prob.gsize[0];
+        break;
+    case IBDVM_GEOM_SPHERE:
+        c->Lref = kPi * c->prob.gsize[0] * c->prob.gsize[0];
+        break;
+    default:
+        c->Lref = 1.0;
+    }
+    if (c->host_only) {
+        *out = c;
+        return IBDVM_OK;
+    }
+    if (!opts->workspace) {
+        delete c;
+        return fail(IBDVM_E_INVALID_ARG, "workspace is NULL");
+    }
+    if (((uintptr_t)opts->workspace & 255u) != 0) {
+        delete c;
+        return fail(IBDVM_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    if (opts->workspace_bytes < c->L.total) {
+        size_t need = c->L.total;
+        delete c;
+        return fail(IBDVM_E_NO_MEMORY, "workspace smaller than footprint (" + std::to_string(need) + " bytes)");
+    }
+    c->ws = (char *)opts->workspace;
+    c->stream = (hipStream_t)opts->stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(IBDVM_E_DEVICE, "no HIP device");
+    }
+
+    // host tables
+    const ibdvm::Geometry &g = c->geo;
+    const int D = c->prob.dim, NV = g.NV;
+    const size_t np = g.pairs.size();
+    std::vector<double> xi((size_t)3 * NV, 0.0), xa((size_t)3 * ibdvm::kMaxVn, 0.0), fs((size_t)2 * NV, 0.0), hw(NV);
+    double adv = 0.0;
+    for (int a = 0; a < D; ++a) {
+        double mx = 0.0;
+        for (int i = 0; i < c->prob.vn[a]; ++i) {
+            xa[(size_t)a * ibdvm::kMaxVn + i] = g.xa[a][i];
+            mx = std::max(mx, std::fabs(g.xa[a][i]));
+        }
+        adv += mx / g.dx[a];
+    }
+    const double Aw = D == 2 ? 1.0 / (kPi * T_w) : std::pow(kPi * T_w, -1.5);
+    const double Af = D == 2 ? 1.0 / kPi : std::pow(kPi, -1.5);
+    for (int k = 0; k < NV; ++k) {
+        double x2 = 0.0, c2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            double x = g.xi[3 * k + a];
+            xi[(size_t)a * NV + k] = x;
+            x2 += x * x;
+            double cc = x - (a == 0 ? c->Uinf : 0.0);
+            c2 += cc * cc;
+        }
+        hw[k] = Aw * std::exp(-x2 / T_w);
+        fs[k] = Af * std::exp(-c2);
+        fs[(size_t)NV + k] = 0.5 * fs[k];
+    }
+    std::vector<ibdvm::DPair> dp(np);
+    for (size_t ip = 0; ip < np; ++ip) {
+        const ibdvm::PairGeom &p = g.pairs[ip];
+        ibdvm::DPair &q = dp[ip];
+        std::memset(&q, 0, sizeof(q));
+        q.gc = p.gc;
+        q.dc = p.dc;
+        q.ac = p.ac;
+        q.axis = p.axis;
+        q.sign = p.sign;
+        q.ns = p.ns;
+        const int a = p.axis;
+        int ig = p.gc, ia[3];
+        ia[0] = ig % c->prob.n[0];
+        ia[1] = (ig / c->prob.n[0]) % c->prob.n[1];
+        ia[2] = D == 3 ? ig / (c->prob.n[0] * c->prob.n[1]) : 0;
+        auto centre = [&](int i) { return c->prob.lo[a] + ((double)i + 0.5) * g.dx[a]; };
+        q.ygc = centre(ia[a]);
+        q.ydc = centre(ia[a] + p.sign);
+        q.yac = p.ac >= 0 ? centre(ia[a] + 2 * p.sign) : 0.0;
+        q.yw = p.xw[a];
+        q.ysp = p.xsp[a];
+        q.yface = q.ygc + 0.5 * p.sign * g.dx[a];
+        q.dS = 1.0;
+        for (int b = 0; b < D; ++b)
+            if (b != a) q.dS *= g.dx[b];
+        for (int b = 0; b < 3; ++b) q.nw[b] = p.nw[b];
+        for (int j = 0; j < p.ns; ++j) {
+            q.sc[j] = p.sc[j];
+            for (int b = 0; b < 3; ++b) {
+                q.r[j][b] = p.r[j][b];
+                q.rh[j][b] = p.rh[j][b];
+                q.snb[j][b][0] = p.snb[j][b][0];
+                q.snb[j][b][1] = p.snb[j][b][1];
+            }
+        }
+        double den = 0.0;
+        for (int k = 0; k < NV; ++k) {
+            uint8_t cl = g.cls[ip * NV + k];
+            double ws = cl == ibdvm::VC_SOLID ? g.w[k] : (cl >= 2 ? g.w[k] - g.wg[ip * NV + k] : 0.0);
+            double dn = 0.0;
+            for (int b = 0; b < D; ++b) dn += g.xi[3 * k + b] * p.nw[b];
+            den += ws * dn * hw[k];
+        }
+        q.den = den;
+    }
+
+    // device view
+    ibdvm::Dev &d = c->dev;
+    std::memset(&d, 0, sizeof(d));
+    d.D = D;
+    d.NA = c->NA;
+    d.NV = NV;
+    c->tile = c->precision == IBDVM_F32_STORE ? ibdvm::Tile{2, 8, 64} : ibdvm::Tile{1, 8, 64};
+    d.nchunk = D == 2 ? (NV + 64 * c->tile.V - 1) / (64 * c->tile.V) : (NV + ibdvm::kChunk - 1) / ibdvm::kChunk;
+    d.Nc = g.Nc;
+    d.npairs = (int)np;
+    d.outer = c->prob.outer;
+    d.flags = c->prob.flags;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = c->prob.n[a];
+        d.vn[a] = c->prob.vn[a];
+        d.dx[a] = g.dx[a];
+        d.inv_dx[a] = 1.0 / g.dx[a];
+    }
+    d.stride[0] = 1;
+    d.stride[1] = c->prob.n[0];
+    d.stride[2] = c->prob.n[0] * c->prob.n[1];
+    d.adv = adv;
+    d.cfl = c->cfl;
+    d.mu0 = c->mu0;
+    d.omega = c->omega;
+    d.Pr = Pr;
+    d.Tw = T_w;
+    d.alpha = alpha;
+    d.shk = 4.0 * (1.0 - Pr) / 5.0;
+    d.Aw = Aw;
+    char *ws = c->ws;
+    const Layout &L = c->L;
+    for (int a = 0; a < 3; ++a) d.xi[a] = (const double *)(ws + L.xi) + (size_t)a * NV;
+    d.xa = (const double *)(ws + L.xa);
+    d.w = (const double *)(ws + L.w);
+    d.fs[0] = (const double *)(ws + L.fs);
+    d.fs[1] = (const double *)(ws + L.fs) + NV;
+    d.hw = (const double *)(ws + L.hw);
+    for (int b = 0; b < 2; ++b)
+        for (int A = 0; A < 2; ++A) d.f[b][A] = A < c->NA ? (void *)(ws + L.f[b][A]) : nullptr;
+    d.cellp = (double *)(ws + L.cellp);
+    d.part = (double *)(ws + L.part);
+    d.cflag = (const uint8_t *)(ws + L.cflag);
+    d.pnb = (const int *)(ws + L.pnb);
+    d.pairs = (const ibdvm::DPair *)(ws + L.pairs);
+    d.cls = (const uint8_t *)(ws + L.cls);
+    d.wg = (const double *)(ws + L.wg);
+    const size_t pstride = np * NV;
+    for (int A = 0; A < 2; ++A) {
+        int AA = A < c->NA ? A : 0;
+        d.ghost[A] = (double *)(ws + L.ghost) + AA * pstride;
+        d.face[A] = (double *)(ws + L.face) + AA * pstride;
+        d.fiw[A] = (double *)(ws + L.fiw) + AA * pstride;
+        d.fsp[A] = (double *)(ws + L.fsp) + AA * pstride;
+    }
+    d.rhow = (double *)(ws + L.rhow);
+    d.pforce = (double *)(ws + L.pforce);
+    d.ctrl = (ibdvm::Ctrl *)(ws + L.ctrl);
+
+    auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        if (!bytes) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up(L.xi, xi.data(), xi.size() * 8);
+    if (e == hipSuccess) e = up(L.xa, xa.data(), xa.size() * 8);
+    if (e == hipSuccess) e = up(L.w, g.w.data(), g.w.size() * 8);
+    if (e == hipSuccess) e = up(L.fs, fs.data(), fs.size() * 8);
+    if (e == hipSuccess) e = up(L.hw, hw.data(), hw.size() * 8);
+    if (e == hipSuccess) e = up(L.cflag, g.cflag.data(), g.cflag.size());
+    if (e == hipSuccess) e = up(L.pnb, g.pnb.data(), g.pnb.size() * 4);
+    if (e == hipSuccess) e = up(L.pairs, dp.data(), dp.size() * sizeof(ibdvm::DPair));
+    if (e == hipSuccess) e = up(L.cls, g.cls.data(), g.cls.size());
+    if (e == hipSuccess) e = up(L.wg, g.wg.data(), g.wg.size() * 8);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(IBDVM_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
+    }
+    st = reset_clock(c);
+    const double *no_noise[2] = {nullptr, nullptr};
+    if (!st) st = upload_state(c, nullptr, no_noise, 0.0);
+    if (!st) st = refresh_moments(c);
+    if (!st) st = sync_and_check(c);
+    if (st) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return IBDVM_OK;
+}
+
+void ibdvm_destroy(ibdvm_ctx *ctx) { delete ctx; }
+
+ibdvm_status ibdvm_info(const ibdvm_ctx *c, int64_t out[7])
+{
+    if (!c || !out) return fail(IBDVM_E_INVALID_ARG, "null argument");
+    out[0] = c->prob.dim;
+    out[1] = c->geo.Nc;
+    out[2] = c->geo.NV;
+    out[3] = c->NA;
+    out[4] = (int64_t)c->geo.pairs.size();
+    out[5] = c->geo.nfluid;
+    out[6] = c->geo.nghost;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_init_freestream(ibdvm_ctx *c, const double *u0, const double *u1, double amp)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = reset_clock(c))) return st;
+    const double *noise[2] = {u0, c->NA == 2 ? u1 : nullptr};
+    if ((st = upload_state(c, nullptr, noise, amp))) return st;
+    if ((st = refresh_moments(c))) return st;
+    return sync_and_check(c);
+}
+
+ibdvm_status ibdvm_set_state(ibdvm_ctx *c, const double *f0, const double *f1)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!f0 || (c->NA == 2 && !f1)) return fail(IBDVM_E_INVALID_ARG, "null state array");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = reset_clock(c))) return st;
+    const double *src[2] = {f0, f1};
+    if ((st = upload_state(c, src, nullptr, 0.0))) return st;
+    if ((st = refresh_moments(c))) return st;
+    return sync_and_check(c);
+}
+
+ibdvm_status ibdvm_get_state(ibdvm_ctx *c, double *f0, double *f1)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!f0 || (c->NA == 2 && !f1)) return fail(IBDVM_E_INVALID_ARG, "null state array");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    // stage through the free state buffer
+    const long long NV = c->geo.NV, Nc = c->geo.Nc;
+    char *stage = c->ws + c->L.f[c->cur ^ 1][0];
+    size_t stage_bytes = c->L.state_bytes * c->NA;
+    long long chunk_cells = std::max<long long>(1, (long long)(stage_bytes / (NV * 8)));
+    double *dst[2] = {f0, f1};
+    for (int A = 0; A < c->NA; ++A)
+        for (long long c0 = 0; c0 < Nc; c0 += chunk_cells) {
+            long long nc = std::min(chunk_cells, Nc - c0);
+            HIP_CHECK(ibdvm::launch_state_get(c->dev, c->precision, c->cur, A, (double *)stage, c0 * NV, nc * NV, c->stream));
+            HIP_CHECK(hipMemcpyAsync(dst[A] + c0 * NV, stage, nc * NV * 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_CHECK(hipStreamSynchronize(c->stream));
+        }
+    return sync_and_check(c);
+}
+
+ibdvm_status ibdvm_step(ibdvm_ctx *c, int32_t nsteps)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (nsteps < 0) return fail(IBDVM_E_INVALID_ARG, "negative step count");
+    HIP_CHECK(hipSetDevice(c->device));
+    for (int32_t i = 0; i < nsteps; ++i)
+        if ((st = one_step(c))) return st;
+    return finish_pending(c);
+}
+
+ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps)
+{
+    if (!ctxs || n < 0 || nsteps < 0) return fail(IBDVM_E_INVALID_ARG, "bad batch arguments");
+    for (int32_t i = 0; i < n; ++i) {
+        ibdvm_status st = require_device(ctxs[i]);
+        if (st) return st;
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
+            return fail(IBDVM_E_INVALID_ARG, "batched contexts must share one stream and device");
+    }
+    if (n == 0) return IBDVM_OK;
+    HIP_CHECK(hipSetDevice(ctxs[0]->device));
+    for (int32_t s = 0; s < nsteps; ++s)
+        for (int32_t i = 0; i < n; ++i) {
+            ibdvm_status st = one_step(ctxs[i]);
+            if (st) return st;
+        }
+    for (int32_t i = 0; i < n; ++i) {
+        ibdvm_status st = finish_pending(ctxs[i]);
+        if (st) return st;
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_moments(ibdvm_ctx *c, double *out, int32_t out_is_device)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!out) return fail(IBDVM_E_INVALID_ARG, "null output");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    if (out_is_device) {
+        HIP_CHECK(ibdvm::launch_moments_out(c->dev, out, c->stream));
+        return IBDVM_OK;
+    }
+    double *stage = c->dev.part;  // holds no pending data once moments are final
+    HIP_CHECK(ibdvm::launch_moments_out(c->dev, stage, c->stream));
+    HIP_CHECK(hipMemcpyAsync(out, stage, (size_t)c->geo.Nc * 8 * 8, hipMemcpyDeviceToHost, c->stream));
+    return sync_and_check(c);
+}
+
+ibdvm_status ibdvm_clock(ibdvm_ctx *c, double *dt, double *time, int64_t *step)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = sync_and_check(c))) return st;
+    ibdvm::Ctrl ctrl;
+    HIP_CHECK(hipMemcpy(&ctrl, c->ws + c->L.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost));
+    if (dt) *dt = ctrl.dt;
+    if (time) *time = ctrl.time;
+    if (step) *step = ctrl.step;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_wall_state(ibdvm_ctx *c, double *ghost, double *face, double *rho_w)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), true, false, c->stream));
+    const size_t np = c->geo.pairs.size(), n = np * c->geo.NV;
+    if (np) {
+        for (int A = 0; A < c->NA; ++A) {
+            if (ghost) HIP_CHECK(hipMemcpyAsync(ghost + A * n, c->dev.ghost[A], n * 8, hipMemcpyDeviceToHost, c->stream));
+            if (face) HIP_CHECK(hipMemcpyAsync(face + A * n, c->dev.face[A], n * 8, hipMemcpyDeviceToHost, c->stream));
+        }
+        if (rho_w) HIP_CHECK(hipMemcpyAsync(rho_w, c->dev.rhow, np * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    return sync_and_check(c);
+}
+
+ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, double *C_L, ibdvm_wall_point *pts,
+                                  int32_t cap, int32_t *n_pts)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    const size_t np = c->geo.pairs.size();
+    HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), true, false, c->stream));
+    HIP_CHECK(ibdvm::launch_force(c->dev, c->precision, c->cur, c->stream));
+    std::vector<double> pf(np * 4), rw(np);
+    if (np) {
+        HIP_CHECK(hipMemcpyAsync(pf.data(), c->dev.pforce, np * 4 * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_CHECK(hipMemcpyAsync(rw.data(), c->dev.rhow, np * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    if ((st = sync_and_check(c))) return st;
+    double F[3] = {0, 0, 0};
+    for (size_t p = 0; p < np; ++p)
+        for (int b = 0; b < 3; ++b) F[b] += pf[4 * p + b];
+    if (force)
+        for (int b = 0; b < 3; ++b) force[b] = F[b];
+    double qd = 0.5 * c->Uinf * c->Uinf * c->Lref;
+    if (C_D) *C_D = qd > 0 ? F[0] / qd : NAN;
+    if (C_L) *C_L = qd > 0 ? F[1] / qd : NAN;
+    int32_t m = 0;
+    if (pts)
+        for (size_t p = 0; p < np && m < cap; ++p, ++m) {
+            const ibdvm::PairGeom &g = c->geo.pairs[p];
+            for (int b = 0; b < 3; ++b) {
+                pts[m].xw[b] = g.xw[b];
+                pts[m].nw[b] = g.nw[b];
+            }
+            pts[m].rho_w = rw[p];
+            pts[m].p_w = pf[4 * p + 3];
+        }
+    if (n_pts) *n_pts = pts ? m : (int32_t)np;
+    return IBDVM_OK;
+}
+
+namespace {
+bool tile_supported(int precision, const ibdvm::Tile &t)
+{
+    bool tx = t.TX == 4 || t.TX == 8;
+    bool v = t.V == 1 || t.V == 2 || (precision == IBDVM_F32_STORE && t.V == 4);
+    return tx && v && t.LY >= 1;
+}
+}  // namespace
+
+ibdvm_status ibdvm_set_tile(ibdvm_ctx *c, int32_t V, int32_t TX, int32_t LY)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (c->prob.dim != 2) return fail(IBDVM_E_UNSUPPORTED, "tile choice applies to 2D problems");
+    ibdvm::Tile t{V, TX, LY};
+    if (!tile_supported(c->precision, t)) return fail(IBDVM_E_INVALID_ARG, "unsupported tile");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    c->tile = t;
+    c->dev.nchunk = (c->geo.NV + 64 * V - 1) / (64 * V);
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_get_tile(const ibdvm_ctx *c, int32_t out[3])
+{
+    if (!c || !out) return fail(IBDVM_E_INVALID_ARG, "null argument");
+    out[0] = c->tile.V;
+    out[1] = c->tile.TX;
+    out[2] = c->tile.LY;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (c->prob.dim != 2) return fail(IBDVM_E_UNSUPPORTED, "tile choice applies to 2D problems");
+    if (reps < 1) return fail(IBDVM_E_INVALID_ARG, "reps must be positive");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    // the update kernel reads the current state and writes the other buffer
+    // and the partial moments; neither is live here, so timing it leaves the
+    // solve unchanged once the control block is restored
+    ibdvm::Ctrl saved;
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    HIP_CHECK(hipMemcpy(&saved, c->ws + c->L.ctrl, sizeof(saved), hipMemcpyDeviceToHost));
+    const int slot = (int)(c->step & 1);
+    ibdvm::Tile best = c->tile;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    const int Vs[3] = {1, 2, 4}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 128};
+    for (int V : Vs)
+        for (int TX : TXs)
+            for (int LY : LYs) {
+                ibdvm::Tile t{V, TX, LY};
+                if (!tile_supported(c->precision, t)) continue;
+                ibdvm::Dev d = c->dev;
+                d.nchunk = (c->geo.NV + 64 * V - 1) / (64 * V);
+                HIP_CHECK(ibdvm::launch_update2d(d, c->precision, c->cur, slot, t, c->stream));
+                HIP_CHECK(hipEventRecord(e0, c->stream));
+                for (int r = 0; r < reps; ++r) HIP_CHECK(ibdvm::launch_update2d(d, c->precision, c->cur, slot, t, c->stream));
+                HIP_CHECK(hipEventRecord(e1, c->stream));
+                HIP_CHECK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    HIP_CHECK(hipEventDestroy(e0));
+    HIP_CHECK(hipEventDestroy(e1));
+    HIP_CHECK(hipMemcpy(c->ws + c->L.ctrl, &saved, sizeof(saved), hipMemcpyHostToDevice));
+    c->tile = best;
+    c->dev.nchunk = (c->geo.NV + 64 * best.V - 1) / (64 * best.V);
+    if (out) {
+        out[0] = best.V;
+        out[1] = best.TX;
+        out[2] = best.LY;
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_profile(ibdvm_ctx *c, int32_t enable)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (auto &v : c->ev) {
+        for (hipEvent_t e : v) HIP_CHECK(hipEventDestroy(e));
+        v.clear();
+    }
+    c->profiling = enable != 0;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_profile_read(ibdvm_ctx *c, double ms[2], int64_t counts[2])
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!ms || !counts) return fail(IBDVM_E_INVALID_ARG, "null output");
+    HIP_CHECK(hipSetDevice(c->device));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (int kind = 0; kind < 2; ++kind) {
+        std::vector<hipEvent_t> &v = c->ev[kind];
+        double total = 0.0;
+        for (size_t i = 0; i + 1 < v.size(); i += 2) {
+            float t = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&t, v[i], v[i + 1]));
+            total += t;
+        }
+        ms[kind] = total;
+        counts[kind] = (int64_t)(v.size() / 2);
+        for (hipEvent_t e : v) HIP_CHECK(hipEventDestroy(e));
+        v.clear();
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_index_sets(const ibdvm_ctx *c, uint8_t *solid, int32_t *pairs, uint8_t *cls)
+{
+    if (!c) return fail(IBDVM_E_INVALID_ARG, "null context");
+    const ibdvm::Geometry &g = c->geo;
+    if (solid)
+        for (int i = 0; i < g.Nc; ++i) solid[i] = g.cflag[i] & ibdvm::CF_SOLID;
+    for (size_t p = 0; p < g.pairs.size(); ++p) {
+        const ibdvm::PairGeom &q = g.pairs[p];
+        if (pairs) {
+            int32_t *o = pairs + 32 * p;
+            o[0] = q.gc;
+            o[1] = q.dc;
+            o[2] = q.ac;
+            o[3] = q.axis;
+            o[4] = q.sign;
+            o[5] = q.ns;
+            for (int j = 0; j < 26; ++j) o[6 + j] = j < q.ns ? q.sc[j] : -1;
+        }
+    }
+    if (cls && !g.cls.empty()) std::memcpy(cls, g.cls.data(), g.cls.size());
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_pair_geometry(const ibdvm_ctx *c, double *g9, double *wg)
+{
+    if (!c) return fail(IBDVM_E_INVALID_ARG, "null context");
+    const ibdvm::Geometry &g = c->geo;
+    for (size_t p = 0; p < g.pairs.size(); ++p) {
+        if (!g9) break;
+        for (int b = 0; b < 3; ++b) {
+            g9[9 * p + b] = g.pairs[p].xw[b];
+            g9[9 * p + 3 + b] = g.pairs[p].nw[b];
+            g9[9 * p + 6 + b] = g.pairs[p].xsp[b];
+        }
+    }
+    if (wg && !g.wg.empty()) std::memcpy(wg, g.wg.data(), g.wg.size() * 8);
+    return IBDVM_OK;
+}
+
+}  // extern "C"

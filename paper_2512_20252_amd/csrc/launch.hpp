@@ -1,0 +1,28 @@
+// launch.hpp -- host-side launchers of the HIP kernels (library-internal).
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "device.hpp"
+
+namespace ibdvm {
+
+// tile of the 2D marching update: V velocity nodes per lane, TX columns per
+// workgroup, LY rows per workgroup
+struct Tile {
+    int V, TX, LY;
+};
+
+hipError_t launch_update(const Dev &d, int storage, int cur, int slot, hipStream_t s);
+hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
+hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
+hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, hipStream_t s);
+hipError_t launch_force(const Dev &d, int storage, int cur, hipStream_t s);
+hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, const double *u, double amp, long long off,
+                                   long long n, hipStream_t s);
+hipError_t launch_state_set(const Dev &d, int storage, int buf, int A, const double *src, long long off, long long n,
+                            hipStream_t s);
+hipError_t launch_state_get(const Dev &d, int storage, int buf, int A, double *dst, long long off, long long n,
+                            hipStream_t s);
+hipError_t launch_moments_out(const Dev &d, double *out, hipStream_t s);
+
+}  // namespace ibdvm

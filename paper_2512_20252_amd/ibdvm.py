@@ -1,0 +1,293 @@
+"""Python binding of libibdvm.so (argument marshalling only).
+
+Every step of the solve runs in the library's HIP kernels; this module turns
+case dicts into the C structs of ``include/ibdvm.h``, allocates the device
+workspace as a torch uint8 tensor, passes the current torch stream and copies
+host arrays in and out.  It raises if the library is missing: there is no
+fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibdvm.so")
+
+OK, E_INVALID_ARG, E_GEOMETRY, E_NO_MEMORY, E_DEVICE, E_UNSTABLE, E_UNSUPPORTED, E_STATE = range(8)
+GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
+OUTER = {"freestream": 0, "periodic": 1}
+RULE = {"midpoint": 0, "trapezoid": 1}
+PRECISION = {"f64": 0, "f32": 1}
+FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "host_only": 1 << 8}
+
+c_int32, c_double, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", c_int32), ("n", c_int32 * 3), ("lo", c_double * 3), ("hi", c_double * 3),
+                ("outer_bc", c_int32)]
+
+
+class VGrid(ctypes.Structure):
+    _fields_ = [("n", c_int32 * 3), ("lo", c_double * 3), ("hi", c_double * 3), ("rule", c_int32)]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("center", c_double * 3), ("size", c_double * 3), ("aoa_rad", c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("cfl", c_double), ("omega_vhs", c_double), ("a_vhs", c_double),
+                ("flags", ctypes.c_uint32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
+                ("stream", c_void_p)]
+
+
+class WallPoint(ctypes.Structure):
+    _fields_ = [("xw", c_double * 3), ("nw", c_double * 3), ("rho_w", c_double), ("p_w", c_double)]
+
+
+class IbdvmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ibdvm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ibdvm_init_freestream",
+           "ibdvm_set_state", "ibdvm_get_state", "ibdvm_step", "ibdvm_moments", "ibdvm_surface_forces",
+           "ibdvm_clock", "ibdvm_index_sets", "ibdvm_pair_geometry", "ibdvm_wall_state", "ibdvm_batch_step",
+           "ibdvm_profile", "ibdvm_profile_read", "ibdvm_set_tile", "ibdvm_get_tile", "ibdvm_autotune",
+           "ibdvm_last_error"]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        dp = P(c_double)
+        L.ibdvm_footprint.argtypes = [P(Grid), P(VGrid), P(Geom), P(Opts), P(c_size_t)]
+        L.ibdvm_create.argtypes = [P(Grid), P(VGrid), P(Geom), c_double, c_double, c_double, c_double, c_double,
+                                   c_double, P(Opts), P(c_void_p)]
+        L.ibdvm_destroy.argtypes = [c_void_p]
+        L.ibdvm_destroy.restype = None
+        L.ibdvm_info.argtypes = [c_void_p, P(ctypes.c_int64)]
+        L.ibdvm_init_freestream.argtypes = [c_void_p, dp, dp, c_double]
+        L.ibdvm_set_state.argtypes = [c_void_p, dp, dp]
+        L.ibdvm_get_state.argtypes = [c_void_p, dp, dp]
+        L.ibdvm_step.argtypes = [c_void_p, c_int32]
+        L.ibdvm_moments.argtypes = [c_void_p, c_void_p, c_int32]
+        L.ibdvm_surface_forces.argtypes = [c_void_p, dp, dp, dp, P(WallPoint), c_int32, P(c_int32)]
+        L.ibdvm_clock.argtypes = [c_void_p, dp, dp, P(ctypes.c_int64)]
+        L.ibdvm_index_sets.argtypes = [c_void_p, P(ctypes.c_uint8), P(ctypes.c_int32), P(ctypes.c_uint8)]
+        L.ibdvm_pair_geometry.argtypes = [c_void_p, dp, dp]
+        L.ibdvm_wall_state.argtypes = [c_void_p, dp, dp, dp]
+        L.ibdvm_batch_step.argtypes = [P(c_void_p), c_int32, c_int32]
+        L.ibdvm_profile.argtypes = [c_void_p, c_int32]
+        L.ibdvm_profile_read.argtypes = [c_void_p, P(c_double), P(ctypes.c_int64)]
+        L.ibdvm_set_tile.argtypes = [c_void_p, c_int32, c_int32, c_int32]
+        L.ibdvm_get_tile.argtypes = [c_void_p, P(c_int32)]
+        L.ibdvm_autotune.argtypes = [c_void_p, c_int32, P(c_int32)]
+        L.ibdvm_last_error.argtypes = []
+        L.ibdvm_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("ibdvm_destroy", "ibdvm_last_error"):
+                getattr(L, name).restype = c_int32
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != OK:
+        raise IbdvmError(code, lib().ibdvm_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(c_double)) if a is not None else None
+
+
+def structs(case, precision="f64", flags=(), workspace=0, nbytes=0, stream=0):
+    d = case["dim"]
+    g = Grid()
+    g.dim = d
+    v = VGrid()
+    for a in range(3):
+        g.n[a] = case["n"][a] if a < d else 1
+        g.lo[a] = case["lo"][a] if a < d else 0.0
+        g.hi[a] = case["hi"][a] if a < d else 1.0
+        v.n[a] = case["vn"][a] if a < d else 1
+        v.lo[a] = case["vlo"][a] if a < d else 0.0
+        v.hi[a] = case["vhi"][a] if a < d else 0.0
+    g.outer_bc = OUTER[case.get("outer", "freestream")]
+    v.rule = RULE[case.get("rule", "midpoint")]
+    ge = Geom()
+    ge.kind = GEOMETRY[case.get("geometry", "none")]
+    cen, size = case.get("center", (0, 0, 0)), case.get("size", (0, 0, 0))
+    for a in range(3):
+        ge.center[a] = cen[a] if a < len(cen) else 0.0
+        ge.size[a] = size[a] if a < len(size) else 0.0
+    ge.aoa_rad = case.get("aoa", 0.0)
+    o = Opts()
+    o.precision = PRECISION[precision]
+    o.cfl = case.get("cfl", 0.5)
+    o.omega_vhs = case.get("omega_vhs", 0.81)
+    o.a_vhs = case.get("a_vhs", 1.0)
+    fl = 0
+    for f in tuple(case.get("flags", ())) + tuple(flags):
+        fl |= FLAGS[f]
+    o.flags = fl
+    o.workspace = workspace
+    o.workspace_bytes = nbytes
+    o.stream = stream
+    return g, v, ge, o
+
+
+def footprint(case, precision="f64"):
+    g, v, ge, o = structs(case, precision)
+    n = c_size_t(0)
+    check(lib().ibdvm_footprint(ctypes.byref(g), ctypes.byref(v), ctypes.byref(ge), ctypes.byref(o), ctypes.byref(n)))
+    return int(n.value)
+
+
+class Solver:
+    """One resident solve.  ``workspace`` may be a caller-provided device
+    tensor (uint8, >= footprint bytes); otherwise one is allocated with torch
+    on the current device.  ``host_only`` builds the geometry tables only."""
+
+    def __init__(self, case, precision="f64", host_only=False, workspace=None, stream=None):
+        self.case = dict(case)
+        self.precision = precision
+        self.host_only = host_only
+        self.workspace = None
+        ws_ptr, nbytes, sptr = 0, 0, 0
+        if not host_only:
+            import torch
+            nbytes = footprint(case, precision)
+            if workspace is None:
+                workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            self.workspace = workspace
+            ws_ptr, nbytes = workspace.data_ptr(), workspace.numel()
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            sptr = self.stream.cuda_stream
+        g, v, ge, o = structs(case, precision, ("host_only",) if host_only else (), ws_ptr, nbytes, sptr)
+        h = c_void_p(0)
+        check(lib().ibdvm_create(ctypes.byref(g), ctypes.byref(v), ctypes.byref(ge), case["Kn"], case["Ma"],
+                                 case["Pr"], case["gamma"], case["alpha"], case["Tw"], ctypes.byref(o),
+                                 ctypes.byref(h)))
+        self._h = h
+        info = (ctypes.c_int64 * 7)()
+        check(lib().ibdvm_info(self._h, info))
+        self.dim, self.Nc, self.NV, self.NA, self.npairs, self.nfluid, self.nghost = [int(x) for x in info]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibdvm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # state --------------------------------------------------------------
+    def init_freestream(self, u=None, amp=0.0):
+        u0 = np.ascontiguousarray(u[0], dtype=np.float64).reshape(-1) if u is not None else None
+        u1 = np.ascontiguousarray(u[1], dtype=np.float64).reshape(-1) if (u is not None and self.NA == 2) else None
+        check(lib().ibdvm_init_freestream(self._h, _dp(u0), _dp(u1), float(amp)))
+
+    def set_state(self, f):
+        f0 = np.ascontiguousarray(f[0], dtype=np.float64).reshape(-1)
+        f1 = np.ascontiguousarray(f[1], dtype=np.float64).reshape(-1) if self.NA == 2 else None
+        check(lib().ibdvm_set_state(self._h, _dp(f0), _dp(f1)))
+
+    def get_state(self):
+        f0 = np.empty((self.Nc, self.NV))
+        f1 = np.empty((self.Nc, self.NV)) if self.NA == 2 else None
+        check(lib().ibdvm_get_state(self._h, _dp(f0), _dp(f1)))
+        return (f0, f1) if self.NA == 2 else (f0,)
+
+    def step(self, n=1):
+        check(lib().ibdvm_step(self._h, int(n)))
+
+    # outputs ------------------------------------------------------------
+    def moments(self):
+        out = np.empty((self.Nc, 8))
+        check(lib().ibdvm_moments(self._h, out.ctypes.data, 0))
+        return out
+
+    def moments_device(self, out):
+        """Enqueue the moments into a device float64 tensor of shape (cells, 8)."""
+        check(lib().ibdvm_moments(self._h, out.data_ptr(), 1))
+
+    def clock(self):
+        dt, t, s = c_double(0), c_double(0), ctypes.c_int64(0)
+        check(lib().ibdvm_clock(self._h, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(s)))
+        return {"dt": dt.value, "time": t.value, "step": int(s.value)}
+
+    def surface_forces(self):
+        F = np.empty(3)
+        cd, cl = c_double(0), c_double(0)
+        cap = max(self.npairs, 1)
+        pts = (WallPoint * cap)()
+        n = c_int32(0)
+        check(lib().ibdvm_surface_forces(self._h, _dp(F), ctypes.byref(cd), ctypes.byref(cl), pts, cap,
+                                         ctypes.byref(n)))
+        wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] for p in pts[: n.value]]).reshape(-1, 8)
+        return F, cd.value, cl.value, wall
+
+    def wall_state(self):
+        n = max(self.npairs, 1) * self.NV
+        ghost = np.empty((self.NA, max(self.npairs, 1), self.NV))
+        face = np.empty_like(ghost)
+        rhow = np.empty(max(self.npairs, 1))
+        check(lib().ibdvm_wall_state(self._h, _dp(ghost), _dp(face), _dp(rhow)))
+        del n
+        return {"ghost": ghost[:, : self.npairs], "face": face[:, : self.npairs], "rhow": rhow[: self.npairs]}
+
+    def profile(self, enable=True):
+        check(lib().ibdvm_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        ms = (c_double * 2)()
+        cnt = (ctypes.c_int64 * 2)()
+        check(lib().ibdvm_profile_read(self._h, ms, cnt))
+        return {"update_ms": ms[0], "update_launches": int(cnt[0]), "fill_ms": ms[1], "fill_launches": int(cnt[1])}
+
+    def set_tile(self, V, TX, LY):
+        check(lib().ibdvm_set_tile(self._h, int(V), int(TX), int(LY)))
+
+    def get_tile(self):
+        out = (c_int32 * 3)()
+        check(lib().ibdvm_get_tile(self._h, out))
+        return tuple(out)
+
+    def autotune(self, reps=3):
+        out = (c_int32 * 3)()
+        check(lib().ibdvm_autotune(self._h, int(reps), out))
+        return tuple(out)
+
+    def index_sets(self):
+        solid = np.empty(self.Nc, dtype=np.uint8)
+        pint = np.empty((max(self.npairs, 1), 32), dtype=np.int32)
+        cls = np.empty((max(self.npairs, 1), self.NV), dtype=np.uint8)
+        check(lib().ibdvm_index_sets(self._h, solid.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                     pint.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     cls.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return {"solid": solid, "pairs": pint[: self.npairs], "cls": cls[: self.npairs]}
+
+    def pair_geometry(self):
+        g = np.empty((max(self.npairs, 1), 9))
+        wg = np.empty((max(self.npairs, 1), self.NV))
+        check(lib().ibdvm_pair_geometry(self._h, _dp(g), _dp(wg)))
+        return {"xw": g[: self.npairs, 0:3], "nw": g[: self.npairs, 3:6], "xsp": g[: self.npairs, 6:9],
+                "wg": wg[: self.npairs]}
+
+
+def batch_step(solvers, n):
+    arr = (c_void_p * len(solvers))(*[s.handle for s in solvers])
+    check(lib().ibdvm_batch_step(arr, len(solvers), int(n)))

@@ -1,0 +1,288 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: integer work bit-exact; FP64 fields within 1e-12 of the oracle
+relative to the field's maximum magnitude; the FP32-storage form within
+1e-5 relative L2 on the macroscopic fields and 1e-4 on C_D.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_20252_amd import cases, ibdvm
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    m = np.isfinite(b)
+    scale = np.max(np.abs(b[m])) if m.any() else 1.0
+    return float(np.max(np.abs(a[m] - b[m])) / scale) if m.any() else 0.0
+
+
+def _pair(oracle_mod, c, seed=0, amp=1e-3, precision="f64"):
+    o = oracle_mod.Oracle(c)
+    s = ibdvm.Solver(c, precision=precision)
+    u = cases.noise(c, seed) if amp else None
+    o.init_freestream(u, amp)
+    s.init_freestream(u, amp)
+    return o, s
+
+
+def _compare_state(o, s, tol=TOL64):
+    for A, (a, b) in enumerate(zip(s.get_state(), o.get_state())):
+        solid = o.index_sets()["solid"].astype(bool)
+        e = _rel(a[~solid], b[~solid])
+        assert e <= tol, (A, e)
+
+
+def _compare_moments(o, s, tol=TOL64):
+    """rho and T against their own maxima; velocity components against the
+    larger of the largest speed and the largest thermal speed sqrt(T), heat
+    flux components against the larger of the largest |q| and the largest
+    rho T^(3/2) (the heat-flux unit of the state).  Near-equilibrium U_y and q
+    are differences of O(1) velocity sums, so their own maxima would measure
+    cancellation, not the step."""
+    mg, mo = s.moments(), o.moments()
+    assert np.array_equal(np.isnan(mg[:, 0]), np.isnan(mo[:, 0]))
+    ok = np.isfinite(mo[:, 0])
+    for j, name in ((0, "rho"), (4, "T")):
+        e = _rel(mg[ok, j], mo[ok, j])
+        assert e <= tol, (name, e)
+    rho, T = mo[ok, 0], mo[ok, 4]
+    scales = {"U": max(np.max(np.linalg.norm(mo[ok, 1:4], axis=1)), np.max(np.sqrt(T))),
+              "q": max(np.max(np.linalg.norm(mo[ok, 5:8], axis=1)), np.max(rho * T ** 1.5))}
+    for sl, name in ((slice(1, 4), "U"), (slice(5, 8), "q")):
+        e = np.max(np.abs(mg[ok, sl] - mo[ok, sl])) / scales[name]
+        assert e <= tol, (name, e)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_initial_moments_and_fill(oracle_mod, torch_cuda):
+    """Moments of the perturbed freestream and one ghost construction on it
+    (Sections 2.1, 3.2.1-3.2.3) match the oracle."""
+    c = cases.cylinder_small()
+    o, s = _pair(oracle_mod, c)
+    _compare_moments(o, s)
+    ws = s.wall_state()
+    od = o.fill_debug()
+    assert _rel(ws["rhow"], od["rhow"]) <= TOL64
+    for A in range(2):
+        assert _rel(ws["ghost"][A], od["ghost"][A]) <= TOL64
+        assert _rel(ws["face"][A], od["face"][A]) <= TOL64
+    assert abs(s.clock()["step"]) == 0
+
+
+@pytest.mark.parametrize("nsteps", [1, 7])
+def test_step_parity_cylinder(oracle_mod, torch_cuda, nsteps):
+    c = cases.cylinder_small()
+    o, s = _pair(oracle_mod, c)
+    o.step(nsteps)
+    s.step(nsteps)
+    _compare_state(o, s)
+    _compare_moments(o, s)
+    co, cg = o.clock(), s.clock()
+    assert cg["step"] == nsteps and abs(cg["dt"] - co["dt"]) <= TOL64 * co["dt"]
+    assert abs(cg["time"] - co["time"]) <= TOL64 * co["time"]
+
+
+def test_cylinder_small_full_run(oracle_mod, torch_cuda):
+    """The 2D cylinder workload (32x32, 16x16 trapezoid velocity grid, Ma 0.5,
+    Kn 0.1, seed-0 perturbation, 500 steps): fields and C_D agree."""
+    c = cases.cylinder_small()
+    o, s = _pair(oracle_mod, c)
+    for _ in range(5):
+        o.step(100)
+        s.step(100)
+    _compare_moments(o, s)
+    Fo, cdo, clo, wo = o.forces()
+    Fg, cdg, clg, wg = s.surface_forces()
+    assert abs(cdg - cdo) <= TOL64 * abs(cdo)
+    assert abs(clg - clo) <= 1e-12 * abs(cdo)
+    assert _rel(wg[:, 6], wo[:, 6]) <= TOL64  # rho_w
+    assert _rel(wg[:, 7], wo[:, 7]) <= TOL64  # p_w
+
+
+def test_ragged_periodic_box(oracle_mod, torch_cuda):
+    """No body, periodic outer boundary, 13x11 velocity nodes (a partial
+    64-node tail): parity and discrete mass conservation."""
+    c = cases.case(dim=2, n=(12, 10), lo=(0.0, 0.0), hi=(1.0, 1.0), vn=(13, 11), vlo=(-4.0, -4.0),
+                   vhi=(4.0, 4.0), outer="periodic", Kn=0.05, Ma=0.3)
+    o, s = _pair(oracle_mod, c, amp=5e-2)
+    o.step(30)
+    s.step(30)
+    _compare_state(o, s)
+    _compare_moments(o, s)
+    # collisionless: the fluxes telescope, total mass is conserved to round-off
+    c = dict(c, Kn=1e15)
+    s = ibdvm.Solver(c)
+    s.init_freestream(cases.noise(c, 0), 5e-2)
+    w = o.velocity()[1]
+    m0 = (s.get_state()[0] @ w).sum()
+    s.step(30)
+    assert abs((s.get_state()[0] @ w).sum() - m0) <= 1e-13 * m0
+
+
+def test_ragged_body(oracle_mod, torch_cuda):
+    """Body, non-square grid and a ragged velocity tail."""
+    c = cases.case(dim=2, n=(24, 20), lo=(-1.2, -1.0), hi=(1.2, 1.0), vn=(13, 11), vlo=(-4.5, -4.0),
+                   vhi=(4.5, 4.0), geometry="circle", size=(0.41, 0.0, 0.0), Kn=0.2, Ma=0.7)
+    o, s = _pair(oracle_mod, c)
+    o.step(12)
+    s.step(12)
+    _compare_state(o, s)
+    _compare_moments(o, s)
+
+
+def test_partial_accommodation_bodies(oracle_mod, torch_cuda):
+    """Airfoil and ellipse at Ma 5 with alpha = 0.8 (specular part at the
+    mirrored velocity, Section 2.3) on a reduced grid."""
+    for c in cases.hypersonic_bodies(0, nx=128, ny=96, vn=20):
+        o, s = _pair(oracle_mod, c)
+        o.step(6)
+        s.step(6)
+        _compare_state(o, s)
+        _compare_moments(o, s)
+        ws, od = s.wall_state(), o.fill_debug()
+        assert _rel(ws["rhow"], od["rhow"]) <= TOL64
+
+
+def test_sphere_3d(oracle_mod, torch_cuda):
+    """3D full distribution, sphere (reduced size of the sphere workload)."""
+    c = cases.sphere(n=24, vn=10)
+    o, s = _pair(oracle_mod, c)
+    o.step(4)
+    s.step(4)
+    _compare_state(o, s)
+    _compare_moments(o, s)
+    Fo, cdo, _, _ = o.forces()
+    Fg, cdg, _, _ = s.surface_forces()
+    assert abs(cdg - cdo) <= TOL64 * abs(cdo)
+
+
+def test_f32_storage_error(oracle_mod, torch_cuda):
+    """FP32 storage with FP64 moments, equilibrium and wall terms: macroscopic
+    fields within 1e-5 relative L2 and C_D within 1e-4 of the FP64 oracle."""
+    c = cases.cylinder_small()
+    o, s = _pair(oracle_mod, c, precision="f32")
+    o.step(300)
+    s.step(300)
+    mg, mo = s.moments(), o.moments()
+    ok = np.isfinite(mo[:, 0])
+    for j in (0, 1, 2, 4):
+        e = np.linalg.norm(mg[ok, j] - mo[ok, j]) / np.linalg.norm(mo[ok, j])
+        assert e <= 1e-5, (j, e)
+    _, cdo, _, _ = o.forces()
+    _, cdg, _, _ = s.surface_forces()
+    assert abs(cdg - cdo) <= 1e-4
+
+
+def test_deterministic(torch_cuda):
+    c = cases.cylinder_small()
+    runs = []
+    for _ in range(2):
+        s = ibdvm.Solver(c)
+        s.init_freestream(cases.noise(c, 3), 1e-3)
+        s.step(25)
+        runs.append(s.get_state())
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_batch_alone_vs_mix(torch_cuda):
+    """Serving form: contexts of different sizes stepped together give the
+    same bits as each stepped alone."""
+    cs = [cases.cylinder_small(), cases.case(**dict(cases.cylinder_small(), vn=(12, 12), Kn=0.3)),
+          cases.case(dim=2, n=(20, 28), lo=(-1.0, -1.4), hi=(1.0, 1.4), vn=(10, 14), vlo=(-5.0, -5.0),
+                     vhi=(5.0, 5.0), geometry="circle", size=(0.35, 0.0, 0.0), Kn=0.05, Ma=1.2)]
+    alone = []
+    for c in cs:
+        s = ibdvm.Solver(c)
+        s.init_freestream(cases.noise(c, 1), 1e-3)
+        s.step(9)
+        alone.append(s.get_state())
+    mix = [ibdvm.Solver(c) for c in cs]
+    for c, s in zip(cs, mix):
+        s.init_freestream(cases.noise(c, 1), 1e-3)
+    ibdvm.batch_step(mix, 9)
+    for s, ref in zip(mix, alone):
+        for a, b in zip(s.get_state(), ref):
+            assert np.array_equal(a, b)
+
+
+def test_nan_state_reported(torch_cuda):
+    c = cases.cylinder_small()
+    s = ibdvm.Solver(c)
+    h, b = s.get_state()
+    h[0, 3] = np.nan  # cell 0 is a fluid cell at the domain corner
+    with pytest.raises(ibdvm.IbdvmError) as e:
+        s.set_state((h, b))
+    assert e.value.code == ibdvm.E_UNSTABLE
+    with pytest.raises(ibdvm.IbdvmError) as e:
+        s.step(1)
+    assert e.value.code == ibdvm.E_STATE
+
+
+def test_full_size_cylinder_step(oracle_mod, torch_cuda):
+    """The 256x256 x 48x48 workload at full size in the benchmark's launch
+    configuration: one step against the oracle, every cell."""
+    c = cases.cylinder_256(Kn=0.1, Ma=0.3)
+    o, s = _pair(oracle_mod, c)
+    o.step(1)
+    s.step(1)
+    _compare_moments(o, s)
+    ho, bo = o.get_state()
+    hg, bg = s.get_state()
+    assert _rel(hg, ho) <= TOL64 and _rel(bg, bo) <= TOL64
+
+
+TILES64 = [(1, 4, 32), (1, 8, 64), (2, 4, 16), (2, 8, 64), (1, 8, 7)]
+TILES32 = [(1, 8, 64), (2, 4, 32), (4, 8, 64), (4, 4, 5)]
+
+
+@pytest.mark.parametrize("precision,tile", [("f64", t) for t in TILES64] + [("f32", t) for t in TILES32])
+def test_tiles_agree_with_oracle(oracle_mod, torch_cuda, precision, tile):
+    """Every tile of the 2D update (nodes per lane, columns per workgroup,
+    rows per workgroup, including segments that do not divide the grid)
+    reproduces the oracle on a body case with a ragged velocity tail."""
+    c = cases.case(dim=2, n=(27, 22), lo=(-1.35, -1.1), hi=(1.35, 1.1), vn=(15, 11), vlo=(-4.5, -4.0),
+                   vhi=(4.5, 4.0), geometry="circle", size=(0.45, 0.0, 0.0), Kn=0.08, Ma=0.9)
+    o = oracle_mod.Oracle(c)
+    s = ibdvm.Solver(c, precision=precision)
+    s.set_tile(*tile)
+    u = cases.noise(c, 2)
+    o.init_freestream(u, 1e-3)
+    s.init_freestream(u, 1e-3)
+    o.step(6)
+    s.step(6)
+    if precision == "f64":
+        _compare_state(o, s)
+        _compare_moments(o, s)
+    else:
+        mg, mo = s.moments(), o.moments()
+        ok = np.isfinite(mo[:, 0])
+        for j in (0, 4):
+            assert np.max(np.abs(mg[ok, j] - mo[ok, j])) / np.max(np.abs(mo[ok, j])) <= 1e-6
+
+
+def test_autotune_leaves_state(torch_cuda):
+    """The autotuner times the update without advancing the solve."""
+    c = cases.cylinder_small()
+    s = ibdvm.Solver(c)
+    s.init_freestream(cases.noise(c, 0), 1e-3)
+    s.step(3)
+    before = s.get_state()
+    clk = s.clock()
+    tile = s.autotune(reps=2)
+    assert tile == s.get_tile()
+    after = s.get_state()
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+    assert s.clock() == clk
