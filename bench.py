@@ -44,12 +44,16 @@ def _traffic(workload, precision, launches_bytes):
     return rec.get("hbm_bytes_per_launch")
 
 
-def run_gpu(case, precision, steps, warmup, seed=0, profile=True):
+def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     import torch
     from paper_2512_20252_amd import cases, ibdvm
 
     s = ibdvm.Solver(case, precision=precision)
     s.init_freestream(cases.noise(case, seed), 1e-3)
+    if tile:
+        s.set_tile(*tile)
+    else:
+        s.autotune(reps=3)
     s.step(warmup)
     torch.cuda.synchronize()
     if profile:
@@ -64,7 +68,7 @@ def run_gpu(case, precision, steps, warmup, seed=0, profile=True):
     ms = t0.elapsed_time(t1)
     prof = s.profile_read() if profile else None
     _, cd, _, _ = s.surface_forces()
-    out = {"ms": ms, "prof": prof, "cd": cd, "nfluid": s.nfluid, "NV": s.NV, "dim": s.dim}
+    out = {"ms": ms, "prof": prof, "cd": cd, "nfluid": s.nfluid, "NV": s.NV, "dim": s.dim, "tile": s.get_tile()}
     del s
     torch.cuda.empty_cache()
     return out
@@ -91,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="time only the FP32-storage form")
+    ap.add_argument("--tile", type=str, default="", help="V,TX,LY of the 2D update (default: autotune)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -101,7 +107,12 @@ def main():
 
     case = cases.cylinder_256(Kn=0.1, Ma=0.3)
     workload = "cylinder_256x256_v48x48"
-    r64 = run_gpu(case, "f64", args.steps, args.warmup)
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    if args.no_f64:
+        r32 = run_gpu(case, "f32", args.steps, args.warmup, tile=tile)
+        print(json.dumps({"f32_ms_per_step": r32["ms"] / args.steps, "tile": r32["tile"], "prof": r32["prof"]}))
+        return
+    r64 = run_gpu(case, "f64", args.steps, args.warmup, tile=tile)
     upd = r64["nfluid"] * r64["NV"]
     value = upd * args.steps / (r64["ms"] * 1e-3)
     prof = r64["prof"]
@@ -128,10 +139,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
-                     "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1)},
+                     "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
+                     "tile": r64["tile"]},
     }
     if not args.no_f32:
         r32 = run_gpu(case, "f32", args.steps, args.warmup)
+        line["precision_form_tile"] = r32["tile"]
         v32 = upd * args.steps / (r32["ms"] * 1e-3)
         avg32 = r32["prof"]["update_ms"] / max(r32["prof"]["update_launches"], 1)
         line["precision_form"] = {"dtype": "f32 storage, f64 moments/equilibrium/wall", "value": v32,

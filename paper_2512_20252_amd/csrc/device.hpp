@@ -54,11 +54,12 @@ struct Dev {
     const double *xa;  // per-axis nodes [3][kMaxVn]
     const double *w;
     const double *fs[2];
+    const void *fsT[2];  // freestream rows in the storage type
     const double *hw;
     void *f[2][2];  // [buffer][array]
     double *cellp;
     double *part;
-    const uint8_t *cflag;
+    const int *cflag;  // CellFlag bits per cell
     const int *pnb;
     const DPair *pairs;
     const uint8_t *cls;

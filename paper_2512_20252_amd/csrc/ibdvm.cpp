@@ -29,7 +29,7 @@ ibdvm_status fail(ibdvm_status s, const std::string &msg)
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2][2], cellp, part, xi, xa, w, fs, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
+    size_t f[2][2], cellp, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
     size_t total;
     size_t state_bytes;  // one array of one buffer
 };
@@ -58,8 +58,9 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.xa = take((size_t)3 * ibdvm::kMaxVn * 8);
     L.w = take((size_t)g.NV * 8);
     L.fs = take((size_t)2 * g.NV * 8);
+    L.fsT = take((size_t)2 * g.NV * es);
     L.hw = take((size_t)g.NV * 8);
-    L.cflag = take((size_t)g.Nc);
+    L.cflag = take((size_t)g.Nc * 4);
     L.pnb = take((size_t)g.Nc * 6 * 4);
     L.pairs = take(np * sizeof(ibdvm::DPair));
     L.cls = take(np * g.NV);
@@ -471,11 +472,13 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.fs[0] = (const double *)(ws + L.fs);
     d.fs[1] = (const double *)(ws + L.fs) + NV;
     d.hw = (const double *)(ws + L.hw);
+    d.fsT[0] = ws + L.fsT;
+    d.fsT[1] = ws + L.fsT + (c->precision == IBDVM_F32_STORE ? 4 : 8) * (size_t)NV;
     for (int b = 0; b < 2; ++b)
         for (int A = 0; A < 2; ++A) d.f[b][A] = A < c->NA ? (void *)(ws + L.f[b][A]) : nullptr;
     d.cellp = (double *)(ws + L.cellp);
     d.part = (double *)(ws + L.part);
-    d.cflag = (const uint8_t *)(ws + L.cflag);
+    d.cflag = (const int *)(ws + L.cflag);
     d.pnb = (const int *)(ws + L.pnb);
     d.pairs = (const ibdvm::DPair *)(ws + L.pairs);
     d.cls = (const uint8_t *)(ws + L.cls);
@@ -502,7 +505,11 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (e == hipSuccess) e = up(L.w, g.w.data(), g.w.size() * 8);
     if (e == hipSuccess) e = up(L.fs, fs.data(), fs.size() * 8);
     if (e == hipSuccess) e = up(L.hw, hw.data(), hw.size() * 8);
-    if (e == hipSuccess) e = up(L.cflag, g.cflag.data(), g.cflag.size());
+    std::vector<float> fs32(fs.begin(), fs.end());
+    if (e == hipSuccess)
+        e = c->precision == IBDVM_F32_STORE ? up(L.fsT, fs32.data(), fs32.size() * 4) : up(L.fsT, fs.data(), fs.size() * 8);
+    std::vector<int> cflag32(g.cflag.begin(), g.cflag.end());
+    if (e == hipSuccess) e = up(L.cflag, cflag32.data(), cflag32.size() * 4);
     if (e == hipSuccess) e = up(L.pnb, g.pnb.data(), g.pnb.size() * 4);
     if (e == hipSuccess) e = up(L.pairs, dp.data(), dp.size() * sizeof(ibdvm::DPair));
     if (e == hipSuccess) e = up(L.cls, g.cls.data(), g.cls.size());
@@ -715,7 +722,7 @@ bool tile_supported(int precision, const ibdvm::Tile &t)
 {
     bool tx = t.TX == 4 || t.TX == 8;
     bool v = t.V == 1 || t.V == 2 || (precision == IBDVM_F32_STORE && t.V == 4);
-    return tx && v && t.LY >= 1;
+    return tx && v && t.LY >= 1 && t.LY <= 126;
 }
 }  // namespace
 
@@ -762,7 +769,7 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    const int Vs[3] = {1, 2, 4}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 128};
+    const int Vs[3] = {1, 2, 4}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 120};
     for (int V : Vs)
         for (int TX : TXs)
             for (int LY : LYs) {

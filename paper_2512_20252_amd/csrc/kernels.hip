@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "device.hpp"
 #include "launch.hpp"
@@ -43,6 +44,27 @@ __device__ __forceinline__ T vanleer(T s1, T s2)
 {
     if ((s1 > T(0) && s2 > T(0)) || (s1 < T(0) && s2 < T(0))) return T(2) * s1 * (s2 / (s1 + s2));
     return T(0);
+}
+
+// van Leer limiter of the hot update: 2 s1 s2 / (s1 + s2) for same-sign
+// differences, with the hardware reciprocal refined by Newton steps instead
+// of the IEEE division sequence (the result differs by a few ulp)
+__device__ __forceinline__ double vl_fast(double s1, double s2)
+{
+    const double p = s1 * s2, den = s1 + s2;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    const double sg = 2.0 * s1 * (s2 * r);
+    return (p > 0.0 && fabs(den) > 1e-290) ? sg : 0.0;
+}
+
+__device__ __forceinline__ float vl_fast(float s1, float s2)
+{
+    const float p = s1 * s2, den = s1 + s2;
+    const float r = __builtin_amdgcn_rcpf(den);
+    const float sg = 2.0f * s1 * (s2 * r);
+    return (p > 0.0f && fabsf(den) > 1e-35f) ? sg : 0.0f;
 }
 
 enum { NB_FLUID = 0, NB_BC = 1, NB_IB = 2 };
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
     const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (wave >= (long long)d.Nc * d.nchunk) return;
     const int c = (int)(wave / d.nchunk), chunk = (int)(wave - (long long)c * d.nchunk);
-    const uint8_t fl = d.cflag[c];
+    const int fl = d.cflag[c];
     const int NV = d.NV;
     const int k = chunk * kChunk + lane;
     const bool act = k < NV;
@@ -564,42 +586,75 @@ __device__ __forceinline__ void reduce9(const double S[9], double &r8, double &s
     s8 = wave_sum(S[8]);
 }
 
+// barrier for LDS traffic only: global loads issued before it stay in flight
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// wavefront-uniform values in scalar registers
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double unid(double x)
+{
+    long long b = __double_as_longlong(x);
+    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// start of the node row of cell (ic, jr); outer freestream ghosts read the
+// freestream row, periodic ghosts wrap
 template <typename T>
-__device__ __forceinline__ T load_bc(const Dev &d, const T *f, int A, int ic, int jr, int kk)
+__device__ __forceinline__ const T *row_of(const Dev &d, const T *f, const T *fsT, int ic, int jr)
 {
     const int nx = d.n[0], ny = d.n[1];
-    if (ic < 0 || ic >= nx || jr < 0 || jr >= ny) {
-        if (d.outer == 0) return (T)d.fs[A][kk];
+    if ((unsigned)ic >= (unsigned)nx || (unsigned)jr >= (unsigned)ny) {
+        if (d.outer == 0) return fsT;
         ic = (ic + nx) % nx;
         jr = (jr + ny) % ny;
     }
-    return f[(size_t)(ic + nx * jr) * d.NV + kk];
+    return f + (size_t)(ic + nx * jr) * d.NV;
 }
 
-__device__ __forceinline__ uint8_t flags_at(const Dev &d, int ic, int jr)
+// read-only tables indexed by wavefront-uniform values go through the
+// scalar cache (constant address space): the loads land in scalar registers
+// and are counted apart from the vector loads still in flight
+typedef const __attribute__((address_space(4))) int *cint_p;
+typedef const __attribute__((address_space(4))) double *cdbl_p;
+
+__device__ __forceinline__ int flags_at(const Dev &d, int ic, int jr)
 {
-    if (ic < 0 || ic >= d.n[0] || jr < 0 || jr >= d.n[1]) return 0;
-    return d.cflag[ic + d.n[0] * jr];
+    if ((unsigned)ic >= (unsigned)d.n[0] || (unsigned)jr >= (unsigned)d.n[1]) return 0;
+    return ((cint_p)d.cflag)[ic + d.n[0] * jr];
 }
 
+// ghost value / ghost-side face value of the pair seen from fluid cell c in
+// direction dir (2 axis + side)
 template <typename T>
 __device__ __forceinline__ T ghost_of(const Dev &d, int A, int c, int dir, int kk)
 {
-    return (T)d.ghost[A][(size_t)d.pnb[6 * c + dir] * d.NV + kk];
+    const int p = ((cint_p)d.pnb)[6 * c + dir];
+    return (T)d.ghost[A][(size_t)p * d.NV + kk];
 }
 
 template <typename T>
 __device__ __forceinline__ T facev_of(const Dev &d, int A, int c, int dir, int kk)
 {
-    return (T)d.face[A][(size_t)d.pnb[6 * c + dir] * d.NV + kk];
+    const int p = ((cint_p)d.pnb)[6 * c + dir];
+    return (T)d.face[A][(size_t)p * d.NV + kk];
 }
 
 template <typename T, int V, int TX>
 __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 {
     constexpr int W = 64 * V;
-    __shared__ T rowb[2][2][TX + 4][W];
-    __shared__ T slb[2][TX + 2][W];
+    // row j of the tile's columns and two halo columns per side (by row
+    // parity), and the outgoing x-face state of the TX + 2 cells the faces
+    // need: f + sigma/2 where xi_x > 0, f - sigma/2 otherwise
+    __shared__ T fb[2][2][TX + 4][W];
+    __shared__ T ob[2][TX + 2][W];
 
     const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
     const double dt = d.cfl / (d.adv + 1.0 / tmin);
@@ -617,12 +672,13 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
     const int tx = L % ntx, ys = (L / ntx) % nys, ch = L / (ntx * nys);
     const int nx = d.n[0], ny = d.n[1], NV = d.NV;
     const int i0 = tx * TX, j0 = ys * LY, j1 = min(j0 + LY, ny);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = uni(threadIdx.x >> 6);
     const int i = i0 + w;
     const bool col_in = i < nx;
 
     int kk[V];
-    bool act[V];
+    bool act[V], pos[V];
     double xx[V], xy[V], wk[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -632,33 +688,35 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
         xx[v] = d.xi[0][kk[v]];
         xy[v] = d.xi[1][kk[v]];
         wk[v] = act[v] ? d.w[kk[v]] : 0.0;
+        pos[v] = xx[v] > 0.0;
     }
     const T *fA[2] = {(const T *)d.f[cur][0], (const T *)d.f[cur][1]};
     T *gA[2] = {(T *)d.f[cur ^ 1][0], (T *)d.f[cur ^ 1][1]};
+    const T *fsT[2] = {(const T *)d.fsT[0], (const T *)d.fsT[1]};
     const T hdx = T(0.5);
     const double idx = d.inv_dx[0], idy = d.inv_dx[1];
 
-    // rows j-2..j+2 of the own column
-    T q[2][5][V];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int A = 0; A < 2; ++A)
-#pragma unroll
-            for (int v = 0; v < V; ++v) q[A][r][v] = load_bc(d, fA[A], A, i, j0 - 2 + r, kk[v]);
+    // halo columns loaded by wavefronts 0..3, halo face states made by 0..1
+    const int hcol = w < 2 ? i0 - 2 + w : i0 + TX + (w - 2);
+    const int hpos = w < 2 ? w : TX + 2 + (w - 2);
+    const int scol = w == 0 ? i0 - 1 : i0 + TX;
+    const int spos = w == 0 ? 0 : TX + 1;
+
+    auto flag_row = [&](int m) -> int { return col_in ? flags_at(d, i, m) : 0; };
+    auto flag_halo = [&](int m) -> int { return flags_at(d, scol, m); };
 
     // y slope of cell (i, m) from rows m-1, m, m+1 with ghost substitution
-    auto slope_y = [&](int A, int v, T fm, T f0, T fp, int m, uint8_t fl) -> T {
+    auto slope_y = [&](int A, int v, T fm, T f0, T fp, int m, int fl) -> T {
         if (fl & CF_SOLID) return T(0);
         if (fl & (CF_YM | CF_YP)) {
             const int c = i + nx * m;
             if (fl & CF_YM) fm = ghost_of<T>(d, A, c, 2, kk[v]);
             if (fl & CF_YP) fp = ghost_of<T>(d, A, c, 3, kk[v]);
         }
-        return vanleer(f0 - fm, fp - f0);
+        return vl_fast(f0 - fm, fp - f0);
     };
     // upwind state of the face between rows m (below) and m+1 (above)
-    auto face_y = [&](int A, int v, T fl_, T sl_, uint8_t flL, T fr_, T sr_, uint8_t flR, int m) -> T {
+    auto face_y = [&](int A, int v, T fl_, T sl_, int flL, T fr_, T sr_, int flR, int m) -> T {
         if (xy[v] > 0.0) {
             if (!(flL & CF_SOLID)) return fl_ + hdx * sl_;
             if (flR & CF_SOLID) return T(0);
@@ -669,142 +727,222 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
         return facev_of<T>(d, A, i + nx * m, 3, kk[v]);
     };
 
-    uint8_t flm1 = flags_at(d, i, j0 - 1), fl0 = flags_at(d, i, j0);
+    // rows j-1..j+2 of the own column; the row after next, the next halo row
+    // and the next cell's equilibrium parameters are fetched one row ahead
+    T q[2][4][V], nxt[2][V], hnx[2][V];
+    double cpn[8];
+    auto fetch_cell = [&](int m) {
+        const cdbl_p cp = (cdbl_p)d.cellp + (size_t)(col_in ? i + nx * m : 0) * kCellWords;
+        cpn[0] = cp[CW_U];
+        cpn[1] = cp[CW_U + 1];
+        cpn[2] = cp[CW_A];
+        cpn[3] = cp[CW_INVT];
+        cpn[4] = cp[CW_S];
+        cpn[5] = cp[CW_S + 1];
+        cpn[6] = cp[CW_TH];
+        cpn[7] = cp[CW_INVTAU];
+    };
     T s0[2][V], Fdn[2][V];
+    {
+        T qm2[2][V];
 #pragma unroll
-    for (int A = 0; A < 2; ++A)
+        for (int A = 0; A < 2; ++A) {
+            const T *r0 = row_of(d, fA[A], fsT[A], i, j0 - 2);
+            const T *r1 = row_of(d, fA[A], fsT[A], i, j0 - 1);
+            const T *r2 = row_of(d, fA[A], fsT[A], i, j0);
+            const T *r3 = row_of(d, fA[A], fsT[A], i, j0 + 1);
+            const T *rp = row_of(d, fA[A], fsT[A], i, j0 + 2);
+            const T *hp = row_of(d, fA[A], fsT[A], hcol, j0);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            T sm = slope_y(A, v, q[A][0][v], q[A][1][v], q[A][2][v], j0 - 1, flm1);
-            s0[A][v] = slope_y(A, v, q[A][1][v], q[A][2][v], q[A][3][v], j0, fl0);
-            Fdn[A][v] = face_y(A, v, q[A][1][v], sm, flm1, q[A][2][v], s0[A][v], fl0, j0 - 1);
+            for (int v = 0; v < V; ++v) {
+                qm2[A][v] = r0[kk[v]];
+                q[A][0][v] = r1[kk[v]];
+                q[A][1][v] = r2[kk[v]];
+                q[A][2][v] = r3[kk[v]];
+                nxt[A][v] = rp[kk[v]];
+                hnx[A][v] = w < 4 ? hp[kk[v]] : T(0);
+            }
         }
-
-    // halo column handled by wavefronts 0..3 and halo slope by 0..1
-    const int hcol = w < 2 ? i0 - 2 + w : i0 + TX + (w - 2);
-    const int hpos = w < 2 ? w : TX + 2 + (w - 2);
-    const int scol = w == 0 ? i0 - 1 : i0 + TX;
-    const int spos = w == 0 ? 0 : TX + 1;
-
-    for (int j = j0; j < j1; ++j) {
-        const int buf = (j - j0) & 1;
+        fetch_cell(j0);
+        const int flm1 = flag_row(j0 - 1), fl0i = flag_row(j0);
 #pragma unroll
         for (int A = 0; A < 2; ++A)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                q[A][4][v] = load_bc(d, fA[A], A, i, j + 2, kk[v]);
-                rowb[buf][A][w + 2][v * 64 + lane] = q[A][2][v];
+                T sm = slope_y(A, v, qm2[A][v], q[A][0][v], q[A][1][v], j0 - 1, flm1);
+                s0[A][v] = slope_y(A, v, q[A][0][v], q[A][1][v], q[A][2][v], j0, fl0i);
+                Fdn[A][v] = face_y(A, v, q[A][0][v], sm, flm1, q[A][1][v], s0[A][v], fl0i, j0 - 1);
             }
-        if (w < 4) {
+    }
+    int fl0 = flag_row(j0);
+
+    for (int j = j0; j < j1; ++j) {
+        const int buf = (j - j0) & 1;
+        // q[A][1] is row j, q[A][2] row j+1, q[A][3] row j+2
+        T hcur[2][V];
 #pragma unroll
-            for (int A = 0; A < 2; ++A)
+        for (int A = 0; A < 2; ++A)
 #pragma unroll
-                for (int v = 0; v < V; ++v) rowb[buf][A][hpos][v * 64 + lane] = load_bc(d, fA[A], A, hcol, j, kk[v]);
+            for (int v = 0; v < V; ++v) {
+                q[A][3][v] = nxt[A][v];
+                hcur[A][v] = hnx[A][v];
+            }
+        // equilibrium parameters of cell (i, j), wavefront-uniform
+        const double U0 = cpn[0], U1 = cpn[1], Ac = cpn[2], invT = cpn[3];
+        const double S0 = cpn[4], S1 = cpn[5], Th = cpn[6], itau = cpn[7];
+        if (j + 1 < j1) {
+#pragma unroll
+            for (int A = 0; A < 2; ++A) {
+                const T *rp = row_of(d, fA[A], fsT[A], i, j + 3);
+#pragma unroll
+                for (int v = 0; v < V; ++v) nxt[A][v] = rp[kk[v]];
+                if (w < 4) {
+                    const T *hp = row_of(d, fA[A], fsT[A], hcol, j + 1);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) hnx[A][v] = hp[kk[v]];
+                }
+            }
+            fetch_cell(j + 1);
         }
-        __syncthreads();
-        // x slopes of the own cell and of the two halo cells next to the tile
+#pragma unroll
+        for (int A = 0; A < 2; ++A)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                fb[buf][A][w + 2][v * 64 + lane] = q[A][1][v];
+                if (w < 4) fb[buf][A][hpos][v * 64 + lane] = hcur[A][v];
+            }
+        lds_barrier();
+        // outgoing x-face states of the own cell and of the halo cell
+        T own_out[2][V];
         {
-            const int nslope = w < 2 ? 2 : 1;
-            for (int t = 0; t < nslope; ++t) {
-                const int col = t == 0 ? i : scol;
-                const int p = t == 0 ? w + 2 : spos + 1;
-                const int sidx = t == 0 ? w + 1 : spos;
-                const uint8_t fl = t == 0 ? fl0 : flags_at(d, col, j);
-                const int c = col + nx * j;
+            const int c = i + nx * j;
+            auto run = [&](auto near_tag) {
+                constexpr bool NEAR = decltype(near_tag)::value;
 #pragma unroll
                 for (int A = 0; A < 2; ++A)
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
-                        T fm = rowb[buf][A][p - 1][v * 64 + lane];
-                        T f0 = rowb[buf][A][p][v * 64 + lane];
-                        T fp = rowb[buf][A][p + 1][v * 64 + lane];
-                        T s = T(0);
-                        if (!(fl & CF_SOLID)) {
-                            if (fl & CF_XM) fm = ghost_of<T>(d, A, c, 0, kk[v]);
-                            if (fl & CF_XP) fp = ghost_of<T>(d, A, c, 1, kk[v]);
-                            s = vanleer(f0 - fm, fp - f0);
-                        }
-                        slb[A][sidx][v * 64 + lane] = s;
+                        T fm = fb[buf][A][w + 1][v * 64 + lane];
+                        T fp = fb[buf][A][w + 3][v * 64 + lane];
+                        const T f0 = q[A][1][v];
+                        if (NEAR && (fl0 & CF_XM)) fm = ghost_of<T>(d, A, c, 0, kk[v]);
+                        if (NEAR && (fl0 & CF_XP)) fp = ghost_of<T>(d, A, c, 1, kk[v]);
+                        T s = vl_fast(f0 - fm, fp - f0);
+                        if (NEAR && (fl0 & CF_SOLID)) s = T(0);
+                        const T o = pos[v] ? f0 + hdx * s : f0 - hdx * s;
+                        own_out[A][v] = o;
+                        ob[A][w + 1][v * 64 + lane] = o;
                     }
-            }
+            };
+            if (fl0 & (CF_SOLID | CF_XM | CF_XP))
+                run(std::true_type{});
+            else
+                run(std::false_type{});
         }
-        __syncthreads();
+        if (w < 2) {
+            const int fl = flag_halo(j);
+            const int c = scol + nx * j;
+            auto run = [&](auto near_tag) {
+                constexpr bool NEAR = decltype(near_tag)::value;
+#pragma unroll
+                for (int A = 0; A < 2; ++A)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        T fm = fb[buf][A][spos][v * 64 + lane];
+                        const T f0 = fb[buf][A][spos + 1][v * 64 + lane];
+                        T fp = fb[buf][A][spos + 2][v * 64 + lane];
+                        if (NEAR && (fl & CF_XM)) fm = ghost_of<T>(d, A, c, 0, kk[v]);
+                        if (NEAR && (fl & CF_XP)) fp = ghost_of<T>(d, A, c, 1, kk[v]);
+                        T s = vl_fast(f0 - fm, fp - f0);
+                        if (NEAR && (fl & CF_SOLID)) s = T(0);
+                        ob[A][spos][v * 64 + lane] = pos[v] ? f0 + hdx * s : f0 - hdx * s;
+                    }
+            };
+            if (fl & (CF_SOLID | CF_XM | CF_XP))
+                run(std::true_type{});
+            else
+                run(std::false_type{});
+        }
+        lds_barrier();
 
-        const uint8_t flp1 = flags_at(d, i, j + 1);
+        const int flp1 = flag_row(j + 1);
         const int c = i + nx * j;
         const bool upd = col_in && !(fl0 & CF_SOLID);
         double mom[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        // cell parameters of the Shakhov equilibrium (uniform per wavefront)
-        double U0 = 0, U1 = 0, Ac = 0, invT = 0, S0 = 0, S1 = 0, Th = 0, itau = 0;
-        if (upd) {
-            const double *cp = d.cellp + (size_t)c * kCellWords;
-            U0 = cp[CW_U];
-            U1 = cp[CW_U + 1];
-            Ac = cp[CW_A];
-            invT = cp[CW_INVT];
-            S0 = cp[CW_S];
-            S1 = cp[CW_S + 1];
-            Th = cp[CW_TH];
-            itau = cp[CW_INVTAU];
-        }
         const double rate = dt * itau;
+        T *g0 = gA[0] + (size_t)c * NV, *g1 = gA[1] + (size_t)c * NV;
+        auto run = [&](auto near_tag) {
+            constexpr bool NEAR = decltype(near_tag)::value;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            T s1[2];
-            T Fup[2];
-#pragma unroll
-            for (int A = 0; A < 2; ++A) {
-                s1[A] = slope_y(A, v, q[A][2][v], q[A][3][v], q[A][4][v], j + 1, flp1);
-                Fup[A] = face_y(A, v, q[A][2][v], s0[A][v], fl0, q[A][3][v], s1[A], flp1, j);
-            }
-            if (upd) {
-                const double cx = xx[v] - U0, cy = xy[v] - U1;
-                const double c2 = cx * cx + cy * cy, cs = cx * S0 + cy * S1;
-                const double H = Ac * exp(-c2 * invT);
-                const double gS[2] = {H * (1.0 + cs * (2.0 * c2 * invT - 4.0)), Th * H * (1.0 + cs * (2.0 * c2 * invT - 2.0))};
-                double fnew[2];
+            for (int v = 0; v < V; ++v) {
+                T s1[2];
+                T Fup[2];
 #pragma unroll
                 for (int A = 0; A < 2; ++A) {
-                    const T f0 = q[A][2][v];
-                    const T sx = slb[A][w + 1][v * 64 + lane];
-                    T Fr, Fl;
-                    if (xx[v] > 0.0) {
-                        Fr = f0 + hdx * sx;
-                        Fl = (fl0 & CF_XM) ? facev_of<T>(d, A, c, 0, kk[v])
-                                           : rowb[buf][A][w + 1][v * 64 + lane] + hdx * slb[A][w][v * 64 + lane];
+                    if (NEAR) {
+                        s1[A] = slope_y(A, v, q[A][1][v], q[A][2][v], q[A][3][v], j + 1, flp1);
+                        Fup[A] = face_y(A, v, q[A][1][v], s0[A][v], fl0, q[A][2][v], s1[A], flp1, j);
                     } else {
-                        Fl = f0 - hdx * sx;
-                        Fr = (fl0 & CF_XP) ? facev_of<T>(d, A, c, 1, kk[v])
-                                           : rowb[buf][A][w + 3][v * 64 + lane] - hdx * slb[A][w + 2][v * 64 + lane];
+                        const T fm = q[A][1][v], f0 = q[A][2][v], fp = q[A][3][v];
+                        s1[A] = vl_fast(f0 - fm, fp - f0);
+                        Fup[A] = xy[v] > 0.0 ? fm + hdx * s0[A][v] : f0 - hdx * s1[A];
                     }
-                    const T div = (T)xx[v] * (Fr - Fl) * (T)idx + (T)xy[v] * (Fup[A] - Fdn[A][v]) * (T)idy;
-                    const double fo = (double)f0;
-                    const T st = (T)(fo - dt * (double)div + rate * (gS[A] - fo));
-                    if (act[v]) gA[A][(size_t)c * NV + kk[v]] = st;
-                    fnew[A] = act[v] ? (double)st : 0.0;
                 }
-                const double h = fnew[0], E = c2 * h + fnew[1], wv = wk[v];
-                mom[0] += wv * h;
-                mom[1] += wv * cx * h;
-                mom[2] += wv * cy * h;
-                mom[3] += wv * E;
-                mom[4] += wv * cx * E;
-                mom[5] += wv * cy * E;
-                mom[6] += wv * cx * cx * h;
-                mom[7] += wv * cx * cy * h;
-                mom[8] += wv * cy * cy * h;
-            } else if (col_in && act[v]) {
-                gA[0][(size_t)c * NV + kk[v]] = q[0][2][v];
-                gA[1][(size_t)c * NV + kk[v]] = q[1][2][v];
-            }
+                if (upd) {
+                    const double cx = xx[v] - U0, cy = xy[v] - U1;
+                    const double c2 = cx * cx + cy * cy, cs = cx * S0 + cy * S1;
+                    const double H = Ac * exp(-c2 * invT);
+                    const double gS[2] = {H * (1.0 + cs * (2.0 * c2 * invT - 4.0)),
+                                          Th * H * (1.0 + cs * (2.0 * c2 * invT - 2.0))};
+                    double fnew[2];
 #pragma unroll
-            for (int A = 0; A < 2; ++A) {
-                Fdn[A][v] = Fup[A];
-                s0[A][v] = s1[A];
+                    for (int A = 0; A < 2; ++A) {
+                        const T f0 = q[A][1][v];
+                        // the neighbour's outgoing state is the face state on the upwind side
+                        const T nb = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
+                        T Fr, Fl;
+                        if (pos[v]) {
+                            Fr = own_out[A][v];
+                            Fl = (NEAR && (fl0 & CF_XM)) ? facev_of<T>(d, A, c, 0, kk[v]) : nb;
+                        } else {
+                            Fl = own_out[A][v];
+                            Fr = (NEAR && (fl0 & CF_XP)) ? facev_of<T>(d, A, c, 1, kk[v]) : nb;
+                        }
+                        const T div = (T)xx[v] * (Fr - Fl) * (T)idx + (T)xy[v] * (Fup[A] - Fdn[A][v]) * (T)idy;
+                        const double fo = (double)f0;
+                        const T st = (T)(fo - dt * (double)div + rate * (gS[A] - fo));
+                        if (act[v]) (A == 0 ? g0 : g1)[kk[v]] = st;
+                        fnew[A] = act[v] ? (double)st : 0.0;
+                    }
+                    const double wh = wk[v] * fnew[0], wE = wk[v] * (c2 * fnew[0] + fnew[1]);
+                    const double tx_ = cx * wh, ty_ = cy * wh;
+                    mom[0] += wh;
+                    mom[1] += tx_;
+                    mom[2] += ty_;
+                    mom[3] += wE;
+                    mom[4] += cx * wE;
+                    mom[5] += cy * wE;
+                    mom[6] += cx * tx_;
+                    mom[7] += cy * tx_;
+                    mom[8] += cy * ty_;
+                } else if (col_in && act[v]) {
+                    // solid cells are not advanced; carry their value
+                    g0[kk[v]] = q[0][1][v];
+                    g1[kk[v]] = q[1][1][v];
+                }
+#pragma unroll
+                for (int A = 0; A < 2; ++A) {
+                    Fdn[A][v] = Fup[A];
+                    s0[A][v] = s1[A];
+                }
             }
-        }
+        };
+        if ((fl0 | flp1) & (CF_SOLID | CF_XM | CF_XP | CF_YM | CF_YP))
+            run(std::true_type{});
+        else
+            run(std::false_type{});
         if (upd) {
-            // S order of the partial record: m0, m1x, m1y, m2, m3x, m3y, Mxx, Mxy, Myy
+            // partial record: m0, m1x, m1y, m2, m3x, m3y, Mxx, Mxy, Myy
             double r8, s8;
             reduce9(mom, r8, s8);
             double *pp = d.part + ((size_t)c * ncv + ch) * kPartialStride;
@@ -819,7 +957,6 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
                 q[A][0][v] = q[A][1][v];
                 q[A][1][v] = q[A][2][v];
                 q[A][2][v] = q[A][3][v];
-                q[A][3][v] = q[A][4][v];
             }
     }
 }
