@@ -29,7 +29,7 @@ ibdvm_status fail(ibdvm_status s, const std::string &msg)
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2][2], cellp, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
+    size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
     size_t total;
     size_t state_bytes;  // one array of one buffer
 };
@@ -53,6 +53,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     for (int b = 0; b < 2; ++b)
         for (int A = 0; A < 2; ++A) L.f[b][A] = A < NA ? take(nf * es) : 0;
     L.cellp = take((size_t)g.Nc * ibdvm::kCellWords * 8);
+    L.cellq = take(g.D == 2 ? (size_t)g.Nc * ibdvm::kQWords * 8 : 0);
     L.part = take((size_t)g.Nc * nchunk * ibdvm::kPartialStride * 8);
     L.xi = take((size_t)3 * g.NV * 8);
     L.xa = take((size_t)3 * ibdvm::kMaxVn * 8);
@@ -477,6 +478,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     for (int b = 0; b < 2; ++b)
         for (int A = 0; A < 2; ++A) d.f[b][A] = A < c->NA ? (void *)(ws + L.f[b][A]) : nullptr;
     d.cellp = (double *)(ws + L.cellp);
+    d.cellq = (double *)(ws + L.cellq);
     d.part = (double *)(ws + L.part);
     d.cflag = (const int *)(ws + L.cflag);
     d.pnb = (const int *)(ws + L.pnb);
@@ -509,6 +511,26 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (e == hipSuccess)
         e = c->precision == IBDVM_F32_STORE ? up(L.fsT, fs32.data(), fs32.size() * 4) : up(L.fsT, fs.data(), fs.size() * 8);
     std::vector<int> cflag32(g.cflag.begin(), g.cflag.end());
+    if (D == 2) {
+        // second neighbours along x, and the 2D update records with the
+        // flag word of the cell above (parameters are written on device)
+        const int nx = c->prob.n[0], ny = c->prob.n[1];
+        auto solid = [&](int i, int j) { return i >= 0 && i < nx && (g.cflag[i + nx * j] & ibdvm::CF_SOLID); };
+        std::vector<double> qrec((size_t)g.Nc * ibdvm::kQWords, 0.0);
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                int &f = cflag32[i + nx * j];
+                if (solid(i - 2, j)) f |= ibdvm::CF_XM2;
+                if (solid(i + 2, j)) f |= ibdvm::CF_XP2;
+            }
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const int up_flags = j + 1 < ny ? cflag32[i + nx * (j + 1)] : 0;
+                std::memcpy(&qrec[(size_t)(i + nx * j) * ibdvm::kQWords + 8], &up_flags, 4);
+            }
+        if (e == hipSuccess) e = up(L.cellq, qrec.data(), qrec.size() * 8);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
     if (e == hipSuccess) e = up(L.cflag, cflag32.data(), cflag32.size() * 4);
     if (e == hipSuccess) e = up(L.pnb, g.pnb.data(), g.pnb.size() * 4);
     if (e == hipSuccess) e = up(L.pairs, dp.data(), dp.size() * sizeof(ibdvm::DPair));
@@ -721,7 +743,8 @@ namespace {
 bool tile_supported(int precision, const ibdvm::Tile &t)
 {
     bool tx = t.TX == 4 || t.TX == 8;
-    bool v = t.V == 1 || t.V == 2 || (precision == IBDVM_F32_STORE && t.V == 4);
+    bool v = t.V == 1 || t.V == 2;
+    (void)precision;
     return tx && v && t.LY >= 1 && t.LY <= 126;
 }
 }  // namespace
@@ -769,7 +792,7 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    const int Vs[3] = {1, 2, 4}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 120};
+    const int Vs[2] = {1, 2}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 120};
     for (int V : Vs)
         for (int TX : TXs)
             for (int LY : LYs) {

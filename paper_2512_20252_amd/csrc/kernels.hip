@@ -46,27 +46,6 @@ __device__ __forceinline__ T vanleer(T s1, T s2)
     return T(0);
 }
 
-// van Leer limiter of the hot update: 2 s1 s2 / (s1 + s2) for same-sign
-// differences, with the hardware reciprocal refined by Newton steps instead
-// of the IEEE division sequence (the result differs by a few ulp)
-__device__ __forceinline__ double vl_fast(double s1, double s2)
-{
-    const double p = s1 * s2, den = s1 + s2;
-    double r = __builtin_amdgcn_rcp(den);
-    r = fma(fma(-den, r, 1.0), r, r);
-    r = fma(fma(-den, r, 1.0), r, r);
-    const double sg = 2.0 * s1 * (s2 * r);
-    return (p > 0.0 && fabs(den) > 1e-290) ? sg : 0.0;
-}
-
-__device__ __forceinline__ float vl_fast(float s1, float s2)
-{
-    const float p = s1 * s2, den = s1 + s2;
-    const float r = __builtin_amdgcn_rcpf(den);
-    const float sg = 2.0f * s1 * (s2 * r);
-    return (p > 0.0f && fabsf(den) > 1e-35f) ? sg : 0.0f;
-}
-
 enum { NB_FLUID = 0, NB_BC = 1, NB_IB = 2 };
 
 // Value seen from fluid cell c (grid coordinates ijk) at c + side e_a:
@@ -118,6 +97,17 @@ __device__ double write_cell(const Dev &d, int c, double rho, const double U[3],
     cp[CW_RHO] = rho;
     cp[CW_T] = T;
     cp[CW_TAU] = tau;
+    if (D == 2) {
+        double *k2 = d.cellq + (size_t)c * kQWords;
+        k2[0] = U[0];
+        k2[1] = U[1];
+        k2[2] = A;
+        k2[3] = 1.0 / T;
+        k2[4] = coef * q[0];
+        k2[5] = coef * q[1];
+        k2[6] = 0.5 * T;
+        k2[7] = 1.0 / tau;
+    }
     bool bad = !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite(tau);
     if (bad) atomicOr(&d.ctrl->health, 1u);
     return bad ? INFINITY : tau;
@@ -556,34 +546,83 @@ __global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
 // ghost value of the pair seen from the fluid cell, and faces toward a solid
 // cell take the pair's ghost-side face value.
 
-// sums S[0..8] over the 64 lanes; lane 8m holds the total of S[m] for m < 8,
-// every lane holds the total of S[8].  Three exchange steps halve the number
-// of values each lane carries, three more finish the lane sum.
+// cross-lane helpers on doubles (two 32-bit halves each)
+__device__ __forceinline__ double mk_dbl(unsigned hi, unsigned lo)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v_permlane32_swap: the upper 32 lanes of x trade places with the lower 32
+// lanes of y
+__device__ __forceinline__ void swap32(double &x, double &y)
+{
+    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = mk_dbl(hi[0], lo[0]);
+    y = mk_dbl(hi[1], lo[1]);
+}
+
+// v_permlane16_swap: within each 32-lane half, lanes 16..31 of x trade places
+// with lanes 0..15 of y
+__device__ __forceinline__ void swap16(double &x, double &y)
+{
+    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = mk_dbl(hi[0], lo[0]);
+    y = mk_dbl(hi[1], lo[1]);
+}
+
+// DPP rotation within 16-lane rows
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x)
+{
+    unsigned long long b = __double_as_longlong(x);
+    unsigned lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    unsigned hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return mk_dbl(hi, lo);
+}
+constexpr int kRowRor1 = 0x121, kRowRor2 = 0x122, kRowRor4 = 0x124, kRowRor8 = 0x128;
+
+// sums S[0..8] over the 64 lanes.  Three exchange steps halve the number of
+// values each lane carries (after them lane l holds value 4 b5 + 2 b4 + b3
+// summed over the 8 lanes that share bits 0..2), three rotate-and-add steps
+// finish the sums in lanes 8m + 7 (whose sources stay inside their group).  On return lane 8m + 7 holds the total of
+// S[m] for m < 8 and lanes 7 and 15 hold the total of S[8].
 __device__ __forceinline__ void reduce9(const double S[9], double &r8, double &s8)
 {
     const int lane = threadIdx.x & 63;
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
     double a[4], b[2];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        double keep = b5 ? S[4 + i] : S[i];
-        double send = b5 ? S[i] : S[4 + i];
-        a[i] = keep + __shfl_xor(send, 32, 64);
+        double x = S[i], y = S[4 + i];
+        swap32(x, y);
+        a[i] = x + y;
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-        double keep = b4 ? a[2 + i] : a[i];
-        double send = b4 ? a[i] : a[2 + i];
-        b[i] = keep + __shfl_xor(send, 16, 64);
+        double x = a[i], y = a[2 + i];
+        swap16(x, y);
+        b[i] = x + y;
     }
-    double keep = b3 ? b[1] : b[0];
-    double send = b3 ? b[0] : b[1];
-    double c = keep + __shfl_xor(send, 8, 64);
-    c += __shfl_xor(c, 4, 64);
-    c += __shfl_xor(c, 2, 64);
-    c += __shfl_xor(c, 1, 64);
+    const bool b3 = lane & 8;
+    double c = (b3 ? b[1] : b[0]) + dpp<kRowRor8>(b3 ? b[0] : b[1]);
+    c += dpp<kRowRor4>(c);
+    c += dpp<kRowRor2>(c);
+    c += dpp<kRowRor1>(c);
     r8 = c;
-    s8 = wave_sum(S[8]);
+    double s = S[8], t = S[8];
+    swap32(s, t);
+    s += t;
+    t = s;
+    swap16(s, t);
+    s += t;
+    s += dpp<kRowRor8>(s);
+    s += dpp<kRowRor4>(s);
+    s += dpp<kRowRor2>(s);
+    s += dpp<kRowRor1>(s);
+    s8 = s;
 }
 
 // barrier for LDS traffic only: global loads issued before it stay in flight
@@ -596,65 +635,122 @@ __device__ __forceinline__ void lds_barrier()
 
 // wavefront-uniform values in scalar registers
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ double unid(double x)
-{
-    long long b = __double_as_longlong(x);
-    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
-    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// start of the node row of cell (ic, jr); outer freestream ghosts read the
-// freestream row, periodic ghosts wrap
-template <typename T>
-__device__ __forceinline__ const T *row_of(const Dev &d, const T *f, const T *fsT, int ic, int jr)
-{
-    const int nx = d.n[0], ny = d.n[1];
-    if ((unsigned)ic >= (unsigned)nx || (unsigned)jr >= (unsigned)ny) {
-        if (d.outer == 0) return fsT;
-        ic = (ic + nx) % nx;
-        jr = (jr + ny) % ny;
-    }
-    return f + (size_t)(ic + nx * jr) * d.NV;
-}
 
 // read-only tables indexed by wavefront-uniform values go through the
 // scalar cache (constant address space): the loads land in scalar registers
-// and are counted apart from the vector loads still in flight
 typedef const __attribute__((address_space(4))) int *cint_p;
-typedef const __attribute__((address_space(4))) double *cdbl_p;
 
-__device__ __forceinline__ int flags_at(const Dev &d, int ic, int jr)
+// ---------------------------------------------------------------- 2D update
+//
+// Raw buffer access: the descriptor carries the base address and the byte
+// length of one velocity row, so the address arithmetic of a row is scalar,
+// lanes past the end of the row read 0, and their stores are dropped.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t brsrc;
+constexpr int kRsrcW3 = 0x00020000;  // descriptor word 3 on the gfx9 family: 32-bit data format
+constexpr int kOob = 0x40000000;     // an offset past every buffer
+
+__device__ __forceinline__ brsrc mk_rsrc(const void *p, int bytes)
 {
-    if ((unsigned)ic >= (unsigned)d.n[0] || (unsigned)jr >= (unsigned)d.n[1]) return 0;
-    return ((cint_p)d.cflag)[ic + d.n[0] * jr];
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, kRsrcW3);
+}
+__device__ __forceinline__ double bld(brsrc r, int off, double)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ float bld(brsrc r, int off, float)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void bst(brsrc r, int off, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, 0);
+}
+__device__ __forceinline__ void bst(brsrc r, int off, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, off, 0, 0);
 }
 
-// ghost value / ghost-side face value of the pair seen from fluid cell c in
-// direction dir (2 axis + side)
+// half the van Leer limited slope of one-sided differences d1, d2:
+// d1 d2 / (d1 + d2) when they have the same sign, else 0 (d1 d2 > 0 keeps
+// |d1 + d2| far from the reciprocal's overflow range)
+__device__ __forceinline__ double vl_half(double d1, double d2)
+{
+    const double p = d1 * d2, den = d1 + d2;
+    double r = __builtin_amdgcn_rcp(den);
+    r = fma(fma(-den, r, 1.0), r, r);
+    r = fma(fma(-den, r, 1.0), r, r);
+    return p > 0.0 ? p * r : 0.0;
+}
+__device__ __forceinline__ float vl_half(float d1, float d2)
+{
+    const float p = d1 * d2, den = d1 + d2;
+    return p > 0.0f ? p * __builtin_amdgcn_rcpf(den) : 0.0f;
+}
+
+// exp(x) for x <= 0: x = (32 m + j) ln2/32 + r with |r| <= ln2/64, so
+// exp(x) = 2^m 2^(j/32) exp(r); 2^(j/32) comes from a 32-entry table and
+// exp(r) from its degree-6 Taylor polynomial (truncation below 4e-18
+// relative).  Below -746 the result underflows to 0.
+__device__ __forceinline__ double exp_neg(double x, const double *tab)
+{
+    constexpr double kInvL = 46.16624130844683;       // 32 / ln 2
+    constexpr double kLhi = 0.02166084939249829;      // ln 2 / 32, leading part
+    constexpr double kLlo = 7.247021293269686e-19;    // ln 2 / 32 - kLhi
+    x = fmax(x, -746.0);
+    const double n = __builtin_rint(x * kInvL);
+    double r = fma(-n, kLhi, x);
+    r = fma(-n, kLlo, r);
+    double p = fma(r, 1.0 / 720, 1.0 / 120);
+    p = fma(p, r, 1.0 / 24);
+    p = fma(p, r, 1.0 / 6);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    const int ni = (int)n;
+    return ldexp(tab[ni & 31] * p, ni >> 5);
+}
+
 template <typename T>
-__device__ __forceinline__ T ghost_of(const Dev &d, int A, int c, int dir, int kk)
+__device__ __forceinline__ T ghost_at(const Dev &d, int A, int c, int dir, int kk)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     return (T)d.ghost[A][(size_t)p * d.NV + kk];
 }
-
 template <typename T>
-__device__ __forceinline__ T facev_of(const Dev &d, int A, int c, int dir, int kk)
+__device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int kk)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     return (T)d.face[A][(size_t)p * d.NV + kk];
 }
 
+// One workgroup = TX wavefronts = TX adjacent columns i0..i0+TX-1, rows
+// j0..j1-1, and one chunk of 64 V velocity nodes (lane l holds nodes
+// chunk*64V + 64 v + l).  Each wavefront marches its column upward.  Per row
+// j the row is staged in LDS with two halo columns per side, the outgoing
+// x-face states (f + sigma/2 toward the downwind side) are exchanged through
+// LDS, and the y direction is carried in registers: rows j..j+2 are held, row
+// j+3 arrives one row ahead, and the outgoing y state of row j and the face
+// j-1/2 come from the previous row.  The Shakhov relaxation and the forward
+// Euler update follow, then the moments of the new state about U^n are summed
+// across the wavefront into one partial record per (cell, chunk).
+//
+// Rows touching the immersed boundary (flag bits of rows j and j+1) take the
+// near path with the pair ghost and face values; every other row runs a
+// branch-free path whose only memory traffic is the prefetch, the stores, the
+// partial record and the next row's cell record, so loads stay in flight.
 template <typename T, int V, int TX>
 __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 {
     constexpr int W = 64 * V;
-    // row j of the tile's columns and two halo columns per side (by row
-    // parity), and the outgoing x-face state of the TX + 2 cells the faces
-    // need: f + sigma/2 where xi_x > 0, f - sigma/2 otherwise
-    __shared__ T fb[2][2][TX + 4][W];
+    constexpr int ST = (int)sizeof(T);
+    constexpr int NEARX = CF_SOLID | CF_XM | CF_XP;
+    constexpr int NEARALL = CF_SOLID | CF_XM | CF_XP | CF_YM | CF_YP;
+    __shared__ T fb[2][TX + 4][W];
     __shared__ T ob[2][TX + 2][W];
+    __shared__ double etab[32];
+    if (threadIdx.x < 32) etab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 32));
 
     const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
     const double dt = d.cfl / (d.adv + 1.0 / tmin);
@@ -676,288 +772,311 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
     const int w = uni(threadIdx.x >> 6);
     const int i = i0 + w;
     const bool col_in = i < nx;
+    const bool per = d.outer != 0;
+    const int rowb = NV * ST;
+    const size_t rstride = (size_t)nx * (size_t)rowb;
 
-    int kk[V];
-    bool act[V], pos[V];
+    // tile column -> grid column (periodic wrap); fs: the freestream row
+    auto colmap = [&](int ic, bool &fs) -> int {
+        fs = !per && (ic < 0 || ic >= nx);
+        return ic < 0 ? ic + nx : (ic >= nx ? ic - nx : ic);
+    };
+    // velocity row at row jr of a column whose row 0 starts at col (fs: the
+    // column reads the freestream row fsr)
+    auto rowp = [&](const char *col, const char *fsr, bool cfs, int jr) -> const char * {
+        const bool in = jr >= 0 && jr < ny;
+        const int jw = jr < 0 ? jr + ny : (jr >= ny ? jr - ny : jr);
+        const bool usefs = cfs || (!in && !per);
+        return usefs ? fsr : col + (size_t)(unsigned)jw * rstride;
+    };
+    auto ldflag = [&](int ic, int jr) -> int {
+        const bool in = ic >= 0 && ic < nx && jr >= 0 && jr < ny;
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(mk_rsrc(d.cflag + (in ? ic + nx * jr : 0), in ? 4 : 0), 0, 0, 0);
+    };
+    // cell record of (i, jr): parameters of the update and the flag word of
+    // the cell above
+    auto ldrec = [&](int jr, double (&P)[8], int &fup) {
+        const bool in = col_in && jr < ny;
+        const brsrc r = mk_rsrc(d.cellq + (size_t)(in ? i + nx * jr : 0) * kQWords, in ? 8 * kQWords : 0);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, 16 * m, 0, 0);
+            P[2 * m] = __builtin_bit_cast(double, u32x2{u.x, u.y});
+            P[2 * m + 1] = __builtin_bit_cast(double, u32x2{u.z, u.w});
+        }
+        fup = (int)__builtin_amdgcn_raw_buffer_load_b32(r, 64, 0, 0);
+    };
+
+    int koff[V], kk[V];
     double xx[V], xy[V], wk[V];
+    T axp[V], ayq[V], sx[V], sy[V];
+    bool pos[V], py[V];
+    const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        int k = ch * W + v * 64 + lane;
-        act[v] = k < NV;
-        kk[v] = act[v] ? k : NV - 1;
+        const int k = ch * W + v * 64 + lane;
+        kk[v] = min(k, NV - 1);
+        koff[v] = k * ST;
         xx[v] = d.xi[0][kk[v]];
         xy[v] = d.xi[1][kk[v]];
-        wk[v] = act[v] ? d.w[kk[v]] : 0.0;
+        wk[v] = k < NV ? d.w[kk[v]] : 0.0;
         pos[v] = xx[v] > 0.0;
+        py[v] = xy[v] > 0.0;
+        axp[v] = (T)fabs(xx[v]) * idx;
+        ayq[v] = (T)xy[v] * idy;
+        sx[v] = pos[v] ? T(1) : T(-1);
+        sy[v] = py[v] ? T(1) : T(-1);
     }
-    const T *fA[2] = {(const T *)d.f[cur][0], (const T *)d.f[cur][1]};
-    T *gA[2] = {(T *)d.f[cur ^ 1][0], (T *)d.f[cur ^ 1][1]};
-    const T *fsT[2] = {(const T *)d.fsT[0], (const T *)d.fsT[1]};
-    const T hdx = T(0.5);
-    const double idx = d.inv_dx[0], idy = d.inv_dx[1];
 
-    // halo columns loaded by wavefronts 0..3, halo face states made by 0..1
+    bool cfs;
+    const int ie = colmap(i, cfs);
+    // halo columns staged by wavefronts 0..3; the halo x states are made by
+    // the edge wavefronts 0 (column i0-1) and TX-1 (column i0+TX)
     const int hcol = w < 2 ? i0 - 2 + w : i0 + TX + (w - 2);
     const int hpos = w < 2 ? w : TX + 2 + (w - 2);
-    const int scol = w == 0 ? i0 - 1 : i0 + TX;
-    const int spos = w == 0 ? 0 : TX + 1;
+    const bool hload = w < 4;
+    const bool sleft = w == 0, sright = w == TX - 1;
+    const int spos = sleft ? 0 : TX + 1;
+    bool hfs;
+    const int he = colmap(hcol, hfs);
+    const char *fcol[2], *hcolp[2], *fsr[2];
+    char *gcol[2];
+#pragma unroll
+    for (int A = 0; A < 2; ++A) {
+        fcol[A] = (const char *)d.f[cur][A] + (size_t)ie * rowb;
+        hcolp[A] = (const char *)d.f[cur][A] + (size_t)he * rowb;
+        gcol[A] = (char *)d.f[cur ^ 1][A] + (size_t)ie * rowb;
+        fsr[A] = (const char *)d.fsT[A];
+    }
 
-    auto flag_row = [&](int m) -> int { return col_in ? flags_at(d, i, m) : 0; };
-    auto flag_halo = [&](int m) -> int { return flags_at(d, scol, m); };
-
-    // y slope of cell (i, m) from rows m-1, m, m+1 with ghost substitution
-    auto slope_y = [&](int A, int v, T fm, T f0, T fp, int m, int fl) -> T {
-        if (fl & CF_SOLID) return T(0);
-        if (fl & (CF_YM | CF_YP)) {
-            const int c = i + nx * m;
-            if (fl & CF_YM) fm = ghost_of<T>(d, A, c, 2, kk[v]);
-            if (fl & CF_YP) fp = ghost_of<T>(d, A, c, 3, kk[v]);
-        }
-        return vl_fast(f0 - fm, fp - f0);
-    };
-    // upwind state of the face between rows m (below) and m+1 (above)
-    auto face_y = [&](int A, int v, T fl_, T sl_, int flL, T fr_, T sr_, int flR, int m) -> T {
-        if (xy[v] > 0.0) {
-            if (!(flL & CF_SOLID)) return fl_ + hdx * sl_;
-            if (flR & CF_SOLID) return T(0);
-            return facev_of<T>(d, A, i + nx * (m + 1), 2, kk[v]);
-        }
-        if (!(flR & CF_SOLID)) return fr_ - hdx * sr_;
-        if (flL & CF_SOLID) return T(0);
-        return facev_of<T>(d, A, i + nx * m, 3, kk[v]);
-    };
-
-    // rows j-1..j+2 of the own column; the row after next, the next halo row
-    // and the next cell's equilibrium parameters are fetched one row ahead
-    T q[2][4][V], nxt[2][V], hnx[2][V];
-    double cpn[8];
-    auto fetch_cell = [&](int m) {
-        const cdbl_p cp = (cdbl_p)d.cellp + (size_t)(col_in ? i + nx * m : 0) * kCellWords;
-        cpn[0] = cp[CW_U];
-        cpn[1] = cp[CW_U + 1];
-        cpn[2] = cp[CW_A];
-        cpn[3] = cp[CW_INVT];
-        cpn[4] = cp[CW_S];
-        cpn[5] = cp[CW_S + 1];
-        cpn[6] = cp[CW_TH];
-        cpn[7] = cp[CW_INVTAU];
-    };
-    T s0[2][V], Fdn[2][V];
+    // rows in flight, selected modulo 4 by the unrolled row position
+    T R[4][2][V];
+    T OY[2][2][V], FD[2][2][V], HH[2][2][V];
+    double P[8];
+    int FL0, fup;
     {
-        T qm2[2][V];
+        T fm2[2][V], fm1[2][V];
 #pragma unroll
         for (int A = 0; A < 2; ++A) {
-            const T *r0 = row_of(d, fA[A], fsT[A], i, j0 - 2);
-            const T *r1 = row_of(d, fA[A], fsT[A], i, j0 - 1);
-            const T *r2 = row_of(d, fA[A], fsT[A], i, j0);
-            const T *r3 = row_of(d, fA[A], fsT[A], i, j0 + 1);
-            const T *rp = row_of(d, fA[A], fsT[A], i, j0 + 2);
-            const T *hp = row_of(d, fA[A], fsT[A], hcol, j0);
+            const brsrc r0 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 - 2), rowb);
+            const brsrc r1 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 - 1), rowb);
+            const brsrc r2 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0), rowb);
+            const brsrc r3 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 + 1), rowb);
+            const brsrc r4 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 + 2), rowb);
+            const brsrc rh = mk_rsrc(rowp(hcolp[A], fsr[A], hfs, j0), hload ? rowb : 0);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                qm2[A][v] = r0[kk[v]];
-                q[A][0][v] = r1[kk[v]];
-                q[A][1][v] = r2[kk[v]];
-                q[A][2][v] = r3[kk[v]];
-                nxt[A][v] = rp[kk[v]];
-                hnx[A][v] = w < 4 ? hp[kk[v]] : T(0);
+                fm2[A][v] = bld(r0, koff[v], T());
+                fm1[A][v] = bld(r1, koff[v], T());
+                R[0][A][v] = bld(r2, koff[v], T());
+                R[1][A][v] = bld(r3, koff[v], T());
+                R[2][A][v] = bld(r4, koff[v], T());
+                HH[0][A][v] = bld(rh, koff[v], T());
             }
         }
-        fetch_cell(j0);
-        const int flm1 = flag_row(j0 - 1), fl0i = flag_row(j0);
+        const int flm1 = uni(ldflag(i, j0 - 1));
+        FL0 = uni(ldflag(i, j0));
+        ldrec(j0, P, fup);
+        const int c0 = i + nx * j0;
+        // outgoing y states of rows j0-1 and j0, and the face j0-1/2
 #pragma unroll
         for (int A = 0; A < 2; ++A)
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                T sm = slope_y(A, v, qm2[A][v], q[A][0][v], q[A][1][v], j0 - 1, flm1);
-                s0[A][v] = slope_y(A, v, q[A][0][v], q[A][1][v], q[A][2][v], j0, fl0i);
-                Fdn[A][v] = face_y(A, v, q[A][0][v], sm, flm1, q[A][1][v], s0[A][v], fl0i, j0 - 1);
+                T fm = fm2[A][v], fp = R[0][A][v];
+                if (flm1 & CF_YM) fm = ghost_at<T>(d, A, c0 - nx, 2, kk[v]);
+                if (flm1 & CF_YP) fp = ghost_at<T>(d, A, c0 - nx, 3, kk[v]);
+                const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[A][v] - fm, fp - fm1[A][v]);
+                const T oym = fma(sy[v], hm, fm1[A][v]);
+                fm = fm1[A][v];
+                fp = R[1][A][v];
+                if (FL0 & CF_YM) fm = ghost_at<T>(d, A, c0, 2, kk[v]);
+                if (FL0 & CF_YP) fp = ghost_at<T>(d, A, c0, 3, kk[v]);
+                const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][A][v] - fm, fp - R[0][A][v]);
+                OY[0][A][v] = fma(sy[v], h0, R[0][A][v]);
+                T F;
+                if (py[v])
+                    F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0, 2, kk[v]));
+                else
+                    F = !(FL0 & CF_SOLID) ? OY[0][A][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0 - nx, 3, kk[v]));
+                FD[0][A][v] = F;
             }
+        __builtin_amdgcn_s_waitcnt(0);
     }
-    int fl0 = flag_row(j0);
 
-    for (int j = j0; j < j1; ++j) {
-        const int buf = (j - j0) & 1;
-        // q[A][1] is row j, q[A][2] row j+1, q[A][3] row j+2
-        T hcur[2][V];
-#pragma unroll
-        for (int A = 0; A < 2; ++A)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                q[A][3][v] = nxt[A][v];
-                hcur[A][v] = hnx[A][v];
-            }
-        // equilibrium parameters of cell (i, j), wavefront-uniform
-        const double U0 = cpn[0], U1 = cpn[1], Ac = cpn[2], invT = cpn[3];
-        const double S0 = cpn[4], S1 = cpn[5], Th = cpn[6], itau = cpn[7];
-        if (j + 1 < j1) {
-#pragma unroll
-            for (int A = 0; A < 2; ++A) {
-                const T *rp = row_of(d, fA[A], fsT[A], i, j + 3);
-#pragma unroll
-                for (int v = 0; v < V; ++v) nxt[A][v] = rp[kk[v]];
-                if (w < 4) {
-                    const T *hp = row_of(d, fA[A], fsT[A], hcol, j + 1);
-#pragma unroll
-                    for (int v = 0; v < V; ++v) hnx[A][v] = hp[kk[v]];
-                }
-            }
-            fetch_cell(j + 1);
-        }
-#pragma unroll
-        for (int A = 0; A < 2; ++A)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                fb[buf][A][w + 2][v * 64 + lane] = q[A][1][v];
-                if (w < 4) fb[buf][A][hpos][v * 64 + lane] = hcur[A][v];
-            }
-        lds_barrier();
-        // outgoing x-face states of the own cell and of the halo cell
-        T own_out[2][V];
-        {
-            const int c = i + nx * j;
-            auto run = [&](auto near_tag) {
-                constexpr bool NEAR = decltype(near_tag)::value;
-#pragma unroll
-                for (int A = 0; A < 2; ++A)
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        T fm = fb[buf][A][w + 1][v * 64 + lane];
-                        T fp = fb[buf][A][w + 3][v * 64 + lane];
-                        const T f0 = q[A][1][v];
-                        if (NEAR && (fl0 & CF_XM)) fm = ghost_of<T>(d, A, c, 0, kk[v]);
-                        if (NEAR && (fl0 & CF_XP)) fp = ghost_of<T>(d, A, c, 1, kk[v]);
-                        T s = vl_fast(f0 - fm, fp - f0);
-                        if (NEAR && (fl0 & CF_SOLID)) s = T(0);
-                        const T o = pos[v] ? f0 + hdx * s : f0 - hdx * s;
-                        own_out[A][v] = o;
-                        ob[A][w + 1][v * 64 + lane] = o;
-                    }
-            };
-            if (fl0 & (CF_SOLID | CF_XM | CF_XP))
-                run(std::true_type{});
-            else
-                run(std::false_type{});
-        }
-        if (w < 2) {
-            const int fl = flag_halo(j);
-            const int c = scol + nx * j;
-            auto run = [&](auto near_tag) {
-                constexpr bool NEAR = decltype(near_tag)::value;
-#pragma unroll
-                for (int A = 0; A < 2; ++A)
-#pragma unroll
-                    for (int v = 0; v < V; ++v) {
-                        T fm = fb[buf][A][spos][v * 64 + lane];
-                        const T f0 = fb[buf][A][spos + 1][v * 64 + lane];
-                        T fp = fb[buf][A][spos + 2][v * 64 + lane];
-                        if (NEAR && (fl & CF_XM)) fm = ghost_of<T>(d, A, c, 0, kk[v]);
-                        if (NEAR && (fl & CF_XP)) fp = ghost_of<T>(d, A, c, 1, kk[v]);
-                        T s = vl_fast(f0 - fm, fp - f0);
-                        if (NEAR && (fl & CF_SOLID)) s = T(0);
-                        ob[A][spos][v * 64 + lane] = pos[v] ? f0 + hdx * s : f0 - hdx * s;
-                    }
-            };
-            if (fl & (CF_SOLID | CF_XM | CF_XP))
-                run(std::true_type{});
-            else
-                run(std::false_type{});
-        }
-        lds_barrier();
-
-        const int flp1 = flag_row(j + 1);
+    int j = j0;
+    auto row = [&](auto S_) {
+        constexpr int S = decltype(S_)::value;
+        T(&f0)[2][V] = R[S & 3];
+        T(&f1)[2][V] = R[(S + 1) & 3];
+        T(&f2)[2][V] = R[(S + 2) & 3];
+        T(&f3)[2][V] = R[(S + 3) & 3];
+        T(&oy0)[2][V] = OY[S & 1];
+        T(&oy1)[2][V] = OY[(S + 1) & 1];
+        T(&Fdn)[2][V] = FD[S & 1];
+        T(&Fup)[2][V] = FD[(S + 1) & 1];
+        T(&hcur)[2][V] = HH[S & 1];
+        T(&hnext)[2][V] = HH[(S + 1) & 1];
         const int c = i + nx * j;
-        const bool upd = col_in && !(fl0 & CF_SOLID);
-        double mom[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        const double rate = dt * itau;
-        T *g0 = gA[0] + (size_t)c * NV, *g1 = gA[1] + (size_t)c * NV;
-        auto run = [&](auto near_tag) {
+
+        // prefetch: own column row j+3, halo column row j+1
+#pragma unroll
+        for (int A = 0; A < 2; ++A) {
+            const brsrc r3 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j + 3), rowb);
+            const brsrc rh = mk_rsrc(rowp(hcolp[A], fsr[A], hfs, j + 1), hload ? rowb : 0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                f3[A][v] = bld(r3, koff[v], T());
+                hnext[A][v] = bld(rh, koff[v], T());
+            }
+        }
+
+        // stage row j
+#pragma unroll
+        for (int A = 0; A < 2; ++A)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                fb[A][w + 2][v * 64 + lane] = f0[A][v];
+                if (hload) fb[A][hpos][v * 64 + lane] = hcur[A][v];
+            }
+        lds_barrier();
+
+        // outgoing x states of the own cell and of the halo cells
+        T ox[2][V];
+        auto xstate = [&](auto near_tag, int fl, int cc, int p0, T (&out)[2][V], bool keep) {
+            constexpr bool NEAR = decltype(near_tag)::value;
+#pragma unroll
+            for (int A = 0; A < 2; ++A)
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    T fm = fb[A][p0][v * 64 + lane];
+                    const T fc = fb[A][p0 + 1][v * 64 + lane];
+                    T fp = fb[A][p0 + 2][v * 64 + lane];
+                    if (NEAR && (fl & CF_XM)) fm = ghost_at<T>(d, A, cc, 0, kk[v]);
+                    if (NEAR && (fl & CF_XP)) fp = ghost_at<T>(d, A, cc, 1, kk[v]);
+                    T h = vl_half(fc - fm, fp - fc);
+                    if (NEAR && (fl & CF_SOLID)) h = T(0);
+                    const T o = fma(sx[v], h, fc);
+                    if (keep) out[A][v] = o;
+                    ob[A][p0][v * 64 + lane] = o;
+                }
+            // the pair loads of the near path are complete here, so the
+            // prefetch of the following rows is not waited for at the join
+            if (NEAR) __builtin_amdgcn_s_waitcnt(0);
+        };
+        if (FL0 & NEARX)
+            xstate(std::true_type{}, FL0, c, w + 1, ox, true);
+        else
+            xstate(std::false_type{}, 0, c, w + 1, ox, true);
+        if (sleft || sright) {
+            // flag word of the halo cell, from the own cell's flags
+            const int flh = sleft ? (((FL0 & CF_XM) ? CF_SOLID : 0) | ((FL0 & CF_XM2) ? CF_XM : 0) |
+                                     ((FL0 & CF_SOLID) ? CF_XP : 0))
+                                  : (((FL0 & CF_XP) ? CF_SOLID : 0) | ((FL0 & CF_SOLID) ? CF_XM : 0) |
+                                     ((FL0 & CF_XP2) ? CF_XP : 0));
+            T dummy[2][V];
+            if (flh)
+                xstate(std::true_type{}, flh, sleft ? c - 1 : c + 1, spos, dummy, false);
+            else
+                xstate(std::false_type{}, 0, 0, spos, dummy, false);
+        }
+        lds_barrier();
+
+        // y direction, fluxes, relaxation, update, moments
+        const int FL1 = uni(fup);
+        const bool upd = col_in && !(FL0 & CF_SOLID);
+        const brsrc ws0 = mk_rsrc(gcol[0] + (size_t)(unsigned)j * rstride, col_in ? rowb : 0);
+        const brsrc ws1 = mk_rsrc(gcol[1] + (size_t)(unsigned)j * rstride, col_in ? rowb : 0);
+        const double U0 = P[0], U1 = P[1], invT = P[3], S0 = P[4], S1 = P[5];
+        const double rate = dt * P[7];
+        const double Ar = rate * P[2], ThAr = P[6] * Ar, c1 = 1.0 - rate;
+        double m[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m[q] = 0.0;
+        auto body = [&](auto near_tag) {
             constexpr bool NEAR = decltype(near_tag)::value;
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                T s1[2];
-                T Fup[2];
+                T div[2];
 #pragma unroll
                 for (int A = 0; A < 2; ++A) {
+                    T fm = f0[A][v], fp = f2[A][v];
+                    if (NEAR && (FL1 & CF_YM)) fm = ghost_at<T>(d, A, c + nx, 2, kk[v]);
+                    if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T>(d, A, c + nx, 3, kk[v]);
+                    T h1 = vl_half(f1[A][v] - fm, fp - f1[A][v]);
+                    if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
+                    oy1[A][v] = fma(sy[v], h1, f1[A][v]);
+                    T F = py[v] ? oy0[A][v] : oy1[A][v];
                     if (NEAR) {
-                        s1[A] = slope_y(A, v, q[A][1][v], q[A][2][v], q[A][3][v], j + 1, flp1);
-                        Fup[A] = face_y(A, v, q[A][1][v], s0[A][v], fl0, q[A][2][v], s1[A], flp1, j);
-                    } else {
-                        const T fm = q[A][1][v], f0 = q[A][2][v], fp = q[A][3][v];
-                        s1[A] = vl_fast(f0 - fm, fp - f0);
-                        Fup[A] = xy[v] > 0.0 ? fm + hdx * s0[A][v] : f0 - hdx * s1[A];
-                    }
-                }
-                if (upd) {
-                    const double cx = xx[v] - U0, cy = xy[v] - U1;
-                    const double c2 = cx * cx + cy * cy, cs = cx * S0 + cy * S1;
-                    const double H = Ac * exp(-c2 * invT);
-                    const double gS[2] = {H * (1.0 + cs * (2.0 * c2 * invT - 4.0)),
-                                          Th * H * (1.0 + cs * (2.0 * c2 * invT - 2.0))};
-                    double fnew[2];
-#pragma unroll
-                    for (int A = 0; A < 2; ++A) {
-                        const T f0 = q[A][1][v];
-                        // the neighbour's outgoing state is the face state on the upwind side
-                        const T nb = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
-                        T Fr, Fl;
-                        if (pos[v]) {
-                            Fr = own_out[A][v];
-                            Fl = (NEAR && (fl0 & CF_XM)) ? facev_of<T>(d, A, c, 0, kk[v]) : nb;
+                        if (py[v]) {
+                            if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c + nx, 2, kk[v]);
                         } else {
-                            Fl = own_out[A][v];
-                            Fr = (NEAR && (fl0 & CF_XP)) ? facev_of<T>(d, A, c, 1, kk[v]) : nb;
+                            if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c, 3, kk[v]);
                         }
-                        const T div = (T)xx[v] * (Fr - Fl) * (T)idx + (T)xy[v] * (Fup[A] - Fdn[A][v]) * (T)idy;
-                        const double fo = (double)f0;
-                        const T st = (T)(fo - dt * (double)div + rate * (gS[A] - fo));
-                        if (act[v]) (A == 0 ? g0 : g1)[kk[v]] = st;
-                        fnew[A] = act[v] ? (double)st : 0.0;
                     }
-                    const double wh = wk[v] * fnew[0], wE = wk[v] * (c2 * fnew[0] + fnew[1]);
-                    const double tx_ = cx * wh, ty_ = cy * wh;
-                    mom[0] += wh;
-                    mom[1] += tx_;
-                    mom[2] += ty_;
-                    mom[3] += wE;
-                    mom[4] += cx * wE;
-                    mom[5] += cy * wE;
-                    mom[6] += cx * tx_;
-                    mom[7] += cy * tx_;
-                    mom[8] += cy * ty_;
-                } else if (col_in && act[v]) {
+                    Fup[A][v] = F;
+                    // the upwind neighbour's outgoing state is the face state on the upwind side
+                    T nbs = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
+                    if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T>(d, A, c, 0, kk[v]);
+                    if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T>(d, A, c, 1, kk[v]);
+                    div[A] = fma(axp[v], ox[A][v] - nbs, ayq[v] * (F - Fdn[A][v]));
+                }
+                if (NEAR && !upd) {
                     // solid cells are not advanced; carry their value
-                    g0[kk[v]] = q[0][1][v];
-                    g1[kk[v]] = q[1][1][v];
+                    bst(ws0, koff[v], f0[0][v]);
+                    bst(ws1, koff[v], f0[1][v]);
+                    continue;
                 }
-#pragma unroll
-                for (int A = 0; A < 2; ++A) {
-                    Fdn[A][v] = Fup[A];
-                    s0[A][v] = s1[A];
-                }
+                const double cx = xx[v] - U0, cy = xy[v] - U1;
+                const double c2 = fma(cy, cy, cx * cx), cs = fma(cy, S1, cx * S0);
+                const double a = c2 * invT;
+                const double e = exp_neg(-a, etab);
+                const double t0 = fma(a, 2.0, -4.0);
+                const double g0 = (Ar * e) * fma(cs, t0, 1.0);
+                const double g1 = (ThAr * e) * fma(cs, t0 + 2.0, 1.0);
+                const T st0 = (T)fma(-dt, (double)div[0], fma(c1, (double)f0[0][v], g0));
+                const T st1 = (T)fma(-dt, (double)div[1], fma(c1, (double)f0[1][v], g1));
+                bst(ws0, koff[v], st0);
+                bst(ws1, koff[v], st1);
+                const double n0 = (double)st0, n1 = (double)st1;
+                const double wh = wk[v] * n0, wE = wk[v] * fma(c2, n0, n1);
+                const double tx_ = cx * wh, ty_ = cy * wh;
+                m[0] += wh;
+                m[1] += tx_;
+                m[2] += ty_;
+                m[3] += wE;
+                m[4] = fma(cx, wE, m[4]);
+                m[5] = fma(cy, wE, m[5]);
+                m[6] = fma(cx, tx_, m[6]);
+                m[7] = fma(cy, tx_, m[7]);
+                m[8] = fma(cy, ty_, m[8]);
             }
+            if (NEAR) __builtin_amdgcn_s_waitcnt(0);
         };
-        if ((fl0 | flp1) & (CF_SOLID | CF_XM | CF_XP | CF_YM | CF_YP))
-            run(std::true_type{});
+        if ((FL0 | FL1) & NEARALL)
+            body(std::true_type{});
         else
-            run(std::false_type{});
-        if (upd) {
-            // partial record: m0, m1x, m1y, m2, m3x, m3y, Mxx, Mxy, Myy
-            double r8, s8;
-            reduce9(mom, r8, s8);
-            double *pp = d.part + ((size_t)c * ncv + ch) * kPartialStride;
-            if ((lane & 7) == 0) pp[lane >> 3] = r8;
-            if (lane == 1) pp[8] = s8;
-        }
-        fl0 = flp1;
-#pragma unroll
-        for (int A = 0; A < 2; ++A)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                q[A][0][v] = q[A][1][v];
-                q[A][1][v] = q[A][2][v];
-                q[A][2][v] = q[A][3][v];
-            }
+            body(std::false_type{});
+        // cell record of the next row
+        ldrec(j + 1, P, fup);
+        // partial record: m0, m1x, m1y, m2, m3x, m3y, Mxx, Mxy, Myy
+        double r8, s8;
+        reduce9(m, r8, s8);
+        const brsrc rp = mk_rsrc(d.part + ((size_t)c * ncv + ch) * kPartialStride, upd ? 72 : 0);
+        bst(rp, (lane & 7) == 7 ? (lane >> 3) * 8 : kOob, r8);
+        bst(rp, lane == 15 ? 64 : kOob, s8);
+        FL0 = FL1;
+    };
+
+    for (;;) {
+        row(std::integral_constant<int, 0>{});
+        if (++j >= j1) break;
+        row(std::integral_constant<int, 1>{});
+        if (++j >= j1) break;
+        row(std::integral_constant<int, 2>{});
+        if (++j >= j1) break;
+        row(std::integral_constant<int, 3>{});
+        if (++j >= j1) break;
     }
 }
 
@@ -1104,7 +1223,7 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     if (storage == 0) {
         U2D(double, 1, 4) U2D(double, 1, 8) U2D(double, 2, 4) U2D(double, 2, 8)
     } else {
-        U2D(float, 1, 4) U2D(float, 1, 8) U2D(float, 2, 4) U2D(float, 2, 8) U2D(float, 4, 4) U2D(float, 4, 8)
+        U2D(float, 1, 4) U2D(float, 1, 8) U2D(float, 2, 4) U2D(float, 2, 8)
     }
 #undef U2D
     return hipErrorInvalidValue;

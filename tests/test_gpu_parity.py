@@ -244,7 +244,7 @@ def test_full_size_cylinder_step(oracle_mod, torch_cuda):
 
 
 TILES64 = [(1, 4, 32), (1, 8, 64), (2, 4, 16), (2, 8, 64), (1, 8, 7)]
-TILES32 = [(1, 8, 64), (2, 4, 32), (4, 8, 64), (4, 4, 5)]
+TILES32 = [(1, 8, 64), (2, 4, 32), (2, 8, 5), (1, 4, 3)]
 
 
 @pytest.mark.parametrize("precision,tile", [("f64", t) for t in TILES64] + [("f32", t) for t in TILES32])
