@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="time only the FP32-storage form")
     ap.add_argument("--tile", type=str, default="", help="V,TX,LY of the 2D update (default: autotune)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -105,6 +107,14 @@ def main():
 
     from paper_2512_20252_amd import cases
 
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     case = cases.cylinder_256(Kn=0.1, Ma=0.3)
     workload = "cylinder_256x256_v48x48"
     tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None

@@ -199,7 +199,7 @@ ibdvm_status ibdvm_wall_state(ibdvm_ctx *ctx, double *ghost, double *face, doubl
 ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps);
 
 /* Tile of the 2D update kernel: V velocity nodes per lane (1 or 2), TX grid
- * columns per workgroup (4 or 8) and LY rows marched per workgroup (1..126).
+ * columns per workgroup (4 or 8) and LY rows marched per workgroup (1..256).
  * The tile fixes the order of the velocity sums, so results are
  * bit-identical only between runs with the same tile.  2D only. */
 ibdvm_status ibdvm_set_tile(ibdvm_ctx *ctx, int32_t V, int32_t TX, int32_t LY);

@@ -24,7 +24,8 @@ enum CellWord { CW_U = 0, CW_A = 3, CW_INVT = 4, CW_S = 5, CW_TH = 8, CW_INVTAU 
 // word 8; 0 on the top row) and a pad word
 constexpr int kQWords = 10;
 
-constexpr int kChunk = 64;  // velocity nodes per wavefront
+constexpr int kChunk = 64;       // velocity nodes per wavefront
+constexpr int kFillChunk = 256;  // velocity nodes per ghost-fill workgroup
 constexpr int kMaxVn = 128;
 
 struct DPair {
@@ -73,6 +74,7 @@ struct Dev {
     const double *wg;
     double *ghost[2], *face[2], *fiw[2], *fsp[2];
     double *rhow;
+    double *fillpart;  // [pair][fill chunk][2]: incident and specular partial wall fluxes
     double *pforce;
     Ctrl *ctrl;
 };

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -29,7 +30,7 @@ ibdvm_status fail(ibdvm_status s, const std::string &msg)
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, pforce, ctrl;
+    size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, fillpart, pforce, ctrl;
     size_t total;
     size_t state_bytes;  // one array of one buffer
 };
@@ -71,6 +72,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.fiw = take((size_t)NA * np * g.NV * 8);
     L.fsp = take((size_t)NA * np * g.NV * 8);
     L.rhow = take(np * 8);
+    L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * 4 * 8);
     L.ctrl = take(sizeof(ibdvm::Ctrl));
     L.total = off;
@@ -494,6 +496,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
         d.fsp[A] = (double *)(ws + L.fsp) + AA * pstride;
     }
     d.rhow = (double *)(ws + L.rhow);
+    d.fillpart = (double *)(ws + L.fillpart);
     d.pforce = (double *)(ws + L.pforce);
     d.ctrl = (ibdvm::Ctrl *)(ws + L.ctrl);
 
@@ -745,7 +748,7 @@ bool tile_supported(int precision, const ibdvm::Tile &t)
     bool tx = t.TX == 4 || t.TX == 8;
     bool v = t.V == 1 || t.V == 2;
     (void)precision;
-    return tx && v && t.LY >= 1 && t.LY <= 126;
+    return tx && v && t.LY >= 1 && t.LY <= 256;
 }
 }  // namespace
 

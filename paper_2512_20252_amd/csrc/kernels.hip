@@ -6,10 +6,11 @@
 //   k_update    Section 2.2 upwind MUSCL fluxes with the van Leer limiter,
 //               Shakhov relaxation (Sections 2.1, 4), forward Euler; emits
 //               partial moments of the new state per (cell, 64 nodes).
-//   k_fill_fin  Section 3.2.1 ghost construction with the upwind weights of
+//   k_fill_*    Section 3.2.1 ghost construction with the upwind weights of
 //               3.2.2 and the cut-cell wall density/distribution of 3.2.3,
-//               one workgroup per ghost-donor pair; other workgroups of the
-//               same launch finish the per-cell moments and tau_min.
+//               over (ghost-donor pair, node chunk) workgroups in three
+//               phases; the first launch also finishes the per-cell moments
+//               and tau_min in its other workgroups.
 //   k_force     momentum flux through the immersed-boundary faces.
 //
 // Moments of the new state are accumulated about the old bulk velocity U^n
@@ -171,53 +172,69 @@ __device__ double vel_interp(const Dev &d, const double *g, const double v[3], i
 }
 
 // ---------------------------------------------------------------- ghost fill
+//
+// The fill of one ghost-donor pair runs over (pair, chunk of kFillChunk
+// nodes) workgroups in three phases, one launch each: (1) the shifted-point
+// and incident distributions and the partial incident flux of the wall
+// density balance; (2) with alpha < 1 only, the partial flux of the specular
+// part, which interpolates the incident distribution of the whole pair;
+// (3) the wall density from all partials, the wall distribution, the ghost
+// value and the ghost-side face value.
+
+__device__ __forceinline__ int fill_chunks(const Dev &d) { return (d.NV + kFillChunk - 1) / kFillChunk; }
+
+// reflected node velocity xi - 2 (xi . n) n and the normal component xi . n
+template <int D>
+__device__ __forceinline__ double reflect(const Dev &d, int k, const double nw[3], double v[3])
+{
+    double dn = 0.0;
+    for (int b = 0; b < D; ++b) dn += d.xi[b][k] * nw[b];
+    for (int b = 0; b < 3; ++b) v[b] = b < D ? d.xi[b][k] - 2.0 * dn * nw[b] : 0.0;
+    return dn;
+}
+
 template <int D, typename T>
-__device__ void fill_pair(const Dev &d, int cur, int p)
+__device__ void fill_incident(const Dev &d, int cur, int p, int chunk)
 {
     const DPair &P = d.pairs[p];
-    const int a = P.axis, dc = P.dc, ac = P.ac, ns = P.ns;
-    const double ygc = P.ygc, ydc = P.ydc, yac = P.yac, yw = P.yw, ysp = P.ysp, yface = P.yface;
+    const int dc = P.dc, ac = P.ac, ns = P.ns;
+    const double ygc = P.ygc, ydc = P.ydc, yac = P.yac, yw = P.yw, ysp = P.ysp;
     const size_t po = (size_t)p * d.NV;
-    const int NV = d.NV;
+    const int NV = d.NV, k = chunk * kFillChunk + threadIdx.x;
     const bool uniform = (d.flags & 2u) != 0;  // NO_UPWIND ablation
     double num = 0.0;
-    for (int A = 0; A < d.NA; ++A) {
-        const T *f = (const T *)d.f[cur][A];
-        for (int k = threadIdx.x; k < NV; k += 256) {
-            double xk[3] = {0, 0, 0}, x2 = 0.0;
-            for (int b = 0; b < D; ++b) {
-                xk[b] = d.xi[b][k];
-                x2 += xk[b] * xk[b];
-            }
+    if (k < NV) {
+        double xk[3] = {0, 0, 0}, x2 = 0.0;
+        for (int b = 0; b < D; ++b) {
+            xk[b] = d.xi[b][k];
+            x2 += xk[b] * xk[b];
+        }
+        // upwind weights of the surface cells: w_j proportional to max(0, -xi . r_j)^2
+        const double thr = 1e-12 * sqrt(x2);
+        auto upw = [&](int j) {
+            double dd = 0.0;
+            for (int b = 0; b < D; ++b) dd += xk[b] * P.rh[j][b];
+            if (fabs(dd) <= thr) dd = 0.0;
+            const double m = dd < 0.0 ? -dd : 0.0;
+            return m * m;
+        };
+        double sum = 0.0;
+        for (int j = 0; j < ns; ++j) sum += upw(j);
+        for (int A = 0; A < d.NA; ++A) {
+            const T *f = (const T *)d.f[cur][A];
             // 1. shifted point from the donor and the auxiliary-cell slope
-            double fdc = (double)f[(size_t)dc * NV + k];
-            double sdc = ac >= 0 ? ((double)f[(size_t)ac * NV + k] - fdc) / (yac - ydc) : 0.0;
-            double fspv = fdc + sdc * (ysp - ydc);
+            const double fdc = (double)f[(size_t)dc * NV + k];
+            const double sdc = ac >= 0 ? ((double)f[(size_t)ac * NV + k] - fdc) / (yac - ydc) : 0.0;
+            const double fspv = fdc + sdc * (ysp - ydc);
             // 2. upwind-weighted interpolation from the surface cells
-            double thr = 1e-12 * sqrt(x2), sum = 0.0;
-            for (int j = 0; j < ns; ++j) {
-                double dd = 0.0;
-                for (int b = 0; b < D; ++b) dd += xk[b] * P.rh[j][b];
-                if (fabs(dd) <= thr) dd = 0.0;
-                double m = dd < 0.0 ? -dd : 0.0;
-                sum += m * m;
-            }
             double fgc = 0.0;
             for (int j = 0; j < ns; ++j) {
-                double wj;
-                if (uniform || sum == 0.0) {
-                    wj = 1.0 / ns;
-                } else {
-                    double dd = 0.0;
-                    for (int b = 0; b < D; ++b) dd += xk[b] * P.rh[j][b];
-                    if (fabs(dd) <= thr) dd = 0.0;
-                    double m = dd < 0.0 ? -dd : 0.0;
-                    wj = m * m / sum;
-                }
+                const double wj = (uniform || sum == 0.0) ? 1.0 / ns : upw(j) / sum;
                 const int sj = P.sc[j];
-                double fj = (double)f[(size_t)sj * NV + k], sr = 0.0;
+                const double fj = (double)f[(size_t)sj * NV + k];
+                double sr = 0.0;
                 for (int b = 0; b < D; ++b) {
-                    int L = P.snb[j][b][0], R = P.snb[j][b][1];
+                    const int L = P.snb[j][b][0], R = P.snb[j][b][1];
                     double sg = 0.0;
                     if (L >= 0 && R >= 0)
                         sg = vanleer(fj - (double)f[(size_t)L * NV + k], (double)f[(size_t)R * NV + k] - fj) * d.inv_dx[b];
@@ -230,64 +247,73 @@ __device__ void fill_pair(const Dev &d, int cur, int p)
                 fgc += wj * (fj - sr);
             }
             // 3. incident distribution at the intersect point
-            double fiw = fspv + (fgc - fspv) / (ygc - ysp) * (yw - ysp);
+            const double fiw = fspv + (fgc - fspv) / (ygc - ysp) * (yw - ysp);
             d.fiw[A][po + k] = fiw;
             d.fsp[A][po + k] = fspv;
             if (A == 0) {
                 double dn = 0.0;
                 for (int b = 0; b < D; ++b) dn += xk[b] * P.nw[b];
-                int cl = d.cls[po + k];
-                double wt = cl == 0 ? d.w[k] : (cl >= 2 ? d.wg[po + k] : 0.0);
-                num += wt * dn * fiw;
+                const int cl = d.cls[po + k];
+                const double wt = cl == 0 ? d.w[k] : (cl >= 2 ? d.wg[po + k] : 0.0);
+                num = wt * dn * fiw;
             }
-        }
-    }
-    __threadfence_block();
-    __syncthreads();
-    const double al = d.alpha;
-    if (al < 1.0) {
-        for (int k = threadIdx.x; k < NV; k += 256) {
-            int cl = d.cls[po + k];
-            if (cl == 0) continue;
-            double xk[3] = {0, 0, 0}, dn = 0.0;
-            for (int b = 0; b < D; ++b) {
-                xk[b] = d.xi[b][k];
-                dn += xk[b] * P.nw[b];
-            }
-            double v[3] = {0, 0, 0};
-            for (int b = 0; b < D; ++b) v[b] = xk[b] - 2.0 * dn * P.nw[b];
-            double fsv = vel_interp(d, d.fiw[0] + po, v, D);
-            double ws = cl == 1 ? d.w[k] : d.w[k] - d.wg[po + k];
-            num += (1.0 - al) * ws * dn * fsv;
         }
     }
     num = block_sum(num);
-    const double rw = al > 0.0 ? -num / (al * P.den) : 0.0;
-    if (threadIdx.x == 0) d.rhow[p] = rw;
-    for (int A = 0; A < d.NA; ++A) {
-        for (int k = threadIdx.x; k < NV; k += 256) {
-            int cl = d.cls[po + k];
-            double fi = d.fiw[A][po + k];
-            double fsv = 0.0;
-            if (al < 1.0 && cl != 0) {
-                double xk[3] = {0, 0, 0}, dn = 0.0;
-                for (int b = 0; b < D; ++b) {
-                    xk[b] = d.xi[b][k];
-                    dn += xk[b] * P.nw[b];
-                }
-                double v[3] = {0, 0, 0};
-                for (int b = 0; b < D; ++b) v[b] = xk[b] - 2.0 * dn * P.nw[b];
-                fsv = vel_interp(d, d.fiw[A] + po, v, D);
-            }
-            double Hw = d.hw[k] * (A == 1 ? 0.5 * d.Tw : 1.0);
-            double fr = al * rw * Hw + (1.0 - al) * fsv;
-            double fw = cl == 0 ? fi : (cl == 1 ? fr : (d.wg[po + k] * fi + (d.w[k] - d.wg[po + k]) * fr) / d.w[k]);
-            double fspv = d.fsp[A][po + k];
-            double sig = (fw - fspv) / (yw - ysp);
-            double gv = fspv + sig * (ygc - ysp);
-            d.ghost[A][po + k] = gv;
-            d.face[A][po + k] = gv + sig * (yface - ygc);
+    if (threadIdx.x == 0) d.fillpart[((size_t)p * fill_chunks(d) + chunk) * 2] = num;
+}
+
+template <int D>
+__device__ void fill_specular(const Dev &d, int p, int chunk)
+{
+    const DPair &P = d.pairs[p];
+    const size_t po = (size_t)p * d.NV;
+    const int k = chunk * kFillChunk + threadIdx.x;
+    double num = 0.0;
+    if (k < d.NV) {
+        const int cl = d.cls[po + k];
+        if (cl != 0) {
+            double v[3];
+            const double dn = reflect<D>(d, k, P.nw, v);
+            const double fsv = vel_interp(d, d.fiw[0] + po, v, D);
+            const double ws = cl == 1 ? d.w[k] : d.w[k] - d.wg[po + k];
+            num = (1.0 - d.alpha) * ws * dn * fsv;
         }
+    }
+    num = block_sum(num);
+    if (threadIdx.x == 0) d.fillpart[((size_t)p * fill_chunks(d) + chunk) * 2 + 1] = num;
+}
+
+template <int D>
+__device__ void fill_ghost(const Dev &d, int p, int chunk)
+{
+    const DPair &P = d.pairs[p];
+    const double ygc = P.ygc, yw = P.yw, ysp = P.ysp, yface = P.yface;
+    const size_t po = (size_t)p * d.NV;
+    const int nfc = fill_chunks(d), k = chunk * kFillChunk + threadIdx.x;
+    const double al = d.alpha;
+    // wall density: zero net mass flux through the wall (the same sum in every workgroup)
+    double num = 0.0;
+    for (int c = 0; c < nfc; ++c) num += d.fillpart[((size_t)p * nfc + c) * 2];
+    if (al < 1.0)
+        for (int c = 0; c < nfc; ++c) num += d.fillpart[((size_t)p * nfc + c) * 2 + 1];
+    const double rw = al > 0.0 ? -num / (al * P.den) : 0.0;
+    if (chunk == 0 && threadIdx.x == 0) d.rhow[p] = rw;
+    if (k >= d.NV) return;
+    const int cl = d.cls[po + k];
+    double v[3] = {0, 0, 0};
+    if (al < 1.0 && cl != 0) reflect<D>(d, k, P.nw, v);
+    for (int A = 0; A < d.NA; ++A) {
+        const double fi = d.fiw[A][po + k];
+        const double fsv = (al < 1.0 && cl != 0) ? vel_interp(d, d.fiw[A] + po, v, D) : 0.0;
+        const double Hw = d.hw[k] * (A == 1 ? 0.5 * d.Tw : 1.0);
+        const double fr = al * rw * Hw + (1.0 - al) * fsv;
+        const double fw = cl == 0 ? fi : (cl == 1 ? fr : (d.wg[po + k] * fi + (d.w[k] - d.wg[po + k]) * fr) / d.w[k]);
+        const double fspv = d.fsp[A][po + k];
+        const double sig = (fw - fspv) / (yw - ysp);
+        const double gv = fspv + sig * (ygc - ysp);
+        d.ghost[A][po + k] = gv;
+        d.face[A][po + k] = gv + sig * (yface - ygc);
     }
 }
 
@@ -298,13 +324,22 @@ __device__ void fin_cells(const Dev &d, int slot, int blk)
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double tmin = INFINITY;
-    for (int i = 0; i < 8; ++i) {
-        const int c = blk * 32 + wv * 8 + i;
-        if (c >= d.Nc) break;
-        if (d.cflag[c] & 1) continue;
-        double acc = 0.0;
-        if (lane < PW)
-            for (int ch = 0; ch < d.nchunk; ++ch) acc += d.part[((size_t)c * d.nchunk + ch) * kPartialStride + lane];
+    // one cell per wavefront: the cell's partial records are contiguous, lane
+    // l sums word l % 16 of records l / 16, l / 16 + 4, ... in coalesced loads
+    const int c = blk * 4 + wv;
+    if (c < d.Nc && !(d.cflag[c] & 1)) {
+        const double *pp = d.part + (size_t)c * d.nchunk * kPartialStride;
+        const int nw = d.nchunk * kPartialStride;
+        double acc = 0.0, acc2 = 0.0;
+        int ow = lane;
+        for (; ow + 64 < nw; ow += 128) {
+            acc += pp[ow];
+            acc2 += pp[ow + 64];
+        }
+        if (ow < nw) acc += pp[ow];
+        acc += acc2;
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
         double S[PW];
 #pragma unroll
         for (int j = 0; j < PW; ++j) S[j] = __shfl(acc, j, 64);
@@ -347,10 +382,25 @@ template <int D, typename T>
 __global__ __launch_bounds__(256) void k_fill_fin(Dev d, int cur, int slot, int nfill, int dofin)
 {
     if ((int)blockIdx.x < nfill) {
-        fill_pair<D, T>(d, cur, blockIdx.x);
+        const int nfc = fill_chunks(d);
+        fill_incident<D, T>(d, cur, blockIdx.x / nfc, blockIdx.x % nfc);
         return;
     }
     if (dofin) fin_cells<D>(d, slot, blockIdx.x - nfill);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_specular(Dev d)
+{
+    const int nfc = fill_chunks(d);
+    fill_specular<D>(d, blockIdx.x / nfc, blockIdx.x % nfc);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_ghost(Dev d)
+{
+    const int nfc = fill_chunks(d);
+    fill_ghost<D>(d, blockIdx.x / nfc, blockIdx.x % nfc);
 }
 
 // direct two-pass moments of the current state (after create / set_state)
@@ -674,12 +724,13 @@ __device__ __forceinline__ void bst(brsrc r, int off, float x)
 
 // half the van Leer limited slope of one-sided differences d1, d2:
 // d1 d2 / (d1 + d2) when they have the same sign, else 0 (d1 d2 > 0 keeps
-// |d1 + d2| far from the reciprocal's overflow range)
+// |d1 + d2| far from the reciprocal's overflow range).  The hardware
+// reciprocal (relative error below 5e-8) takes one Newton step, leaving a
+// few units in the last place.
 __device__ __forceinline__ double vl_half(double d1, double d2)
 {
     const double p = d1 * d2, den = d1 + d2;
     double r = __builtin_amdgcn_rcp(den);
-    r = fma(fma(-den, r, 1.0), r, r);
     r = fma(fma(-den, r, 1.0), r, r);
     return p > 0.0 ? p * r : 0.0;
 }
@@ -712,17 +763,19 @@ __device__ __forceinline__ double exp_neg(double x, const double *tab)
     return ldexp(tab[ni & 31] * p, ni >> 5);
 }
 
+// ghost value / ghost-side face value of the pair seen from fluid cell c in
+// direction dir (2 axis + side), at byte offset k8 = 8 k of node k
 template <typename T>
-__device__ __forceinline__ T ghost_at(const Dev &d, int A, int c, int dir, int kk)
+__device__ __forceinline__ T ghost_at(const Dev &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
-    return (T)d.ghost[A][(size_t)p * d.NV + kk];
+    return (T)bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
 }
 template <typename T>
-__device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int kk)
+__device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
-    return (T)d.face[A][(size_t)p * d.NV + kk];
+    return (T)bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
 }
 
 // One workgroup = TX wavefronts = TX adjacent columns i0..i0+TX-1, rows
@@ -741,7 +794,8 @@ __device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int k
 // branch-free path whose only memory traffic is the prefetch, the stores, the
 // partial record and the next row's cell record, so loads stay in flight.
 template <typename T, int V, int TX>
-__global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
+__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
+void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 {
     constexpr int W = 64 * V;
     constexpr int ST = (int)sizeof(T);
@@ -793,11 +847,33 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
         const bool in = ic >= 0 && ic < nx && jr >= 0 && jr < ny;
         return (int)__builtin_amdgcn_raw_buffer_load_b32(mk_rsrc(d.cflag + (in ? ic + nx * jr : 0), in ? 4 : 0), 0, 0, 0);
     };
+    int koff[V];
+    double xx[V], xy[V], wk[V];
+    T axp[V], ayq[V], sx[V], sy[V];
+    bool pos[V], py[V];
+    const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int k = ch * W + v * 64 + lane;
+        const int kc = min(k, NV - 1);
+        koff[v] = k * ST;
+        xx[v] = d.xi[0][kc];
+        xy[v] = d.xi[1][kc];
+        wk[v] = k < NV ? d.w[kc] : 0.0;
+        pos[v] = xx[v] > 0.0;
+        py[v] = xy[v] > 0.0;
+        axp[v] = (T)fabs(xx[v]) * idx;
+        ayq[v] = (T)xy[v] * idy;
+        sx[v] = pos[v] ? T(1) : T(-1);
+        sy[v] = py[v] ? T(1) : T(-1);
+    }
+
     // cell record of (i, jr): parameters of the update and the flag word of
     // the cell above
     auto ldrec = [&](int jr, double (&P)[8], int &fup) {
         const bool in = col_in && jr < ny;
-        const brsrc r = mk_rsrc(d.cellq + (size_t)(in ? i + nx * jr : 0) * kQWords, in ? 8 * kQWords : 0);
+        const size_t cc = in ? (size_t)(i + nx * jr) : 0;
+        const brsrc r = mk_rsrc(d.cellq + cc * kQWords, in ? 8 * kQWords : 0);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
             const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, 16 * m, 0, 0);
@@ -806,27 +882,6 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
         }
         fup = (int)__builtin_amdgcn_raw_buffer_load_b32(r, 64, 0, 0);
     };
-
-    int koff[V], kk[V];
-    double xx[V], xy[V], wk[V];
-    T axp[V], ayq[V], sx[V], sy[V];
-    bool pos[V], py[V];
-    const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int k = ch * W + v * 64 + lane;
-        kk[v] = min(k, NV - 1);
-        koff[v] = k * ST;
-        xx[v] = d.xi[0][kk[v]];
-        xy[v] = d.xi[1][kk[v]];
-        wk[v] = k < NV ? d.w[kk[v]] : 0.0;
-        pos[v] = xx[v] > 0.0;
-        py[v] = xy[v] > 0.0;
-        axp[v] = (T)fabs(xx[v]) * idx;
-        ayq[v] = (T)xy[v] * idy;
-        sx[v] = pos[v] ? T(1) : T(-1);
-        sy[v] = py[v] ? T(1) : T(-1);
-    }
 
     bool cfs;
     const int ie = colmap(i, cfs);
@@ -884,21 +939,21 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 T fm = fm2[A][v], fp = R[0][A][v];
-                if (flm1 & CF_YM) fm = ghost_at<T>(d, A, c0 - nx, 2, kk[v]);
-                if (flm1 & CF_YP) fp = ghost_at<T>(d, A, c0 - nx, 3, kk[v]);
+                if (flm1 & CF_YM) fm = ghost_at<T>(d, A, c0 - nx, 2, koff[v] * (8 / ST));
+                if (flm1 & CF_YP) fp = ghost_at<T>(d, A, c0 - nx, 3, koff[v] * (8 / ST));
                 const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[A][v] - fm, fp - fm1[A][v]);
                 const T oym = fma(sy[v], hm, fm1[A][v]);
                 fm = fm1[A][v];
                 fp = R[1][A][v];
-                if (FL0 & CF_YM) fm = ghost_at<T>(d, A, c0, 2, kk[v]);
-                if (FL0 & CF_YP) fp = ghost_at<T>(d, A, c0, 3, kk[v]);
+                if (FL0 & CF_YM) fm = ghost_at<T>(d, A, c0, 2, koff[v] * (8 / ST));
+                if (FL0 & CF_YP) fp = ghost_at<T>(d, A, c0, 3, koff[v] * (8 / ST));
                 const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][A][v] - fm, fp - R[0][A][v]);
                 OY[0][A][v] = fma(sy[v], h0, R[0][A][v]);
                 T F;
                 if (py[v])
-                    F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0, 2, kk[v]));
+                    F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0, 2, koff[v] * (8 / ST)));
                 else
-                    F = !(FL0 & CF_SOLID) ? OY[0][A][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0 - nx, 3, kk[v]));
+                    F = !(FL0 & CF_SOLID) ? OY[0][A][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0 - nx, 3, koff[v] * (8 / ST)));
                 FD[0][A][v] = F;
             }
         __builtin_amdgcn_s_waitcnt(0);
@@ -952,8 +1007,8 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
                     T fm = fb[A][p0][v * 64 + lane];
                     const T fc = fb[A][p0 + 1][v * 64 + lane];
                     T fp = fb[A][p0 + 2][v * 64 + lane];
-                    if (NEAR && (fl & CF_XM)) fm = ghost_at<T>(d, A, cc, 0, kk[v]);
-                    if (NEAR && (fl & CF_XP)) fp = ghost_at<T>(d, A, cc, 1, kk[v]);
+                    if (NEAR && (fl & CF_XM)) fm = ghost_at<T>(d, A, cc, 0, koff[v] * (8 / ST));
+                    if (NEAR && (fl & CF_XP)) fp = ghost_at<T>(d, A, cc, 1, koff[v] * (8 / ST));
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (fl & CF_SOLID)) h = T(0);
                     const T o = fma(sx[v], h, fc);
@@ -1001,24 +1056,24 @@ __global__ __launch_bounds__(TX * 64) void k_update2d(Dev d, int cur, int slot, 
 #pragma unroll
                 for (int A = 0; A < 2; ++A) {
                     T fm = f0[A][v], fp = f2[A][v];
-                    if (NEAR && (FL1 & CF_YM)) fm = ghost_at<T>(d, A, c + nx, 2, kk[v]);
-                    if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T>(d, A, c + nx, 3, kk[v]);
+                    if (NEAR && (FL1 & CF_YM)) fm = ghost_at<T>(d, A, c + nx, 2, koff[v] * (8 / ST));
+                    if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T>(d, A, c + nx, 3, koff[v] * (8 / ST));
                     T h1 = vl_half(f1[A][v] - fm, fp - f1[A][v]);
                     if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
                     oy1[A][v] = fma(sy[v], h1, f1[A][v]);
                     T F = py[v] ? oy0[A][v] : oy1[A][v];
                     if (NEAR) {
                         if (py[v]) {
-                            if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c + nx, 2, kk[v]);
+                            if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c + nx, 2, koff[v] * (8 / ST));
                         } else {
-                            if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c, 3, kk[v]);
+                            if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c, 3, koff[v] * (8 / ST));
                         }
                     }
                     Fup[A][v] = F;
                     // the upwind neighbour's outgoing state is the face state on the upwind side
                     T nbs = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
-                    if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T>(d, A, c, 0, kk[v]);
-                    if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T>(d, A, c, 1, kk[v]);
+                    if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T>(d, A, c, 0, koff[v] * (8 / ST));
+                    if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T>(d, A, c, 1, koff[v] * (8 / ST));
                     div[A] = fma(axp[v], ox[A][v] - nbs, ayq[v] * (F - Fdn[A][v]));
                 }
                 if (NEAR && !upd) {
@@ -1231,11 +1286,24 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
 
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s)
 {
-    int nfill = fill ? d.npairs : 0;
-    int nfin = fin ? (int)blocks_for(d.Nc, 32) : 0;
+    const int nfill = fill ? d.npairs * ((d.NV + kFillChunk - 1) / kFillChunk) : 0;
+    const int nfin = fin ? (int)blocks_for(d.Nc, 4) : 0;
     if (nfill + nfin == 0) return hipSuccess;
     DISPATCH(d.D, storage,
              hipLaunchKernelGGL((k_fill_fin<DD, TT>), dim3(nfill + nfin), dim3(256), 0, s, d, cur, slot, nfill, fin ? 1 : 0));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nfill == 0) return e;
+    if (d.alpha < 1.0) {
+        if (d.D == 2)
+            hipLaunchKernelGGL((k_fill_specular<2>), dim3(nfill), dim3(256), 0, s, d);
+        else
+            hipLaunchKernelGGL((k_fill_specular<3>), dim3(nfill), dim3(256), 0, s, d);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (d.D == 2)
+        hipLaunchKernelGGL((k_fill_ghost<2>), dim3(nfill), dim3(256), 0, s, d);
+    else
+        hipLaunchKernelGGL((k_fill_ghost<3>), dim3(nfill), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 
