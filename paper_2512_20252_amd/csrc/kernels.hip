@@ -123,8 +123,12 @@ __device__ __forceinline__ void tau_min_commit(const Dev &d, int slot, double ta
     if (lane == 0) red[wv] = tau;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
-        if (t < INFINITY) atomicMin(&d.ctrl->tau_bits[slot], (unsigned long long)__double_as_longlong(t));
+        // positive doubles order as their bit patterns; most workgroups see a
+        // smaller minimum already and skip the atomic on the shared word
+        const double t = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+        const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+        unsigned long long *w = &d.ctrl->tau_bits[slot];
+        if (t < INFINITY && tb < __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(w, tb);
     }
 }
 
