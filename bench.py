@@ -32,14 +32,15 @@ def _kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(workload, precision, launches_bytes):
-    """HBM bytes per update launch from committed rocprofv3 counter runs,
-    or None when they are missing or were taken on a different kernel."""
+def _traffic(workload, precision, tile):
+    """HBM bytes per update launch from committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
+    when they are missing or were taken on another kernel source or tile."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("kernel_sha") != _kernel_sha():
+    if rec.get("kernel_sha") != _kernel_sha() or list(rec.get("tile", [])) != list(tile):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -96,7 +97,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="time only the FP32-storage form")
-    ap.add_argument("--tile", type=str, default="", help="V,TX,LY of the 2D update (default: autotune)")
+    ap.add_argument("--tile", type=str, default="", help="V,TX,LY of the FP64 2D update (default: autotune)")
+    ap.add_argument("--tile32", type=str, default="", help="V,TX,LY of the FP32-storage 2D update (default: autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -118,8 +120,9 @@ def main():
     case = cases.cylinder_256(Kn=0.1, Ma=0.3)
     workload = "cylinder_256x256_v48x48"
     tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    tile32 = tuple(int(x) for x in args.tile32.split(",")) if args.tile32 else None
     if args.no_f64:
-        r32 = run_gpu(case, "f32", args.steps, args.warmup, tile=tile)
+        r32 = run_gpu(case, "f32", args.steps, args.warmup, tile=tile32)
         print(json.dumps({"f32_ms_per_step": r32["ms"] / args.steps, "tile": r32["tile"], "prof": r32["prof"]}))
         return
     r64 = run_gpu(case, "f64", args.steps, args.warmup, tile=tile)
@@ -129,7 +132,7 @@ def main():
     avg_ms = prof["update_ms"] / max(prof["update_launches"], 1)
     bytes_launch = upd * B_ALG[(r64["dim"], "f64")]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    traffic = _traffic(workload, "f64", bytes_launch)
+    traffic = _traffic(workload, "f64", r64["tile"])
     line = {
         "metric": "cell*vel updates/s & %HBM peak, FP32-store vs FP64 at fixed C_D err; p50/p99",
         "value": value,
@@ -147,13 +150,14 @@ def main():
                                "Kn 0.1, Ma 0.3, Shakhov, diffuse wall, FP64",
                    "cells": 65536, "fluid_cells": r64["nfluid"], "velocity_nodes": r64["NV"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_update",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_update2d<double,%d,%d>" % tuple(r64["tile"][:2]),
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
                      "tile": r64["tile"]},
     }
     if not args.no_f32:
-        r32 = run_gpu(case, "f32", args.steps, args.warmup)
+        r32 = run_gpu(case, "f32", args.steps, args.warmup, tile=tile32)
         line["precision_form_tile"] = r32["tile"]
         v32 = upd * args.steps / (r32["ms"] * 1e-3)
         avg32 = r32["prof"]["update_ms"] / max(r32["prof"]["update_launches"], 1)
