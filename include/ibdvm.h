@@ -222,6 +222,72 @@ ibdvm_status ibdvm_profile_read(ibdvm_ctx *ctx, double ms[2], int64_t counts[2])
 /* Thread-local message describing the last failure on this thread. */
 const char *ibdvm_last_error(void);
 
+/* State := freestream Maxwellian times (1 + amp * u) with u uniform on
+ * (-1, 1) from a counter-based generator on the device: the SplitMix64
+ * output function of seed + (i + 1) * 0x9e3779b97f4a7c15, i running over
+ * (array, cell, node) in storage order.  For inputs that need no host
+ * arrays (serving).  Synchronises. */
+ibdvm_status ibdvm_init_freestream_hashed(ibdvm_ctx *ctx, uint64_t seed, double amp);
+
+/* ---------------------------------------------------------------- serving
+ * Captured steps: nsteps (even, >= 2) steps of ctx recorded once as a HIP
+ * graph and replayed on the context stream; a replay gives the same bits as
+ * ibdvm_step(ctx, nsteps).  The graph addresses the context's buffers, so
+ * it replays only while the context has advanced by an even number of steps
+ * since the capture (IBDVM_E_STATE otherwise).  The context's stream must
+ * not be the legacy default stream (IBDVM_E_STATE).  Launch only enqueues.
+ * The graph must be destroyed before its context. */
+typedef struct ibdvm_graph ibdvm_graph;
+ibdvm_status ibdvm_graph_create(ibdvm_ctx *ctx, int32_t nsteps, ibdvm_graph **out);
+ibdvm_status ibdvm_graph_launch(ibdvm_graph *graph);
+void ibdvm_graph_destroy(ibdvm_graph *graph);
+
+/* Continuous batching of many 2D solves on one device (serving form).  The
+ * server owns no device memory: it sub-allocates each admitted request's
+ * footprint from the caller's workspace (256-byte aligned, kept by the
+ * caller until ibdvm_server_destroy).  Requests are admitted in submission
+ * order as soon as a block of their footprint and one of max_active slots
+ * are free; each active solve has its own stream and a captured graph of
+ * steps_per_replay steps (even), replayed until |C_D(n) - C_D(n - K)| < tol
+ * (tol <= 0: never) or max_steps steps are done; then its memory and slot
+ * go back to the queue.  A tile shape per (grid, velocity grid, precision)
+ * is chosen once by ibdvm_autotune and reused.  Single-threaded: one thread
+ * submits and polls. */
+typedef struct ibdvm_server ibdvm_server;
+typedef struct {
+    int64_t id;
+    int32_t status;    /* IBDVM_OK, or the error that ended the solve */
+    int32_t converged; /* 1: C_D settled; 0: stopped at max_steps or failed */
+    int64_t steps;
+    double C_D, C_L;
+    double t_submit, t_admit, t_done; /* seconds on the server clock */
+    int64_t updates;                  /* fluid cells x velocity nodes x steps */
+    int32_t tile[3];                  /* 2D update tile used */
+} ibdvm_result;
+
+ibdvm_status ibdvm_server_create(void *workspace, size_t bytes, int32_t max_active, int32_t steps_per_replay,
+                                 ibdvm_server **out);
+/* Queues a solve (the problem arguments are those of ibdvm_create; opts'
+ * workspace and stream are ignored).  The initial state is the freestream
+ * times (1 + amp u) of ibdvm_init_freestream_hashed(seed).  moments_out
+ * (host, [cells][8], may be NULL) receives the final moments and must stay
+ * valid until the request is returned by poll.  IBDVM_E_NO_MEMORY if the
+ * footprint exceeds the whole workspace. */
+ibdvm_status ibdvm_server_submit(ibdvm_server *srv, const ibdvm_grid *grid, const ibdvm_vgrid *vgrid,
+                                 const ibdvm_geometry *geom, double Kn, double Ma, double Pr, double gamma,
+                                 double alpha, double T_w, const ibdvm_opts *opts, uint64_t seed, double amp,
+                                 double tol, int64_t max_steps, double *moments_out, int64_t *id);
+/* Advances the server: harvests finished replays, checks convergence,
+ * admits queued requests, relaunches.  block != 0 waits until at least one
+ * solve finishes (or none is active).  Returns up to cap finished results. */
+ibdvm_status ibdvm_server_poll(ibdvm_server *srv, int32_t block, ibdvm_result *done, int32_t cap, int32_t *n_done);
+/* out = queued, active, finished, workspace bytes in use, workspace bytes. */
+ibdvm_status ibdvm_server_info(const ibdvm_server *srv, int64_t out[5]);
+double ibdvm_server_clock(const ibdvm_server *srv);
+const char *ibdvm_server_error(const ibdvm_server *srv);
+/* Waits for the active solves and releases them; queued ones are dropped. */
+void ibdvm_server_destroy(ibdvm_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,7 +36,7 @@ def build(verbose=False):
     k_obj = os.path.join(BUILD, "kernels.o")
     _run([HIPCC] + HIP_FLAGS + INCLUDES + ["-c", os.path.join(HERE, "kernels.hip"), "-o", k_obj], verbose)
     objs.append(k_obj)
-    for src in ("geometry.cpp", "ibdvm.cpp"):
+    for src in ("geometry.cpp", "ibdvm.cpp", "server.cpp"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o"))
         _run(["g++"] + HOST_FLAGS + INCLUDES + ["-c", os.path.join(HERE, src), "-o", o], verbose)
         objs.append(o)

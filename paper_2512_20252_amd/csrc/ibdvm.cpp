@@ -584,6 +584,18 @@ ibdvm_status ibdvm_init_freestream(ibdvm_ctx *c, const double *u0, const double 
     return sync_and_check(c);
 }
 
+ibdvm_status ibdvm_init_freestream_hashed(ibdvm_ctx *c, uint64_t seed, double amp)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = reset_clock(c))) return st;
+    for (int A = 0; A < c->NA; ++A)
+        HIP_CHECK(ibdvm::launch_state_hashed(c->dev, c->precision, c->cur, A, (unsigned long long)seed, amp, c->stream));
+    if ((st = refresh_moments(c))) return st;
+    return sync_and_check(c);
+}
+
 ibdvm_status ibdvm_set_state(ibdvm_ctx *c, const double *f0, const double *f1)
 {
     ibdvm_status st = require_device(c);
@@ -629,6 +641,77 @@ ibdvm_status ibdvm_step(ibdvm_ctx *c, int32_t nsteps)
     for (int32_t i = 0; i < nsteps; ++i)
         if ((st = one_step(c))) return st;
     return finish_pending(c);
+}
+
+struct ibdvm_graph {
+    ibdvm_ctx *ctx = nullptr;
+    int32_t nsteps = 0;
+    int cur0 = 0, parity0 = 0;  // buffer and tau slot the captured launches address
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+ibdvm_status ibdvm_graph_create(ibdvm_ctx *c, int32_t nsteps, ibdvm_graph **out)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!out) return fail(IBDVM_E_INVALID_ARG, "null output");
+    *out = nullptr;
+    if (nsteps < 2 || (nsteps & 1)) return fail(IBDVM_E_INVALID_ARG, "graph step count must be even and >= 2");
+    if (c->profiling) return fail(IBDVM_E_STATE, "profiling is on; turn it off before capturing");
+    if (!c->stream) return fail(IBDVM_E_STATE, "capture needs a stream other than the legacy default stream");
+    HIP_CHECK(hipSetDevice(c->device));
+    // the capture starts and ends with the moments finished, as ibdvm_step leaves them
+    if ((st = finish_pending(c))) return st;
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    const int cur0 = c->cur;
+    const long long step0 = c->step;
+    auto *g = new ibdvm_graph;
+    g->ctx = c;
+    g->nsteps = nsteps;
+    g->cur0 = cur0;
+    g->parity0 = (int)(step0 & 1);
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int32_t i = 0; i < nsteps && !st; ++i) st = one_step(c);
+        if (!st) st = finish_pending(c);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g->graph);
+        if (!st && e2 != hipSuccess) e = e2;
+    }
+    // capturing records the launches without running them
+    c->cur = cur0;
+    c->step = step0;
+    c->pending = false;
+    if (e == hipSuccess && !st) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess || st) {
+        (void)hipGetLastError();  // leave no stale error for the next launch check
+        ibdvm_graph_destroy(g);
+        return st ? st : fail(IBDVM_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_graph_launch(ibdvm_graph *g)
+{
+    if (!g || !g->exec) return fail(IBDVM_E_INVALID_ARG, "null graph");
+    ibdvm_status st = require_device(g->ctx);
+    if (st) return st;
+    if (g->ctx->cur != g->cur0 || (int)(g->ctx->step & 1) != g->parity0)
+        return fail(IBDVM_E_STATE, "context advanced by an odd number of steps since the capture");
+    HIP_CHECK(hipSetDevice(g->ctx->device));
+    if ((st = finish_pending(g->ctx))) return st;
+    HIP_CHECK(hipGraphLaunch(g->exec, g->ctx->stream));
+    g->ctx->step += g->nsteps;
+    return IBDVM_OK;
+}
+
+void ibdvm_graph_destroy(ibdvm_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps)

@@ -1192,6 +1192,29 @@ __global__ void k_state_from_freestream(Dev d, int buf, int A, const double *u, 
     ((T *)d.f[buf][A])[g] = (T)v;
 }
 
+// freestream times (1 + amp u) with u uniform on (-1, 1) from a counter-based
+// generator: the SplitMix64 output function (Steele, Lea and Flood, OOPSLA
+// 2014) applied to seed + (index + 1) * golden-ratio increment, index running
+// over (array, cell, node) in storage order
+__device__ __forceinline__ double hashed_uniform(unsigned long long seed, unsigned long long idx)
+{
+    unsigned long long z = seed + (idx + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+template <typename T>
+__global__ void k_state_hashed(Dev d, int buf, int A, unsigned long long seed, double amp, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = (int)(i % d.NV);
+    const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
+    ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
+}
+
 template <typename T>
 __global__ void k_state_set(Dev d, int buf, int A, const double *src, long long off, long long n)
 {
@@ -1332,6 +1355,17 @@ hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, co
         hipLaunchKernelGGL(k_state_from_freestream<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
     else
         hipLaunchKernelGGL(k_state_from_freestream<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_hashed(const Dev &d, int storage, int buf, int A, unsigned long long seed, double amp,
+                               hipStream_t s)
+{
+    const long long n = (long long)d.Nc * d.NV;
+    if (storage == 0)
+        hipLaunchKernelGGL(k_state_hashed<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
+    else
+        hipLaunchKernelGGL(k_state_hashed<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, h
 hipError_t launch_force(const Dev &d, int storage, int cur, hipStream_t s);
 hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, const double *u, double amp, long long off,
                                    long long n, hipStream_t s);
+hipError_t launch_state_hashed(const Dev &d, int storage, int buf, int A, unsigned long long seed, double amp,
+                               hipStream_t s);
 hipError_t launch_state_set(const Dev &d, int storage, int buf, int A, const double *src, long long off, long long n,
                             hipStream_t s);
 hipError_t launch_state_get(const Dev &d, int storage, int buf, int A, double *dst, long long off, long long n,

@@ -47,6 +47,12 @@ class WallPoint(ctypes.Structure):
     _fields_ = [("xw", c_double * 3), ("nw", c_double * 3), ("rho_w", c_double), ("p_w", c_double)]
 
 
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", c_int32), ("converged", c_int32), ("steps", ctypes.c_int64),
+                ("C_D", c_double), ("C_L", c_double), ("t_submit", c_double), ("t_admit", c_double),
+                ("t_done", c_double), ("updates", ctypes.c_int64), ("tile", c_int32 * 3)]
+
+
 class IbdvmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"ibdvm error {code}: {msg}")
@@ -58,7 +64,11 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_set_state", "ibdvm_get_state", "ibdvm_step", "ibdvm_moments", "ibdvm_surface_forces",
            "ibdvm_clock", "ibdvm_index_sets", "ibdvm_pair_geometry", "ibdvm_wall_state", "ibdvm_batch_step",
            "ibdvm_profile", "ibdvm_profile_read", "ibdvm_set_tile", "ibdvm_get_tile", "ibdvm_autotune",
-           "ibdvm_last_error"]
+           "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_graph_launch",
+           "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
+           "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy"]
+_NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
+               "ibdvm_server_error", "ibdvm_server_destroy")
 
 
 def lib():
@@ -93,8 +103,25 @@ def lib():
         L.ibdvm_autotune.argtypes = [c_void_p, c_int32, P(c_int32)]
         L.ibdvm_last_error.argtypes = []
         L.ibdvm_last_error.restype = ctypes.c_char_p
+        L.ibdvm_init_freestream_hashed.argtypes = [c_void_p, ctypes.c_uint64, c_double]
+        L.ibdvm_graph_create.argtypes = [c_void_p, c_int32, P(c_void_p)]
+        L.ibdvm_graph_launch.argtypes = [c_void_p]
+        L.ibdvm_graph_destroy.argtypes = [c_void_p]
+        L.ibdvm_graph_destroy.restype = None
+        L.ibdvm_server_create.argtypes = [c_void_p, c_size_t, c_int32, c_int32, P(c_void_p)]
+        L.ibdvm_server_submit.argtypes = [c_void_p, P(Grid), P(VGrid), P(Geom), c_double, c_double, c_double,
+                                          c_double, c_double, c_double, P(Opts), ctypes.c_uint64, c_double,
+                                          c_double, ctypes.c_int64, dp, P(ctypes.c_int64)]
+        L.ibdvm_server_poll.argtypes = [c_void_p, c_int32, P(Result), c_int32, P(c_int32)]
+        L.ibdvm_server_info.argtypes = [c_void_p, P(ctypes.c_int64)]
+        L.ibdvm_server_clock.argtypes = [c_void_p]
+        L.ibdvm_server_clock.restype = c_double
+        L.ibdvm_server_error.argtypes = [c_void_p]
+        L.ibdvm_server_error.restype = ctypes.c_char_p
+        L.ibdvm_server_destroy.argtypes = [c_void_p]
+        L.ibdvm_server_destroy.restype = None
         for name in EXPORTS:
-            if name not in ("ibdvm_destroy", "ibdvm_last_error"):
+            if name not in _NOT_STATUS:
                 getattr(L, name).restype = c_int32
         _lib = L
     return _lib
@@ -200,6 +227,9 @@ class Solver:
         u1 = np.ascontiguousarray(u[1], dtype=np.float64).reshape(-1) if (u is not None and self.NA == 2) else None
         check(lib().ibdvm_init_freestream(self._h, _dp(u0), _dp(u1), float(amp)))
 
+    def init_freestream_hashed(self, seed, amp):
+        check(lib().ibdvm_init_freestream_hashed(self._h, int(seed), float(amp)))
+
     def set_state(self, f):
         f0 = np.ascontiguousarray(f[0], dtype=np.float64).reshape(-1)
         f1 = np.ascontiguousarray(f[1], dtype=np.float64).reshape(-1) if self.NA == 2 else None
@@ -291,3 +321,85 @@ class Solver:
 def batch_step(solvers, n):
     arr = (c_void_p * len(solvers))(*[s.handle for s in solvers])
     check(lib().ibdvm_batch_step(arr, len(solvers), int(n)))
+
+
+class Graph:
+    """nsteps captured steps of one solver, replayed on its stream."""
+
+    def __init__(self, solver, nsteps):
+        self.solver = solver
+        h = c_void_p(0)
+        check(lib().ibdvm_graph_create(solver.handle, int(nsteps), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self):
+        check(lib().ibdvm_graph_launch(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibdvm_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Server:
+    """Continuous batching of 2D solves in one device workspace (a torch
+    uint8 tensor of ``nbytes``)."""
+
+    def __init__(self, nbytes, max_active=4, steps_per_replay=100):
+        import torch
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        h = c_void_p(0)
+        code = lib().ibdvm_server_create(self.workspace.data_ptr(), self.workspace.numel(), int(max_active),
+                                         int(steps_per_replay), ctypes.byref(h))
+        if code != OK:
+            raise IbdvmError(code, "server_create")
+        self._h = h
+        self._outs = {}
+
+    def _check(self, code):
+        if code != OK:
+            raise IbdvmError(code, lib().ibdvm_server_error(self._h).decode())
+
+    def submit(self, case, precision="f32", seed=0, amp=1e-3, tol=1e-6, max_steps=200000, keep_moments=False):
+        g, v, ge, o = structs(case, precision)
+        out = None
+        if keep_moments:
+            out = np.empty((int(np.prod(case["n"][: case["dim"]])), 8))
+        rid = ctypes.c_int64(0)
+        self._check(lib().ibdvm_server_submit(self._h, ctypes.byref(g), ctypes.byref(v), ctypes.byref(ge),
+                                              case["Kn"], case["Ma"], case["Pr"], case["gamma"], case["alpha"],
+                                              case["Tw"], ctypes.byref(o), int(seed), float(amp), float(tol),
+                                              int(max_steps), _dp(out), ctypes.byref(rid)))
+        self._outs[rid.value] = out
+        return rid.value
+
+    def poll(self, block=False, cap=64):
+        res = (Result * cap)()
+        n = c_int32(0)
+        self._check(lib().ibdvm_server_poll(self._h, 1 if block else 0, res, cap, ctypes.byref(n)))
+        out = []
+        for r in res[: n.value]:
+            d = {k: getattr(r, k) for k, _ in Result._fields_ if k != "tile"}
+            d["tile"] = tuple(r.tile)
+            d["moments"] = self._outs.pop(r.id, None)
+            out.append(d)
+        return out
+
+    def info(self):
+        a = (ctypes.c_int64 * 5)()
+        self._check(lib().ibdvm_server_info(self._h, a))
+        return dict(zip(("queued", "active", "finished", "bytes_used", "bytes_total"), [int(x) for x in a]))
+
+    def clock(self):
+        return lib().ibdvm_server_clock(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ibdvm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

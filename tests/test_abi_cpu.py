@@ -116,3 +116,32 @@ def test_null_workspace_rejected():
     code = ibdvm.lib().ibdvm_create(ctypes.byref(g), ctypes.byref(v), ctypes.byref(ge), c["Kn"], c["Ma"], c["Pr"],
                                     c["gamma"], c["alpha"], c["Tw"], ctypes.byref(o), ctypes.byref(h))
     assert code == ibdvm.E_INVALID_ARG and not h.value
+
+
+def test_server_argument_checks():
+    """Serving form, host side only: bad arguments are refused and a request
+    larger than the whole workspace is refused before any device work."""
+    L = ibdvm.lib()
+    h = ctypes.c_void_p(0)
+    assert L.ibdvm_server_create(None, 1 << 20, 1, 2, ctypes.byref(h)) == ibdvm.E_INVALID_ARG
+    assert L.ibdvm_server_create(ctypes.c_void_p(256), 1 << 20, 1, 3, ctypes.byref(h)) == ibdvm.E_INVALID_ARG
+    assert L.ibdvm_server_create(ctypes.c_void_p(256), 1 << 20, 0, 2, ctypes.byref(h)) == ibdvm.E_INVALID_ARG
+    # a fake, never dereferenced workspace address: create and submit touch no device memory
+    assert L.ibdvm_server_create(ctypes.c_void_p(1 << 20), 1 << 20, 2, 4, ctypes.byref(h)) == ibdvm.OK
+    c = cases.cylinder_small()
+    g, v, ge, o = ibdvm.structs(c)
+    rid = ctypes.c_int64(0)
+    args = (ctypes.byref(g), ctypes.byref(v), ctypes.byref(ge), c["Kn"], c["Ma"], c["Pr"], c["gamma"], c["alpha"],
+            c["Tw"], ctypes.byref(o), 1, 1e-3, 1e-6)
+    assert ibdvm.footprint(c) > (1 << 20)
+    assert L.ibdvm_server_submit(h, *args, 100, None, ctypes.byref(rid)) == ibdvm.E_NO_MEMORY
+    assert L.ibdvm_server_submit(h, *args, 2, None, ctypes.byref(rid)) == ibdvm.E_INVALID_ARG  # fewer steps than a replay
+    c3 = cases.sphere(n=12, vn=6)
+    g3, v3, ge3, o3 = ibdvm.structs(c3)
+    assert L.ibdvm_server_submit(h, ctypes.byref(g3), ctypes.byref(v3), ctypes.byref(ge3), c3["Kn"], c3["Ma"], c3["Pr"],
+                                 c3["gamma"], c3["alpha"], c3["Tw"], ctypes.byref(o3), 1, 1e-3, 1e-6, 100, None,
+                                 ctypes.byref(rid)) == ibdvm.E_UNSUPPORTED
+    info = (ctypes.c_int64 * 5)()
+    assert L.ibdvm_server_info(h, info) == ibdvm.OK
+    assert list(info)[:3] == [0, 0, 0] and info[4] == 1 << 20
+    L.ibdvm_server_destroy(h)

@@ -286,3 +286,93 @@ def test_autotune_leaves_state(torch_cuda):
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
     assert s.clock() == clk
+
+
+@pytest.mark.gpu
+def test_graph_replays_match_eager_steps(torch_cuda):
+    """A captured graph of 4 steps, replayed three times with eager work in
+    between, gives the bits of ibdvm_step(4) each time; an odd eager step
+    between replays is refused until the parity is restored."""
+    import torch
+    c = cases.cylinder_small()
+    u = cases.noise(c, 2)
+    side = torch.cuda.Stream()  # graphs are captured on a stream other than the legacy default one
+    eager, cap = ibdvm.Solver(c), ibdvm.Solver(c, stream=side)
+    eager.init_freestream(u, 1e-3)
+    cap.init_freestream(u, 1e-3)
+    g = ibdvm.Graph(cap, 4)
+    for _ in range(3):
+        eager.step(4)
+        g.launch()
+        assert np.array_equal(eager.moments(), cap.moments(), equal_nan=True)
+        assert eager.surface_forces()[1] == cap.surface_forces()[1]
+    for a, b in zip(eager.get_state(), cap.get_state()):
+        assert np.array_equal(a, b)
+    cap.step(1)
+    with pytest.raises(ibdvm.IbdvmError) as e:
+        g.launch()
+    assert e.value.code == ibdvm.E_STATE
+    cap.step(1)
+    g.launch()
+    eager.step(6)
+    assert np.array_equal(eager.moments(), cap.moments(), equal_nan=True)
+    g.close()
+
+
+SERVE_CASES = [cases.cylinder_small(),
+               cases.case(**dict(cases.cylinder_small(), vn=(12, 12), Kn=0.3)),
+               cases.case(dim=2, n=(20, 28), lo=(-1.0, -1.4), hi=(1.0, 1.4), vn=(10, 14), vlo=(-5.0, -5.0),
+                          vhi=(5.0, 5.0), geometry="circle", size=(0.35, 0.0, 0.0), Kn=0.05, Ma=1.2, alpha=0.7),
+               cases.case(dim=2, n=(24, 24), lo=(-1.2, -1.2), hi=(1.2, 1.2), vn=(16, 16), vlo=(-5.0, -5.0),
+                          vhi=(5.0, 5.0), geometry="ellipse", center=(0.0, 0.0, 0.0), size=(0.4, 0.2, 0.0),
+                          aoa=0.3, Kn=0.1, Ma=0.8)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_server_alone_vs_mix(torch_cuda, precision):
+    """Serving form: solves of different sizes and physics admitted into one
+    workspace (two active slots, so the others queue and start as slots free
+    up) give bitwise the same moments as each solve stepped alone with the
+    tile the server chose."""
+    srv = ibdvm.Server(sum(ibdvm.footprint(c, precision) for c in SERVE_CASES) + (1 << 20), max_active=2,
+                       steps_per_replay=4)
+    ids = [srv.submit(c, precision, seed=11 + i, amp=1e-3, tol=0.0, max_steps=12, keep_moments=True)
+           for i, c in enumerate(SERVE_CASES)]
+    done = {}
+    while len(done) < len(ids):
+        for r in srv.poll(block=True):
+            done[r["id"]] = r
+    assert srv.info()["bytes_used"] == 0
+    t_done = sorted(r["t_done"] for r in done.values())
+    for i, (rid, c) in enumerate(zip(ids, SERVE_CASES)):
+        r = done[rid]
+        assert r["status"] == ibdvm.OK and r["steps"] == 12 and not r["converged"]
+        if i >= 2:  # admitted only after an earlier solve finished
+            assert r["t_admit"] >= t_done[0]
+        s = ibdvm.Solver(c, precision=precision)
+        s.init_freestream_hashed(11 + i, 1e-3)
+        s.set_tile(*r["tile"])
+        s.step(12)
+        assert np.array_equal(s.moments(), r["moments"], equal_nan=True)
+        assert s.surface_forces()[1] == r["C_D"]
+    srv.close()
+
+
+@pytest.mark.gpu
+def test_server_admission_by_memory(torch_cuda):
+    """A workspace that holds one solve at a time runs them one after the
+    other, whatever the slot count; convergence stops a solve early."""
+    c = SERVE_CASES[0]
+    srv = ibdvm.Server(ibdvm.footprint(c, "f32") + 4096, max_active=4, steps_per_replay=10)
+    ids = [srv.submit(c, "f32", seed=i, amp=1e-3, tol=0.1, max_steps=200) for i in range(3)]
+    res = []
+    while len(res) < 3:
+        res += srv.poll(block=True)
+    res.sort(key=lambda r: r["t_admit"])
+    assert [r["id"] for r in res] == ids
+    for a, b in zip(res, res[1:]):
+        assert b["t_admit"] >= a["t_done"]
+    for r in res:
+        assert r["status"] == ibdvm.OK and r["converged"] == 1 and 20 <= r["steps"] < 200
+    srv.close()
