@@ -89,6 +89,43 @@ def cpu_baseline(case, seed=0):
                                         "OpenMP over cells, sequential velocity sums", "seconds": dt}
 
 
+def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
+    """Continuous-batching leg: a seeded Poisson stream of mixed 2D solves
+    (FP32 storage) through one server; time-to-converged-C_D percentiles and
+    aggregate updates/s."""
+    import numpy as np
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    reqs, gaps = cases.serving_requests(nreq, seed)
+    arrivals = np.cumsum(gaps) * gap_s
+    fps = [ibdvm.footprint(c, "f32") for c in reqs]
+    free, _ = torch.cuda.mem_get_info()
+    ws = int(max(max(fps) + (1 << 20), min(sum(fps) + (1 << 20), 0.8 * free)))
+    srv = ibdvm.Server(ws, max_active=max_active, steps_per_replay=100)
+    t0, sub, done, samples = srv.clock(), 0, [], []
+    while len(done) < nreq:
+        now = srv.clock() - t0
+        while sub < nreq and arrivals[sub] <= now:
+            srv.submit(reqs[sub], "f32", seed=sub, amp=1e-3, tol=tol, max_steps=cap)
+            sub += 1
+        done += srv.poll(block=False)
+        samples.append(srv.info()["active"])
+        time.sleep(0.002)
+    srv.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in done])
+    conv = np.array([r["converged"] == 1 for r in done])
+    ups = sum(r["updates"] for r in done) / (max(r["t_done"] for r in done) - min(r["t_submit"] for r in done))
+    pct = lambda x, q: float(np.percentile(x, q)) if len(x) else None
+    return {"requests": nreq, "precision": "f32", "step_cap": cap, "tol_dCD_per_100_steps": tol,
+            "mean_arrival_gap_s": gap_s, "max_active": max_active, "workspace_GiB": ws / 2 ** 30,
+            "converged": int(conv.sum()), "failed": int(sum(r["status"] != 0 for r in done)),
+            "p50_time_to_converged_s": pct(lat[conv], 50), "p99_time_to_converged_s": pct(lat[conv], 99),
+            "p50_time_to_done_s": pct(lat, 50), "p99_time_to_done_s": pct(lat, 99),
+            "mean_active": float(np.mean(samples)), "aggregate_updates_per_s": ups,
+            "steps": [int(r["steps"]) for r in done]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +136,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="time only the FP32-storage form")
     ap.add_argument("--tile", type=str, default="", help="V,TX,LY of the FP64 2D update (default: autotune)")
     ap.add_argument("--tile32", type=str, default="", help="V,TX,LY of the FP32-storage 2D update (default: autotune)")
+    ap.add_argument("--serving", type=int, default=12, help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serving-cap", type=int, default=2000, help="step cap per serving request")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -165,6 +204,8 @@ def main():
                                   "ratio_vs_f64": v32 / value, "dCD_vs_f64": abs(r32["cd"] - r64["cd"]),
                                   "CD_f64": r64["cd"], "update_avg_launch_ms": avg32,
                                   "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9}
+    if args.serving > 0:
+        line["serving"] = serving(args.serving, args.serving_cap, 1e-4, 0.5)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)

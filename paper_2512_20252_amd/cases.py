@@ -78,3 +78,38 @@ def noise(c, seed=0):
     shape = (n_cells(c), n_vel(c))
     na = 2 if c["dim"] == 2 else 1
     return tuple(rng.uniform(-1.0, 1.0, size=shape) for _ in range(na))
+
+
+def serving_requests(n=128, seed=0):
+    """Seeded stream of 2D solve requests of mixed sizes on [-4,4]^2: grid
+    N in {64, 96, ..., 384}, velocity grid N_xi in {16, 24, ..., 56} on
+    [-V, V]^2 with V = max(6, ceil(U_inf + 4 sqrt(1 + Ma^2/3))), geometry
+    uniform over cylinder (r ~ U(0.2, 0.6)), ellipse (chord 1, aspect ~
+    U(1, 4)) and airfoil (chord 1, t ~ U(0.08, 0.2)), Kn log-uniform on
+    [1e-3, 1], Ma ~ U(0.2, 3), alpha ~ U(0.5, 1).  Fields are drawn per
+    request in that order, then the arrival gaps as unit-mean exponentials
+    (scaled by the caller)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        N = int(rng.choice(np.arange(64, 385, 32)))
+        nxi = int(rng.choice(np.arange(16, 57, 8)))
+        kind = int(rng.integers(0, 3))
+        shape = float(rng.uniform(0.2, 0.6)) if kind == 0 else (float(rng.uniform(1.0, 4.0)) if kind == 1
+                                                                else float(rng.uniform(0.08, 0.2)))
+        Kn = float(10.0 ** rng.uniform(-3.0, 0.0))
+        Ma = float(rng.uniform(0.2, 3.0))
+        alpha = float(rng.uniform(0.5, 1.0))
+        U = Ma * np.sqrt(5.0 / 6.0)
+        V = float(max(6.0, np.ceil(U + 4.0 * np.sqrt(1.0 + Ma * Ma / 3.0))))
+        common = dict(dim=2, n=(N, N), lo=(-4.0, -4.0), hi=(4.0, 4.0), vn=(nxi, nxi), vlo=(-V, -V), vhi=(V, V),
+                      Kn=Kn, Ma=Ma, alpha=alpha)
+        if kind == 0:
+            c = case(geometry="circle", size=(shape, 0.0, 0.0), **common)
+        elif kind == 1:
+            c = case(geometry="ellipse", center=(0.0, 0.0, 0.0), size=(0.5, 0.5 / shape, 0.0), **common)
+        else:
+            c = case(geometry="airfoil", center=(-0.5, 0.0, 0.0), size=(1.0, shape, 0.0), **common)
+        out.append(c)
+    gaps = rng.exponential(1.0, size=n)
+    return out, gaps
