@@ -962,6 +962,7 @@ static void ib_fill(or_state *s)
                 }
                 /* 3. incident distribution at the intersect point */
                 double fiw = fsp + (fgc - fsp) / (ygc - ysp) * (yw - ysp);
+                if (fiw < 0.0) fiw = 0.0; /* distributions are non-negative (reading R28) */
                 s->fsp[A][o + k] = fsp;
                 s->fgc[A][o + k] = fgc;
                 s->fiw[A][o + k] = fiw;
@@ -979,8 +980,15 @@ static void ib_fill(or_state *s)
                 double fsp = s->fsp[A][o + k], fw = s->fw[A][o + k];
                 double sig = (fw - fsp) / (yw - ysp); /* ghost-side slope (reading R8) */
                 double gval = fsp + sig * (ygc - ysp);
-                s->gh[A][o + k] = gval;
-                s->fc[A][o + k] = gval + sig * (yface - ygc);
+                /* reading R28: the ghost value and the face value stay
+                 * non-negative, and the face value, taken on the same line,
+                 * goes no further than the wall value when the face lies
+                 * beyond the wall */
+                double t = (yface - ysp) / (yw - ysp);
+                if (t > 1.0) t = 1.0;
+                double fval = fsp + (fw - fsp) * t;
+                s->gh[A][o + k] = gval < 0.0 ? 0.0 : gval;
+                s->fc[A][o + k] = fval < 0.0 ? 0.0 : fval;
             }
     }
 }

@@ -72,7 +72,7 @@ struct Dev {
     const DPair *pairs;
     const uint8_t *cls;
     const double *wg;
-    double *ghost[2], *face[2], *fiw[2], *fsp[2];
+    double *ghost[2], *face[2], *fiw[2], *fsp[2], *fwall[2];
     double *rhow;
     double *fillpart;  // [pair][fill chunk][2]: incident and specular partial wall fluxes
     double *pforce;

@@ -30,7 +30,7 @@ ibdvm_status fail(ibdvm_status s, const std::string &msg)
 constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
-    size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, rhow, fillpart, pforce, ctrl;
+    size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, fwall, rhow, fillpart, pforce, ctrl;
     size_t total;
     size_t state_bytes;  // one array of one buffer
 };
@@ -71,6 +71,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.face = take((size_t)NA * np * g.NV * 8);
     L.fiw = take((size_t)NA * np * g.NV * 8);
     L.fsp = take((size_t)NA * np * g.NV * 8);
+    L.fwall = take((size_t)NA * np * g.NV * 8);
     L.rhow = take(np * 8);
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * 4 * 8);
@@ -494,6 +495,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
         d.face[A] = (double *)(ws + L.face) + AA * pstride;
         d.fiw[A] = (double *)(ws + L.fiw) + AA * pstride;
         d.fsp[A] = (double *)(ws + L.fsp) + AA * pstride;
+        d.fwall[A] = (double *)(ws + L.fwall) + AA * pstride;
     }
     d.rhow = (double *)(ws + L.rhow);
     d.fillpart = (double *)(ws + L.fillpart);

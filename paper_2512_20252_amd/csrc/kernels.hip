@@ -251,7 +251,8 @@ __device__ void fill_incident(const Dev &d, int cur, int p, int chunk)
                 fgc += wj * (fj - sr);
             }
             // 3. incident distribution at the intersect point
-            const double fiw = fspv + (fgc - fspv) / (ygc - ysp) * (yw - ysp);
+            double fiw = fspv + (fgc - fspv) / (ygc - ysp) * (yw - ysp);
+            if (fiw < 0.0) fiw = 0.0;  // R28: distributions are non-negative
             d.fiw[A][po + k] = fiw;
             d.fsp[A][po + k] = fspv;
             if (A == 0) {
@@ -316,8 +317,14 @@ __device__ void fill_ghost(const Dev &d, int p, int chunk)
         const double fspv = d.fsp[A][po + k];
         const double sig = (fw - fspv) / (yw - ysp);
         const double gv = fspv + sig * (ygc - ysp);
-        d.ghost[A][po + k] = gv;
-        d.face[A][po + k] = gv + sig * (yface - ygc);
+        // R28: ghost and face values stay non-negative; the face value goes
+        // no further than the wall value when the face lies beyond the wall
+        double t = (yface - ysp) / (yw - ysp);
+        if (t > 1.0) t = 1.0;
+        const double fv = fspv + (fw - fspv) * t;
+        d.ghost[A][po + k] = gv < 0.0 ? 0.0 : gv;
+        d.face[A][po + k] = fv < 0.0 ? 0.0 : fv;
+        d.fwall[A][po + k] = fw;
     }
 }
 
@@ -1152,7 +1159,6 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
     ijk[1] = (dc / d.n[0]) % d.n[1];
     ijk[2] = D == 3 ? dc / (d.n[0] * d.n[1]) : 0;
     double acc[4] = {0, 0, 0, 0};
-    const double ygc = P.ygc, yw = P.yw, ysp = P.ysp;
     for (int k = threadIdx.x; k < NV; k += 256) {
         double xa = d.xi[a][k], st;
         if (side * xa > 0.0) {
@@ -1169,10 +1175,7 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
             acc[b] += d.w[k] * d.xi[b][k] * xn * st;
             dn += d.xi[b][k] * P.nw[b];
         }
-        // wall distribution on the line through the shifted and ghost points
-        double fsp = d.fsp[0][(size_t)p * NV + k], gv = d.ghost[0][(size_t)p * NV + k];
-        double fw = fsp + (gv - fsp) / (ygc - ysp) * (yw - ysp);
-        acc[3] += d.w[k] * dn * dn * fw;
+        acc[3] += d.w[k] * dn * dn * d.fwall[0][(size_t)p * NV + k];
     }
     for (int b = 0; b < 4; ++b) {
         double s = block_sum(acc[b]);

@@ -331,13 +331,15 @@ def test_ghost_interpolation_linear_exact(oracle_mod):
     rng = np.random.default_rng(11)
     A = rng.normal(size=(2, o.NV))
     B = rng.normal(size=(2, o.NV))
-    C = rng.normal(size=(2, o.NV)) + 3.0
+    C = rng.normal(size=(2, o.NV)) + 12.0
     nx = 40
     dx = 2.0 / 40
     ci = np.arange(o.Nc)
     x = -1.0 + (ci % nx + 0.5) * dx
     y = -1.0 + (ci // nx + 0.5) * dx
     f = tuple(A[i][None, :] * x[:, None] + B[i][None, :] * y[:, None] + C[i][None, :] for i in range(2))
+    # a positive field: the exactness holds where the non-negativity limits of the wall values are inactive
+    assert min(fi.min() for fi in f) > 0.0
     o.set_state(f)
     dbg = o.fill_debug()
     geo = o.pair_geometry()
