@@ -473,125 +473,127 @@ __global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
         d.ctrl->time += dt;
         d.ctrl->step += 1;
     }
-    const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (wave >= (long long)d.Nc * d.nchunk) return;
-    const int c = (int)(wave / d.nchunk), chunk = (int)(wave - (long long)c * d.nchunk);
-    const int fl = d.cflag[c];
-    const int NV = d.NV;
-    const int k = chunk * kChunk + lane;
-    const bool act = k < NV;
-    const int kk = act ? k : NV - 1;
-    if (fl & 1) {
-        // solid cells are not advanced; carry their value into the new buffer
-        if (act)
-            for (int A = 0; A < d.NA; ++A)
-                ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = ((const T *)d.f[cur][A])[(size_t)c * NV + k];
-        return;
-    }
-    int ijk[3];
-    ijk[0] = c % d.n[0];
-    ijk[1] = (c / d.n[0]) % d.n[1];
-    ijk[2] = D == 3 ? c / (d.n[0] * d.n[1]) : 0;
-
-    const double *cp = d.cellp + (size_t)c * kCellWords;
-    double cc[3] = {0, 0, 0}, c2 = 0.0, cs = 0.0, xi[3] = {0, 0, 0};
-    for (int a = 0; a < D; ++a) {
-        xi[a] = d.xi[a][kk];
-        cc[a] = xi[a] - cp[CW_U + a];
-        c2 += cc[a] * cc[a];
-        cs += cc[a] * cp[CW_S + a];
-    }
-    const double invT = cp[CW_INVT];
-    const double H = cp[CW_A] * exp(-c2 * invT);
-    double gS[2];
-    if (D == 2) {
-        gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 4.0));
-        gS[1] = cp[CW_TH] * H * (1.0 + cs * (2.0 * c2 * invT - 2.0));
-    } else {
-        gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 5.0));
-        gS[1] = 0.0;
-    }
-    const double rate = dt * cp[CW_INVTAU];
-    double fnew[2] = {0.0, 0.0};
-    for (int A = 0; A < d.NA; ++A) {
-        const T *f = (const T *)d.f[cur][A];
-        const T v0 = f[(size_t)c * NV + kk];
-        T div = T(0);
-        for (int a = 0; a < D; ++a) {
-            T vm2, vm1, vp1, vp2;
-            int km1 = NB_FLUID, kp1 = NB_FLUID, pm1 = -1, pp1 = -1;
-            if (!(fl & 2)) {
-                const size_t s = (size_t)d.stride[a] * NV, o = (size_t)c * NV + kk;
-                vm2 = f[o - 2 * s];
-                vm1 = f[o - s];
-                vp1 = f[o + s];
-                vp2 = f[o + 2 * s];
-            } else {
-                int nm, np, dummy, kind2;
-                vm1 = neighbour(d, f, A, kk, c, ijk, a, -1, km1, nm, pm1);
-                vp1 = neighbour(d, f, A, kk, c, ijk, a, +1, kp1, np, pp1);
-                vm2 = vm1;
-                vp2 = vp1;
-                if (km1 == NB_FLUID) {
-                    int j2[3] = {ijk[0], ijk[1], ijk[2]};
-                    j2[a] = (ijk[a] - 1 + d.n[a]) % d.n[a];
-                    vm2 = neighbour(d, f, A, kk, nm, j2, a, -1, kind2, dummy, dummy);
-                }
-                if (kp1 == NB_FLUID) {
-                    int j2[3] = {ijk[0], ijk[1], ijk[2]};
-                    j2[a] = (ijk[a] + 1) % d.n[a];
-                    vp2 = neighbour(d, f, A, kk, np, j2, a, +1, kind2, dummy, dummy);
-                }
-            }
-            const T s0 = vanleer(v0 - vm1, vp1 - v0);
-            const T xa = (T)xi[a];
-            T fr, fl_;
-            if (xa > T(0)) {
-                fr = v0 + T(0.5) * s0;
-                if (km1 == NB_IB)
-                    fl_ = (T)d.face[A][(size_t)pm1 * NV + kk];
-                else if (km1 == NB_BC)
-                    fl_ = vm1;
-                else
-                    fl_ = vm1 + T(0.5) * vanleer(vm1 - vm2, v0 - vm1);
-            } else {
-                fl_ = v0 - T(0.5) * s0;
-                if (kp1 == NB_IB)
-                    fr = (T)d.face[A][(size_t)pp1 * NV + kk];
-                else if (kp1 == NB_BC)
-                    fr = vp1;
-                else
-                    fr = vp1 - T(0.5) * vanleer(vp1 - v0, vp2 - vp1);
-            }
-            div += xa * (fr - fl_) * (T)d.inv_dx[a];
+    // one wavefront per (cell, chunk of 64 nodes), grid-stride over the cells
+    const long long nw = (long long)d.Nc * d.nchunk;
+    for (long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); wave < nw; wave += (long long)gridDim.x * 4) {
+        const int c = (int)(wave / d.nchunk), chunk = (int)(wave - (long long)c * d.nchunk);
+        const int fl = d.cflag[c];
+        const int NV = d.NV;
+        const int k = chunk * kChunk + lane;
+        const bool act = k < NV;
+        const int kk = act ? k : NV - 1;
+        if (fl & 1) {
+            // solid cells are not advanced; carry their value into the new buffer
+            if (act)
+                for (int A = 0; A < d.NA; ++A)
+                    ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = ((const T *)d.f[cur][A])[(size_t)c * NV + k];
+            continue;
         }
-        const double fo = (double)v0;
-        const double fn = fo - dt * (double)div + rate * (gS[A] - fo);
-        const T st = (T)fn;
-        if (act) ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = st;
-        fnew[A] = act ? (double)st : 0.0;
+        int ijk[3];
+        ijk[0] = c % d.n[0];
+        ijk[1] = (c / d.n[0]) % d.n[1];
+        ijk[2] = D == 3 ? c / (d.n[0] * d.n[1]) : 0;
+
+        const double *cp = d.cellp + (size_t)c * kCellWords;
+        double cc[3] = {0, 0, 0}, c2 = 0.0, cs = 0.0, xi[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            xi[a] = d.xi[a][kk];
+            cc[a] = xi[a] - cp[CW_U + a];
+            c2 += cc[a] * cc[a];
+            cs += cc[a] * cp[CW_S + a];
+        }
+        const double invT = cp[CW_INVT];
+        const double H = cp[CW_A] * exp(-c2 * invT);
+        double gS[2];
+        if (D == 2) {
+            gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 4.0));
+            gS[1] = cp[CW_TH] * H * (1.0 + cs * (2.0 * c2 * invT - 2.0));
+        } else {
+            gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 5.0));
+            gS[1] = 0.0;
+        }
+        const double rate = dt * cp[CW_INVTAU];
+        double fnew[2] = {0.0, 0.0};
+        for (int A = 0; A < d.NA; ++A) {
+            const T *f = (const T *)d.f[cur][A];
+            const T v0 = f[(size_t)c * NV + kk];
+            T div = T(0);
+            for (int a = 0; a < D; ++a) {
+                T vm2, vm1, vp1, vp2;
+                int km1 = NB_FLUID, kp1 = NB_FLUID, pm1 = -1, pp1 = -1;
+                if (!(fl & 2)) {
+                    const size_t s = (size_t)d.stride[a] * NV, o = (size_t)c * NV + kk;
+                    vm2 = f[o - 2 * s];
+                    vm1 = f[o - s];
+                    vp1 = f[o + s];
+                    vp2 = f[o + 2 * s];
+                } else {
+                    int nm, np, dummy, kind2;
+                    vm1 = neighbour(d, f, A, kk, c, ijk, a, -1, km1, nm, pm1);
+                    vp1 = neighbour(d, f, A, kk, c, ijk, a, +1, kp1, np, pp1);
+                    vm2 = vm1;
+                    vp2 = vp1;
+                    if (km1 == NB_FLUID) {
+                        int j2[3] = {ijk[0], ijk[1], ijk[2]};
+                        j2[a] = (ijk[a] - 1 + d.n[a]) % d.n[a];
+                        vm2 = neighbour(d, f, A, kk, nm, j2, a, -1, kind2, dummy, dummy);
+                    }
+                    if (kp1 == NB_FLUID) {
+                        int j2[3] = {ijk[0], ijk[1], ijk[2]};
+                        j2[a] = (ijk[a] + 1) % d.n[a];
+                        vp2 = neighbour(d, f, A, kk, np, j2, a, +1, kind2, dummy, dummy);
+                    }
+                }
+                const T s0 = vanleer(v0 - vm1, vp1 - v0);
+                const T xa = (T)xi[a];
+                T fr, fl_;
+                if (xa > T(0)) {
+                    fr = v0 + T(0.5) * s0;
+                    if (km1 == NB_IB)
+                        fl_ = (T)d.face[A][(size_t)pm1 * NV + kk];
+                    else if (km1 == NB_BC)
+                        fl_ = vm1;
+                    else
+                        fl_ = vm1 + T(0.5) * vanleer(vm1 - vm2, v0 - vm1);
+                } else {
+                    fl_ = v0 - T(0.5) * s0;
+                    if (kp1 == NB_IB)
+                        fr = (T)d.face[A][(size_t)pp1 * NV + kk];
+                    else if (kp1 == NB_BC)
+                        fr = vp1;
+                    else
+                        fr = vp1 - T(0.5) * vanleer(vp1 - v0, vp2 - vp1);
+                }
+                div += xa * (fr - fl_) * (T)d.inv_dx[a];
+            }
+            const double fo = (double)v0;
+            const double fn = fo - dt * (double)div + rate * (gS[A] - fo);
+            const T st = (T)fn;
+            if (act) ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = st;
+            fnew[A] = act ? (double)st : 0.0;
+        }
+        // partial moments of the new state about U^n
+        const double wk = act ? d.w[k] : 0.0;
+        const double h = fnew[0];
+        const double E = c2 * h + (D == 2 ? fnew[1] : 0.0);
+        double S[PW];
+        S[0] = wk * h;
+        for (int a = 0; a < D; ++a) {
+            S[1 + a] = wk * cc[a] * h;
+            S[2 + D + a] = wk * cc[a] * E;
+        }
+        S[1 + D] = wk * E;
+        int o = 2 + 2 * D;
+        for (int a = 0; a < D; ++a)
+            for (int b = a; b < D; ++b) S[o++] = wk * cc[a] * cc[b] * h;
+        double mine = 0.0;
+    #pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            double v = wave_sum(S[j]);
+            if (lane == j) mine = v;
+        }
+        if (lane < PW) d.part[((size_t)c * d.nchunk + chunk) * kPartialStride + lane] = mine;
     }
-    // partial moments of the new state about U^n
-    const double wk = act ? d.w[k] : 0.0;
-    const double h = fnew[0];
-    const double E = c2 * h + (D == 2 ? fnew[1] : 0.0);
-    double S[PW];
-    S[0] = wk * h;
-    for (int a = 0; a < D; ++a) {
-        S[1 + a] = wk * cc[a] * h;
-        S[2 + D + a] = wk * cc[a] * E;
-    }
-    S[1 + D] = wk * E;
-    int o = 2 + 2 * D;
-    for (int a = 0; a < D; ++a)
-        for (int b = a; b < D; ++b) S[o++] = wk * cc[a] * cc[b] * h;
-    double mine = 0.0;
-#pragma unroll
-    for (int j = 0; j < PW; ++j) {
-        double v = wave_sum(S[j]);
-        if (lane == j) mine = v;
-    }
-    if (lane < PW) d.part[((size_t)c * d.nchunk + chunk) * kPartialStride + lane] = mine;
 }
 
 // ---------------------------------------------------------------- 2D update, marching in y
@@ -1187,12 +1189,12 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
 template <typename T>
 __global__ void k_state_from_freestream(Dev d, int buf, int A, const double *u, double amp, long long off, long long n)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    long long g = off + i;
-    int k = (int)(g % d.NV);
-    double v = d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0));
-    ((T *)d.f[buf][A])[g] = (T)v;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const long long g = off + i;
+        const int k = (int)(g % d.NV);
+        const double v = d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0));
+        ((T *)d.f[buf][A])[g] = (T)v;
+    }
 }
 
 // freestream times (1 + amp u) with u uniform on (-1, 1) from a counter-based
@@ -1211,27 +1213,25 @@ __device__ __forceinline__ double hashed_uniform(unsigned long long seed, unsign
 template <typename T>
 __global__ void k_state_hashed(Dev d, int buf, int A, unsigned long long seed, double amp, long long n)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int k = (int)(i % d.NV);
-    const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
-    ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(i % d.NV);
+        const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
+        ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
+    }
 }
 
 template <typename T>
 __global__ void k_state_set(Dev d, int buf, int A, const double *src, long long off, long long n)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    ((T *)d.f[buf][A])[off + i] = (T)src[i];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        ((T *)d.f[buf][A])[off + i] = (T)src[i];
 }
 
 template <typename T>
 __global__ void k_state_get(Dev d, int buf, int A, double *dst, long long off, long long n)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    dst[i] = (double)((const T *)d.f[buf][A])[off + i];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (double)((const T *)d.f[buf][A])[off + i];
 }
 
 __global__ void k_ctrl_reset(Ctrl *c, int slot)
@@ -1285,11 +1285,18 @@ __global__ void k_moments_out(Dev d, double *out)
     } while (0)
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+// grid of a grid-stride loop: a dispatch carries at most 2^32 - 1 work-items
+// per dimension, so large element counts loop instead of widening the grid
+static inline unsigned stride_blocks(long long n, int bs)
+{
+    const long long b = (n + bs - 1) / bs;
+    return (unsigned)(b < (1ll << 20) ? (b > 0 ? b : 1) : (1ll << 20));
+}
 
 hipError_t launch_update(const Dev &d, int storage, int cur, int slot, hipStream_t s)
 {
     long long waves = (long long)d.Nc * d.nchunk;
-    DISPATCH(d.D, storage, hipLaunchKernelGGL((k_update<DD, TT>), dim3(blocks_for(waves, 4)), dim3(256), 0, s, d, cur, slot));
+    DISPATCH(d.D, storage, hipLaunchKernelGGL((k_update<DD, TT>), dim3(stride_blocks(waves, 4)), dim3(256), 0, s, d, cur, slot));
     return hipGetLastError();
 }
 
@@ -1355,9 +1362,9 @@ hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, co
                                    long long n, hipStream_t s)
 {
     if (storage == 0)
-        hipLaunchKernelGGL(k_state_from_freestream<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
+        hipLaunchKernelGGL(k_state_from_freestream<double>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
     else
-        hipLaunchKernelGGL(k_state_from_freestream<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
+        hipLaunchKernelGGL(k_state_from_freestream<float>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, u, amp, off, n);
     return hipGetLastError();
 }
 
@@ -1366,9 +1373,9 @@ hipError_t launch_state_hashed(const Dev &d, int storage, int buf, int A, unsign
 {
     const long long n = (long long)d.Nc * d.NV;
     if (storage == 0)
-        hipLaunchKernelGGL(k_state_hashed<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
+        hipLaunchKernelGGL(k_state_hashed<double>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
     else
-        hipLaunchKernelGGL(k_state_hashed<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
+        hipLaunchKernelGGL(k_state_hashed<float>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, seed, amp, n);
     return hipGetLastError();
 }
 
@@ -1376,9 +1383,9 @@ hipError_t launch_state_set(const Dev &d, int storage, int buf, int A, const dou
                             hipStream_t s)
 {
     if (storage == 0)
-        hipLaunchKernelGGL(k_state_set<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, src, off, n);
+        hipLaunchKernelGGL(k_state_set<double>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, src, off, n);
     else
-        hipLaunchKernelGGL(k_state_set<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, src, off, n);
+        hipLaunchKernelGGL(k_state_set<float>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, src, off, n);
     return hipGetLastError();
 }
 
@@ -1386,9 +1393,9 @@ hipError_t launch_state_get(const Dev &d, int storage, int buf, int A, double *d
                             hipStream_t s)
 {
     if (storage == 0)
-        hipLaunchKernelGGL(k_state_get<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, dst, off, n);
+        hipLaunchKernelGGL(k_state_get<double>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, dst, off, n);
     else
-        hipLaunchKernelGGL(k_state_get<float>, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, buf, A, dst, off, n);
+        hipLaunchKernelGGL(k_state_get<float>, dim3(stride_blocks(n, 256)), dim3(256), 0, s, d, buf, A, dst, off, n);
     return hipGetLastError();
 }
 
