@@ -460,6 +460,133 @@ __global__ __launch_bounds__(256) void k_moments_direct(Dev d, int cur, int slot
 }
 
 // ---------------------------------------------------------------- update
+
+// ---------------------------------------------------------------- 2D update, marching in y
+// Workgroup = TX wavefronts; wavefront w owns grid column i0 + w and its lanes
+// own velocity nodes k0 + lane + 64 v (v < V).  The workgroup marches up a
+// segment of rows.  Rows j-2..j+2 of the own column live in registers; row j
+// of the TX columns plus two halo columns per side is exchanged through LDS
+// (double-buffered by row parity), the x slopes of the TX + 2 cells the faces
+// need are computed once per row and shared through LDS, and the y slope of
+// row j+1 and the flux state of face j+1/2 are carried to the next row.  Outer
+// freestream ghosts are the freestream values (zero slope follows from the
+// limiter); periodic ghosts wrap.  Solid face neighbours are replaced by the
+// ghost value of the pair seen from the fluid cell, and faces toward a solid
+// cell take the pair's ghost-side face value.
+
+// cross-lane helpers on doubles (two 32-bit halves each)
+__device__ __forceinline__ double mk_dbl(unsigned hi, unsigned lo)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// v_permlane32_swap: the upper 32 lanes of x trade places with the lower 32
+// lanes of y
+__device__ __forceinline__ void swap32(double &x, double &y)
+{
+    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = mk_dbl(hi[0], lo[0]);
+    y = mk_dbl(hi[1], lo[1]);
+}
+
+// v_permlane16_swap: within each 32-lane half, lanes 16..31 of x trade places
+// with lanes 0..15 of y
+__device__ __forceinline__ void swap16(double &x, double &y)
+{
+    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
+    x = mk_dbl(hi[0], lo[0]);
+    y = mk_dbl(hi[1], lo[1]);
+}
+
+// DPP rotation within 16-lane rows
+template <int CTRL>
+__device__ __forceinline__ double dpp(double x)
+{
+    unsigned long long b = __double_as_longlong(x);
+    unsigned lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    unsigned hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return mk_dbl(hi, lo);
+}
+constexpr int kRowRor1 = 0x121, kRowRor2 = 0x122, kRowRor4 = 0x124, kRowRor8 = 0x128;
+
+// sums S[0..8] over the 64 lanes.  Three exchange steps halve the number of
+// values each lane carries (after them lane l holds value 4 b5 + 2 b4 + b3
+// summed over the 8 lanes that share bits 0..2), three rotate-and-add steps
+// finish the sums in lanes 8m + 7 (whose sources stay inside their group).  On return lane 8m + 7 holds the total of
+// S[m] for m < 8 and lanes 7 and 15 hold the total of S[8].
+__device__ __forceinline__ void reduce9(const double S[9], double &r8, double &s8)
+{
+    const int lane = threadIdx.x & 63;
+    double a[4], b[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double x = S[i], y = S[4 + i];
+        swap32(x, y);
+        a[i] = x + y;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        double x = a[i], y = a[2 + i];
+        swap16(x, y);
+        b[i] = x + y;
+    }
+    const bool b3 = lane & 8;
+    double c = (b3 ? b[1] : b[0]) + dpp<kRowRor8>(b3 ? b[0] : b[1]);
+    c += dpp<kRowRor4>(c);
+    c += dpp<kRowRor2>(c);
+    c += dpp<kRowRor1>(c);
+    r8 = c;
+    double s = S[8], t = S[8];
+    swap32(s, t);
+    s += t;
+    t = s;
+    swap16(s, t);
+    s += t;
+    s += dpp<kRowRor8>(s);
+    s += dpp<kRowRor4>(s);
+    s += dpp<kRowRor2>(s);
+    s += dpp<kRowRor1>(s);
+    s8 = s;
+}
+
+// sums S[0..15] over the 64 lanes with the exchange steps of reduce9 stopped
+// one step earlier: afterwards lane l carries S[2 g + i] for i = 0, 1 and
+// g = (l >> 3) & 7, summed over the lanes that share bits 3..5; three
+// rotate-and-add steps finish both sums in lanes 8 g + 7 (out[0], out[1]).
+__device__ __forceinline__ void reduce16(const double S[16], double out[2])
+{
+    const int lane = threadIdx.x & 63;
+    double a[8], b[4];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        double x = S[i], y = S[8 + i];
+        swap32(x, y);
+        a[i] = x + y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double x = a[i], y = a[4 + i];
+        swap16(x, y);
+        b[i] = x + y;
+    }
+    const bool b3 = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        double c = (b3 ? b[2 + i] : b[i]) + dpp<kRowRor8>(b3 ? b[i] : b[2 + i]);
+        c += dpp<kRowRor4>(c);
+        c += dpp<kRowRor2>(c);
+        c += dpp<kRowRor1>(c);
+        out[i] = c;
+    }
+}
+
+// ---------------------------------------------------------------- generic update
+// One wavefront per (cell, 64-node chunk), neighbours read directly; the 3D
+// update (the 2D one marches, below).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
 {
@@ -586,106 +713,26 @@ __global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
         int o = 2 + 2 * D;
         for (int a = 0; a < D; ++a)
             for (int b = a; b < D; ++b) S[o++] = wk * cc[a] * cc[b] * h;
-        double mine = 0.0;
-    #pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            double v = wave_sum(S[j]);
-            if (lane == j) mine = v;
+        double *pp = d.part + ((size_t)c * d.nchunk + chunk) * kPartialStride;
+        if (D == 3) {
+            // 14 words, transposed: lane 8 g + 7 holds words 2 g and 2 g + 1
+            double S16[16], r[2];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) S16[j] = j < PW ? S[j] : 0.0;
+            reduce16(S16, r);
+            const int g = lane >> 3;
+            if ((lane & 7) == 7 && 2 * g < PW) pp[2 * g] = r[0];
+            if ((lane & 7) == 7 && 2 * g + 1 < PW) pp[2 * g + 1] = r[1];
+        } else {
+            double mine = 0.0;
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                double v = wave_sum(S[j]);
+                if (lane == j) mine = v;
+            }
+            if (lane < PW) pp[lane] = mine;
         }
-        if (lane < PW) d.part[((size_t)c * d.nchunk + chunk) * kPartialStride + lane] = mine;
     }
-}
-
-// ---------------------------------------------------------------- 2D update, marching in y
-// Workgroup = TX wavefronts; wavefront w owns grid column i0 + w and its lanes
-// own velocity nodes k0 + lane + 64 v (v < V).  The workgroup marches up a
-// segment of rows.  Rows j-2..j+2 of the own column live in registers; row j
-// of the TX columns plus two halo columns per side is exchanged through LDS
-// (double-buffered by row parity), the x slopes of the TX + 2 cells the faces
-// need are computed once per row and shared through LDS, and the y slope of
-// row j+1 and the flux state of face j+1/2 are carried to the next row.  Outer
-// freestream ghosts are the freestream values (zero slope follows from the
-// limiter); periodic ghosts wrap.  Solid face neighbours are replaced by the
-// ghost value of the pair seen from the fluid cell, and faces toward a solid
-// cell take the pair's ghost-side face value.
-
-// cross-lane helpers on doubles (two 32-bit halves each)
-__device__ __forceinline__ double mk_dbl(unsigned hi, unsigned lo)
-{
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// v_permlane32_swap: the upper 32 lanes of x trade places with the lower 32
-// lanes of y
-__device__ __forceinline__ void swap32(double &x, double &y)
-{
-    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
-    auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bx, (unsigned)by, false, false);
-    auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
-    x = mk_dbl(hi[0], lo[0]);
-    y = mk_dbl(hi[1], lo[1]);
-}
-
-// v_permlane16_swap: within each 32-lane half, lanes 16..31 of x trade places
-// with lanes 0..15 of y
-__device__ __forceinline__ void swap16(double &x, double &y)
-{
-    unsigned long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
-    auto lo = __builtin_amdgcn_permlane16_swap((unsigned)bx, (unsigned)by, false, false);
-    auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(bx >> 32), (unsigned)(by >> 32), false, false);
-    x = mk_dbl(hi[0], lo[0]);
-    y = mk_dbl(hi[1], lo[1]);
-}
-
-// DPP rotation within 16-lane rows
-template <int CTRL>
-__device__ __forceinline__ double dpp(double x)
-{
-    unsigned long long b = __double_as_longlong(x);
-    unsigned lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xf, 0xf, false);
-    unsigned hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
-    return mk_dbl(hi, lo);
-}
-constexpr int kRowRor1 = 0x121, kRowRor2 = 0x122, kRowRor4 = 0x124, kRowRor8 = 0x128;
-
-// sums S[0..8] over the 64 lanes.  Three exchange steps halve the number of
-// values each lane carries (after them lane l holds value 4 b5 + 2 b4 + b3
-// summed over the 8 lanes that share bits 0..2), three rotate-and-add steps
-// finish the sums in lanes 8m + 7 (whose sources stay inside their group).  On return lane 8m + 7 holds the total of
-// S[m] for m < 8 and lanes 7 and 15 hold the total of S[8].
-__device__ __forceinline__ void reduce9(const double S[9], double &r8, double &s8)
-{
-    const int lane = threadIdx.x & 63;
-    double a[4], b[2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        double x = S[i], y = S[4 + i];
-        swap32(x, y);
-        a[i] = x + y;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        double x = a[i], y = a[2 + i];
-        swap16(x, y);
-        b[i] = x + y;
-    }
-    const bool b3 = lane & 8;
-    double c = (b3 ? b[1] : b[0]) + dpp<kRowRor8>(b3 ? b[0] : b[1]);
-    c += dpp<kRowRor4>(c);
-    c += dpp<kRowRor2>(c);
-    c += dpp<kRowRor1>(c);
-    r8 = c;
-    double s = S[8], t = S[8];
-    swap32(s, t);
-    s += t;
-    t = s;
-    swap16(s, t);
-    s += t;
-    s += dpp<kRowRor8>(s);
-    s += dpp<kRowRor4>(s);
-    s += dpp<kRowRor2>(s);
-    s += dpp<kRowRor1>(s);
-    s8 = s;
 }
 
 // barrier for LDS traffic only: global loads issued before it stay in flight
