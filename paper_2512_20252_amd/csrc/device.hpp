@@ -8,8 +8,8 @@ namespace ibdvm {
 // or outside the grid; and one bit per face neighbour that is solid
 // (x-, x+, y-, y+, z-, z+)
 enum CellFlag : uint8_t { CF_SOLID = 1, CF_NEAR = 2, CF_XM = 4, CF_XP = 8, CF_YM = 16, CF_YP = 32, CF_ZM = 64, CF_ZP = 128 };
-// device flag words add: the cell two steps along -x / +x is solid
-constexpr int CF_XM2 = 256, CF_XP2 = 512;
+// device flag words add: the cell two steps along -x / +x (-y / +y) is solid
+constexpr int CF_XM2 = 256, CF_XP2 = 512, CF_YM2 = 1024, CF_YP2 = 2048;
 
 // per-(cell, velocity chunk) partial moments of the new state, relative to
 // the reference velocity U of the old state: m0, m1[D], m2, m3[D], M2[D(D+1)/2]
@@ -19,9 +19,10 @@ constexpr int kPartialStride = 16;
 // per-cell parameter words: U[3], A, 1/T, s[3], T/2, 1/tau, rho, T, q[3], tau
 constexpr int kCellWords = 16;
 enum CellWord { CW_U = 0, CW_A = 3, CW_INVT = 4, CW_S = 5, CW_TH = 8, CW_INVTAU = 9, CW_RHO = 10, CW_T = 11, CW_Q = 12, CW_TAU = 15 };
-// per-cell record of the 2D update, one contiguous 80-byte load: U0, U1, A,
-// 1/T, s0, s1, T/2, 1/tau, then the flag word of the cell above (low half of
-// word 8; 0 on the top row) and a pad word
+// per-cell record of the marching updates, one contiguous 80-byte load.
+// 2D: U0, U1, A, 1/T, s0, s1, T/2, 1/tau, then the flag word of the cell
+// above (low half of word 8; 0 on the top row) and a pad word.  3D: U[3], A,
+// 1/T, s[3], 1/tau, then the flag word of the cell above in z (word 9).
 constexpr int kQWords = 10;
 
 constexpr int kChunk = 64;       // velocity nodes per wavefront

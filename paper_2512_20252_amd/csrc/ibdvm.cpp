@@ -54,7 +54,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     for (int b = 0; b < 2; ++b)
         for (int A = 0; A < 2; ++A) L.f[b][A] = A < NA ? take(nf * es) : 0;
     L.cellp = take((size_t)g.Nc * ibdvm::kCellWords * 8);
-    L.cellq = take(g.D == 2 ? (size_t)g.Nc * ibdvm::kQWords * 8 : 0);
+    L.cellq = take((size_t)g.Nc * ibdvm::kQWords * 8);
     L.part = take((size_t)g.Nc * nchunk * ibdvm::kPartialStride * 8);
     L.xi = take((size_t)3 * g.NV * 8);
     L.xa = take((size_t)3 * ibdvm::kMaxVn * 8);
@@ -250,7 +250,7 @@ ibdvm_status one_step(ibdvm_ctx *c)
     if (c->prob.dim == 2)
         HIP_CHECK(ibdvm::launch_update2d(c->dev, c->precision, c->cur, slot, c->tile, c->stream));
     else
-        HIP_CHECK(ibdvm::launch_update(c->dev, c->precision, c->cur, slot, c->stream));
+        HIP_CHECK(ibdvm::launch_update3d(c->dev, c->precision, c->cur, slot, c->tile, c->stream));
     if ((st = mark(c, 0))) return st;
     c->cur ^= 1;
     c->step += 1;
@@ -444,8 +444,11 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.D = D;
     d.NA = c->NA;
     d.NV = NV;
-    c->tile = c->precision == IBDVM_F32_STORE ? ibdvm::Tile{2, 8, 64} : ibdvm::Tile{1, 8, 64};
-    d.nchunk = D == 2 ? (NV + 64 * c->tile.V - 1) / (64 * c->tile.V) : (NV + ibdvm::kChunk - 1) / ibdvm::kChunk;
+    if (D == 2)
+        c->tile = c->precision == IBDVM_F32_STORE ? ibdvm::Tile{2, 8, 64} : ibdvm::Tile{1, 8, 64};
+    else
+        c->tile = ibdvm::Tile{1, 4, 256};
+    d.nchunk = (NV + 64 * c->tile.V - 1) / (64 * c->tile.V);
     d.Nc = g.Nc;
     d.npairs = (int)np;
     d.outer = c->prob.outer;
@@ -516,23 +519,31 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (e == hipSuccess)
         e = c->precision == IBDVM_F32_STORE ? up(L.fsT, fs32.data(), fs32.size() * 4) : up(L.fsT, fs.data(), fs.size() * 8);
     std::vector<int> cflag32(g.cflag.begin(), g.cflag.end());
-    if (D == 2) {
-        // second neighbours along x, and the 2D update records with the
-        // flag word of the cell above (parameters are written on device)
-        const int nx = c->prob.n[0], ny = c->prob.n[1];
-        auto solid = [&](int i, int j) { return i >= 0 && i < nx && (g.cflag[i + nx * j] & ibdvm::CF_SOLID); };
+    {
+        // second neighbours along x (and y in 3D), and the update records with
+        // the flag word of the cell above along the marching axis (y in 2D, z
+        // in 3D; the parameters are written on device)
+        const int nx = c->prob.n[0], ny = c->prob.n[1], nz = D == 3 ? c->prob.n[2] : 1;
+        const size_t nxy = (size_t)nx * ny;
+        auto solid = [&](int i, int j, int k) {
+            return i >= 0 && i < nx && j >= 0 && j < ny && (g.cflag[i + nx * j + nxy * k] & ibdvm::CF_SOLID);
+        };
         std::vector<double> qrec((size_t)g.Nc * ibdvm::kQWords, 0.0);
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                int &f = cflag32[i + nx * j];
-                if (solid(i - 2, j)) f |= ibdvm::CF_XM2;
-                if (solid(i + 2, j)) f |= ibdvm::CF_XP2;
-            }
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                const int up_flags = j + 1 < ny ? cflag32[i + nx * (j + 1)] : 0;
-                std::memcpy(&qrec[(size_t)(i + nx * j) * ibdvm::kQWords + 8], &up_flags, 4);
-            }
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int &f = cflag32[i + nx * j + nxy * k];
+                    if (solid(i - 2, j, k)) f |= ibdvm::CF_XM2;
+                    if (solid(i + 2, j, k)) f |= ibdvm::CF_XP2;
+                    if (D == 3 && solid(i, j - 2, k)) f |= ibdvm::CF_YM2;
+                    if (D == 3 && solid(i, j + 2, k)) f |= ibdvm::CF_YP2;
+                }
+        const size_t up_stride = D == 2 ? (size_t)nx : nxy;
+        const size_t up_word = D == 2 ? 8 : 9;
+        for (size_t cc = 0; cc < (size_t)g.Nc; ++cc) {
+            const int up_flags = cc + up_stride < (size_t)g.Nc ? cflag32[cc + up_stride] : 0;
+            std::memcpy(&qrec[cc * ibdvm::kQWords + up_word], &up_flags, 4);
+        }
         if (e == hipSuccess) e = up(L.cellq, qrec.data(), qrec.size() * 8);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
@@ -828,12 +839,19 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
 }
 
 namespace {
-bool tile_supported(int precision, const ibdvm::Tile &t)
+// 2D: TX 4 or 8 columns; 3D: a 4 x 4 tile of columns (TX = 4)
+bool tile_supported(int dim, const ibdvm::Tile &t)
 {
-    bool tx = t.TX == 4 || t.TX == 8;
+    bool tx = dim == 2 ? (t.TX == 4 || t.TX == 8) : t.TX == 4;
     bool v = t.V == 1 || t.V == 2;
-    (void)precision;
     return tx && v && t.LY >= 1 && t.LY <= 256;
+}
+
+hipError_t launch_update_tile(const ibdvm::Dev &d, int dim, int precision, int cur, int slot, const ibdvm::Tile &t,
+                              hipStream_t s)
+{
+    return dim == 2 ? ibdvm::launch_update2d(d, precision, cur, slot, t, s)
+                    : ibdvm::launch_update3d(d, precision, cur, slot, t, s);
 }
 }  // namespace
 
@@ -841,9 +859,8 @@ ibdvm_status ibdvm_set_tile(ibdvm_ctx *c, int32_t V, int32_t TX, int32_t LY)
 {
     ibdvm_status st = require_device(c);
     if (st) return st;
-    if (c->prob.dim != 2) return fail(IBDVM_E_UNSUPPORTED, "tile choice applies to 2D problems");
     ibdvm::Tile t{V, TX, LY};
-    if (!tile_supported(c->precision, t)) return fail(IBDVM_E_INVALID_ARG, "unsupported tile");
+    if (!tile_supported(c->prob.dim, t)) return fail(IBDVM_E_INVALID_ARG, "unsupported tile");
     HIP_CHECK(hipSetDevice(c->device));
     if ((st = finish_pending(c))) return st;
     c->tile = t;
@@ -864,7 +881,6 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
 {
     ibdvm_status st = require_device(c);
     if (st) return st;
-    if (c->prob.dim != 2) return fail(IBDVM_E_UNSUPPORTED, "tile choice applies to 2D problems");
     if (reps < 1) return fail(IBDVM_E_INVALID_ARG, "reps must be positive");
     HIP_CHECK(hipSetDevice(c->device));
     if ((st = finish_pending(c))) return st;
@@ -880,17 +896,19 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
     hipEvent_t e0, e1;
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
-    const int Vs[2] = {1, 2}, TXs[2] = {4, 8}, LYs[3] = {32, 64, 120};
+    const int dim = c->prob.dim;
+    const int Vs[2] = {1, 2}, TXs[2] = {4, 8};
+    const int LYs[3] = {dim == 2 ? 32 : 16, dim == 2 ? 64 : 48, dim == 2 ? 120 : 256};
     for (int V : Vs)
         for (int TX : TXs)
             for (int LY : LYs) {
                 ibdvm::Tile t{V, TX, LY};
-                if (!tile_supported(c->precision, t)) continue;
+                if (!tile_supported(dim, t)) continue;
                 ibdvm::Dev d = c->dev;
                 d.nchunk = (c->geo.NV + 64 * V - 1) / (64 * V);
-                HIP_CHECK(ibdvm::launch_update2d(d, c->precision, c->cur, slot, t, c->stream));
+                HIP_CHECK(launch_update_tile(d, dim, c->precision, c->cur, slot, t, c->stream));
                 HIP_CHECK(hipEventRecord(e0, c->stream));
-                for (int r = 0; r < reps; ++r) HIP_CHECK(ibdvm::launch_update2d(d, c->precision, c->cur, slot, t, c->stream));
+                for (int r = 0; r < reps; ++r) HIP_CHECK(launch_update_tile(d, dim, c->precision, c->cur, slot, t, c->stream));
                 HIP_CHECK(hipEventRecord(e1, c->stream));
                 HIP_CHECK(hipEventSynchronize(e1));
                 float ms = 0.f;

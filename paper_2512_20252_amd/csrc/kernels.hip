@@ -108,6 +108,18 @@ __device__ double write_cell(const Dev &d, int c, double rho, const double U[3],
         k2[5] = coef * q[1];
         k2[6] = 0.5 * T;
         k2[7] = 1.0 / tau;
+    } else {
+        // 3D update record: U[3], A, 1/T, s[3], 1/tau (word 9: flag word of the cell above)
+        double *k3 = d.cellq + (size_t)c * kQWords;
+        k3[0] = U[0];
+        k3[1] = U[1];
+        k3[2] = U[2];
+        k3[3] = A;
+        k3[4] = 1.0 / T;
+        k3[5] = coef * q[0];
+        k3[6] = coef * q[1];
+        k3[7] = coef * q[2];
+        k3[8] = 1.0 / tau;
     }
     bool bad = !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite(tau);
     if (bad) atomicOr(&d.ctrl->health, 1u);
@@ -749,6 +761,7 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // read-only tables indexed by wavefront-uniform values go through the
 // scalar cache (constant address space): the loads land in scalar registers
 typedef const __attribute__((address_space(4))) int *cint_p;
+typedef const __attribute__((address_space(4))) double *cdbl_p;
 
 // ---------------------------------------------------------------- 2D update
 //
@@ -1195,6 +1208,410 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
     }
 }
 
+// ---------------------------------------------------------------- 3D update, marching in z
+//
+// One workgroup = 16 wavefronts on a 4 x 4 tile of grid columns (i0 + tx,
+// j0 + ty), a segment of planes k0..k1-1 and one chunk of 64 V velocity
+// nodes.  Each wavefront marches its column in z: planes k..k+2 of the own
+// column are held in registers and plane k+3 arrives one plane ahead, so the
+// z slope of plane k+1 and the flux state of face k+1/2 are carried to the
+// next plane as in the 2D update.  Plane k of the tile and of the two halo
+// cells on each side along x and y (the cross-shaped stencil) is staged in
+// LDS; each wavefront forms the outgoing x and y states of its own cell and
+// the outgoing state of one of the 16 halo cells next to the tile (their
+// flags follow from those of the adjacent tile cell), and the faces take the
+// upwind neighbour's state from LDS.  Immersed-boundary substitutions are
+// those of the 2D update with the z pair directions 4 and 5 added.
+// outgoing state f + sign(xi) h toward the downwind face: the sign bit of
+// the node velocity is XORed into h instead of multiplying by a stored +-1
+__device__ __forceinline__ double ostate(double h, double f, double xi)
+{
+    const unsigned long long s = __builtin_bit_cast(unsigned long long, xi) & 0x8000000000000000ull;
+    return f + __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, h) ^ s);
+}
+__device__ __forceinline__ float ostate(float h, float f, double xi)
+{
+    const unsigned s = (unsigned)(__builtin_bit_cast(unsigned long long, xi) >> 32) & 0x80000000u;
+    return f + __builtin_bit_cast(float, __builtin_bit_cast(unsigned, h) ^ s);
+}
+
+constexpr int kT3 = 4;  // tile edge along x and y
+
+// staged plane: slot of tile position (x, y), x, y in [-2, 6), on the cross
+// (rows 0..3 with two halo columns per side: 8 slots each; then the two halo
+// rows below and above, 4 slots each)
+__device__ __forceinline__ int xslot(int x, int y)
+{
+    return (y >= 0 && y < kT3) ? y * (kT3 + 4) + x + 2 : kT3 * (kT3 + 4) + (y < 0 ? y + 2 : y - kT3 + 2) * kT3 + x;
+}
+constexpr int kXSlots = kT3 * (kT3 + 4) + 4 * kT3;
+
+template <typename T, int V>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int ncv)
+{
+    constexpr int W = 64 * V;
+    constexpr int ST = (int)sizeof(T);
+    constexpr int NEAROWN = CF_SOLID | CF_XM | CF_XP | CF_YM | CF_YP;
+    constexpr int NEARALL = NEAROWN | CF_ZM | CF_ZP;
+    __shared__ T fb[kXSlots][W];
+    __shared__ T obx[kT3][kT3 + 2][W];  // outgoing x states, x in [-1, 4]
+    __shared__ T oby[kT3 + 2][kT3][W];  // outgoing y states, y in [-1, 4]
+    __shared__ int flw[kT3 * kT3];
+    __shared__ double etab[32];
+    if (threadIdx.x < 32) etab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 32));
+
+    const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
+    const double dt = d.cfl / (d.adv + 1.0 / tmin);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.ctrl->tau_bits[slot ^ 1] = kInfBits;
+        d.ctrl->dt = dt;
+        d.ctrl->time += dt;
+        d.ctrl->step += 1;
+    }
+    // contiguous runs of tiles per XCD (workgroups go round-robin over the 8)
+    const int nb = gridDim.x;
+    const int L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
+    if (L >= ntx * nty * nzs * ncv) return;
+    const int tX = L % ntx, tY = (L / ntx) % nty, zs = (L / (ntx * nty)) % nzs, ch = L / (ntx * nty * nzs);
+    const int nx = d.n[0], ny = d.n[1], nz = d.n[2], NV = d.NV;
+    const int i0 = tX * kT3, j0 = tY * kT3, k0 = zs * LZ, k1 = min(k0 + LZ, nz);
+    const int lane = threadIdx.x & 63;
+    const int w = uni(threadIdx.x >> 6);
+    const int tx = w & 3, ty = w >> 2;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool col_in = i < nx && j < ny;
+    const bool per = d.outer != 0;
+    const int rowb = NV * ST;
+    const size_t nxy = (size_t)nx * ny;
+    const size_t pstride = nxy * (size_t)rowb;
+
+    // first velocity row of grid column (ic, jc); fs: outside the grid and
+    // not periodic, so the column reads the freestream row
+    auto column = [&](int ic, int jc, bool &fs) -> size_t {
+        fs = !per && (ic < 0 || ic >= nx || jc < 0 || jc >= ny);
+        ic = ic < 0 ? ic + nx : (ic >= nx ? ic - nx : ic);
+        jc = jc < 0 ? jc + ny : (jc >= ny ? jc - ny : jc);
+        return ((size_t)ic + (size_t)nx * jc) * rowb;
+    };
+    auto planep = [&](const char *base, size_t col, bool cfs, const char *fsr, int kr) -> const char * {
+        const bool in = kr >= 0 && kr < nz;
+        const int kw = kr < 0 ? kr + nz : (kr >= nz ? kr - nz : kr);
+        return (cfs || (!in && !per)) ? fsr : base + col + (size_t)(unsigned)kw * pstride;
+    };
+    auto ldflag = [&](int kr) -> int {
+        const bool in = col_in && kr >= 0 && kr < nz;
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(
+            mk_rsrc(d.cflag + (in ? (size_t)i + (size_t)nx * j + nxy * kr : 0), in ? 4 : 0), 0, 0, 0);
+    };
+    int koff[V];
+    double xv[3][V], wk[V];
+    bool pos[3][V];
+    const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1], idz = (T)d.inv_dx[2];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int k = ch * W + v * 64 + lane;
+        const int kc = min(k, NV - 1);
+        koff[v] = k * ST;
+        wk[v] = k < NV ? d.w[kc] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xv[a][v] = d.xi[a][kc];
+            pos[a][v] = xv[a][v] > 0.0;
+        }
+    }
+
+    // cell record of (i, j, kr): update parameters and the flag word of the
+    // cell above
+    auto ldrec = [&](int kr, double (&P)[9], int &fup) {
+        // wavefront-uniform: scalar loads into scalar registers
+        const bool in = col_in && kr < nz;
+        const size_t cc = in ? (size_t)i + (size_t)nx * j + nxy * kr : 0;
+        const cdbl_p q = (cdbl_p)(d.cellq + cc * kQWords);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) P[m] = q[m];
+        fup = in ? ((cint_p)q)[18] : 0;
+    };
+
+    const char *fcur = (const char *)d.f[cur][0];
+    const char *fsr = (const char *)d.fsT[0];
+    char *fnext = (char *)d.f[cur ^ 1][0];
+    bool cfs;
+    const size_t ccol = column(i, j, cfs);
+    // halo cells staged by this wavefront: one of the x halo (columns -2, -1,
+    // 4, 5 of row ty) and one of the y halo (rows -2, -1, 4, 5 of column tx)
+    const int hxx = (tx < 2 ? tx - 2 : tx + 2), hyy = (ty < 2 ? ty - 2 : ty + 2);
+    bool hxfs, hyfs;
+    const size_t hxcol = column(i0 + hxx, j, hxfs), hycol = column(i, j0 + hyy, hyfs);
+    const int sown = xslot(tx, ty), shx = xslot(hxx, ty), shy = xslot(tx, hyy);
+    // halo cell whose outgoing state this wavefront forms: w < 8 the x halo
+    // cell (-1 or 4, w & 3), else the y halo cell (w & 3, -1 or 4); adj is the
+    // tile cell next to it
+    const bool hox = w < 8;
+    const int hside = (w >> 2) & 1, hq = w & 3;
+    const int hx = hox ? (hside ? kT3 : -1) : hq, hy = hox ? hq : (hside ? kT3 : -1);
+    const int adj = hox ? hq * kT3 + (hside ? kT3 - 1 : 0) : (hside ? kT3 - 1 : 0) * kT3 + hq;
+    const int hdc = hox ? (hside ? 1 : -1) : (hside ? nx : -nx);  // halo cell - adjacent cell
+
+    T R[4][V], OZ[2][V], FD[2][V], HX[2][V], HY[2][V];
+    double P[9];
+    int FL0, fup;
+    {
+        T fm2[V], fm1[V];
+        const brsrc r0 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 - 2), rowb);
+        const brsrc r1 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 - 1), rowb);
+        const brsrc r2 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0), rowb);
+        const brsrc r3 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 + 1), rowb);
+        const brsrc r4 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 + 2), rowb);
+        const brsrc rx = mk_rsrc(planep(fcur, hxcol, hxfs, fsr, k0), rowb);
+        const brsrc ry = mk_rsrc(planep(fcur, hycol, hyfs, fsr, k0), rowb);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            fm2[v] = bld(r0, koff[v], T());
+            fm1[v] = bld(r1, koff[v], T());
+            R[0][v] = bld(r2, koff[v], T());
+            R[1][v] = bld(r3, koff[v], T());
+            R[2][v] = bld(r4, koff[v], T());
+            HX[0][v] = bld(rx, koff[v], T());
+            HY[0][v] = bld(ry, koff[v], T());
+        }
+        const int flm1 = uni(ldflag(k0 - 1));
+        FL0 = uni(ldflag(k0));
+        ldrec(k0, P, fup);
+        const int c0 = (int)((size_t)i + (size_t)nx * j + nxy * k0);
+        const int cm = c0 - (int)nxy;
+        // outgoing z states of planes k0-1 and k0, and the face k0-1/2
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int k8 = koff[v] * (8 / ST);
+            T fm = fm2[v], fp = R[0][v];
+            if (flm1 & CF_ZM) fm = ghost_at<T>(d, 0, cm, 4, k8);
+            if (flm1 & CF_ZP) fp = ghost_at<T>(d, 0, cm, 5, k8);
+            const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[v] - fm, fp - fm1[v]);
+            const T ozm = ostate(hm, fm1[v], xv[2][v]);
+            fm = fm1[v];
+            fp = R[1][v];
+            if (FL0 & CF_ZM) fm = ghost_at<T>(d, 0, c0, 4, k8);
+            if (FL0 & CF_ZP) fp = ghost_at<T>(d, 0, c0, 5, k8);
+            const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][v] - fm, fp - R[0][v]);
+            OZ[0][v] = ostate(h0, R[0][v], xv[2][v]);
+            T F;
+            if (pos[2][v])
+                F = !(flm1 & CF_SOLID) ? ozm : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c0, 4, k8));
+            else
+                F = !(FL0 & CF_SOLID) ? OZ[0][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, cm, 5, k8));
+            FD[0][v] = F;
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+
+    int k = k0;
+    auto plane = [&](auto S_) {
+        constexpr int S = decltype(S_)::value;
+        T(&f0)[V] = R[S & 3];
+        T(&f1)[V] = R[(S + 1) & 3];
+        T(&f2)[V] = R[(S + 2) & 3];
+        T(&f3)[V] = R[(S + 3) & 3];
+        T(&oz0)[V] = OZ[S & 1];
+        T(&oz1)[V] = OZ[(S + 1) & 1];
+        T(&Fdn)[V] = FD[S & 1];
+        T(&Fup)[V] = FD[(S + 1) & 1];
+        T(&hxc)[V] = HX[S & 1];
+        T(&hxn)[V] = HX[(S + 1) & 1];
+        T(&hyc)[V] = HY[S & 1];
+        T(&hyn)[V] = HY[(S + 1) & 1];
+        const int c = (int)((size_t)i + (size_t)nx * j + nxy * k);
+
+        // prefetch: own column plane k+3, halo cells plane k+1
+        {
+            const brsrc r3 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k + 3), rowb);
+            const brsrc rx = mk_rsrc(planep(fcur, hxcol, hxfs, fsr, k + 1), rowb);
+            const brsrc ry = mk_rsrc(planep(fcur, hycol, hyfs, fsr, k + 1), rowb);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                f3[v] = bld(r3, koff[v], T());
+                hxn[v] = bld(rx, koff[v], T());
+                hyn[v] = bld(ry, koff[v], T());
+            }
+        }
+        // stage plane k
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            fb[sown][v * 64 + lane] = f0[v];
+            fb[shx][v * 64 + lane] = hxc[v];
+            fb[shy][v * 64 + lane] = hyc[v];
+        }
+        if (lane == 0) flw[w] = FL0;
+        lds_barrier();
+
+        // outgoing x and y states of the own cell
+        T ox[V], oy[V];
+        auto own = [&](auto near_tag) {
+            constexpr bool NEAR = decltype(near_tag)::value;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k8 = koff[v] * (8 / ST);
+                const T fc = f0[v];
+                T fm = fb[sown - 1][v * 64 + lane], fp = fb[sown + 1][v * 64 + lane];
+                if (NEAR && (FL0 & CF_XM)) fm = ghost_at<T>(d, 0, c, 0, k8);
+                if (NEAR && (FL0 & CF_XP)) fp = ghost_at<T>(d, 0, c, 1, k8);
+                T h = vl_half(fc - fm, fp - fc);
+                if (NEAR && (FL0 & CF_SOLID)) h = T(0);
+                ox[v] = ostate(h, fc, xv[0][v]);
+                obx[ty][tx + 1][v * 64 + lane] = ox[v];
+                fm = fb[xslot(tx, ty - 1)][v * 64 + lane];
+                fp = fb[xslot(tx, ty + 1)][v * 64 + lane];
+                if (NEAR && (FL0 & CF_YM)) fm = ghost_at<T>(d, 0, c, 2, k8);
+                if (NEAR && (FL0 & CF_YP)) fp = ghost_at<T>(d, 0, c, 3, k8);
+                h = vl_half(fc - fm, fp - fc);
+                if (NEAR && (FL0 & CF_SOLID)) h = T(0);
+                oy[v] = ostate(h, fc, xv[1][v]);
+                oby[ty + 1][tx][v * 64 + lane] = oy[v];
+            }
+            if (NEAR) __builtin_amdgcn_s_waitcnt(0);
+        };
+        if (FL0 & NEAROWN)
+            own(std::true_type{});
+        else
+            own(std::false_type{});
+        // outgoing state of one halo cell, with flags from the adjacent tile cell
+        {
+            const int fa = uni(flw[adj]);
+            int flh;
+            if (hox)
+                flh = hside ? (((fa & CF_XP) ? CF_SOLID : 0) | ((fa & CF_SOLID) ? CF_XM : 0) | ((fa & CF_XP2) ? CF_XP : 0))
+                            : (((fa & CF_XM) ? CF_SOLID : 0) | ((fa & CF_XM2) ? CF_XM : 0) | ((fa & CF_SOLID) ? CF_XP : 0));
+            else
+                flh = hside ? (((fa & CF_YP) ? CF_SOLID : 0) | ((fa & CF_SOLID) ? CF_YM : 0) | ((fa & CF_YP2) ? CF_YP : 0))
+                            : (((fa & CF_YM) ? CF_SOLID : 0) | ((fa & CF_YM2) ? CF_YM : 0) | ((fa & CF_SOLID) ? CF_YP : 0));
+            const int sm = hox ? xslot(hx - 1, hy) : xslot(hx, hy - 1);
+            const int sc = xslot(hx, hy);
+            const int sp = hox ? xslot(hx + 1, hy) : xslot(hx, hy + 1);
+            T *dst = hox ? &obx[hy][hx + 1][0] : &oby[hy + 1][hx][0];
+            const int dm = hox ? 0 : 2;
+            auto halo = [&](auto near_tag) {
+                constexpr bool NEAR = decltype(near_tag)::value;
+                const int ch_ = c + ((adj & 3) - tx) + ((adj >> 2) - ty) * nx + hdc;  // halo cell index
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int k8 = koff[v] * (8 / ST);
+                    T fm = fb[sm][v * 64 + lane];
+                    const T fc = fb[sc][v * 64 + lane];
+                    T fp = fb[sp][v * 64 + lane];
+                    if (NEAR && (flh & (CF_XM | CF_YM))) fm = ghost_at<T>(d, 0, ch_, dm, k8);
+                    if (NEAR && (flh & (CF_XP | CF_YP))) fp = ghost_at<T>(d, 0, ch_, dm + 1, k8);
+                    T h = vl_half(fc - fm, fp - fc);
+                    if (NEAR && (flh & CF_SOLID)) h = T(0);
+                    dst[v * 64 + lane] = ostate(h, fc, hox ? xv[0][v] : xv[1][v]);
+                }
+                if (NEAR) __builtin_amdgcn_s_waitcnt(0);
+            };
+            if (flh)
+                halo(std::true_type{});
+            else
+                halo(std::false_type{});
+        }
+        lds_barrier();
+
+        // z direction, fluxes, relaxation, update, moments
+        const int FL1 = uni(fup);
+        const bool upd = col_in && !(FL0 & CF_SOLID);
+        const int c1 = c + (int)nxy;
+        const brsrc ws = mk_rsrc(fnext + ccol + (size_t)(unsigned)k * pstride, col_in ? rowb : 0);
+        const double U0 = P[0], U1 = P[1], U2 = P[2], invT = P[4], S0 = P[5], S1 = P[6], S2 = P[7];
+        const double rate = dt * P[8];
+        const double Ar = rate * P[3], c1r = 1.0 - rate;
+        double m[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) m[q] = 0.0;
+        auto body = [&](auto near_tag) {
+            constexpr bool NEAR = decltype(near_tag)::value;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int k8 = koff[v] * (8 / ST);
+                T fm = f0[v], fp = f2[v];
+                if (NEAR && (FL1 & CF_ZM)) fm = ghost_at<T>(d, 0, c1, 4, k8);
+                if (NEAR && (FL1 & CF_ZP)) fp = ghost_at<T>(d, 0, c1, 5, k8);
+                T h1 = vl_half(f1[v] - fm, fp - f1[v]);
+                if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
+                oz1[v] = ostate(h1, f1[v], xv[2][v]);
+                T F = pos[2][v] ? oz0[v] : oz1[v];
+                if (NEAR) {
+                    if (pos[2][v]) {
+                        if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c1, 4, k8);
+                    } else {
+                        if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c, 5, k8);
+                    }
+                }
+                Fup[v] = F;
+                // upwind neighbours' outgoing states are the face states on the upwind side
+                T nx_ = obx[ty][pos[0][v] ? tx : tx + 2][v * 64 + lane];
+                T ny_ = oby[pos[1][v] ? ty : ty + 2][tx][v * 64 + lane];
+                if (NEAR && pos[0][v] && (FL0 & CF_XM)) nx_ = facev_at<T>(d, 0, c, 0, k8);
+                if (NEAR && !pos[0][v] && (FL0 & CF_XP)) nx_ = facev_at<T>(d, 0, c, 1, k8);
+                if (NEAR && pos[1][v] && (FL0 & CF_YM)) ny_ = facev_at<T>(d, 0, c, 2, k8);
+                if (NEAR && !pos[1][v] && (FL0 & CF_YP)) ny_ = facev_at<T>(d, 0, c, 3, k8);
+                const T ax = (T)fabs(xv[0][v]) * idx, ay = (T)fabs(xv[1][v]) * idy, az = (T)xv[2][v] * idz;
+                const T div = fma(ax, ox[v] - nx_, fma(ay, oy[v] - ny_, az * (F - Fdn[v])));
+                if (NEAR && !upd) {
+                    // solid cells are not advanced; carry their value
+                    bst(ws, koff[v], f0[v]);
+                    continue;
+                }
+                const double cx = xv[0][v] - U0, cy = xv[1][v] - U1, cz = xv[2][v] - U2;
+                const double c2 = fma(cz, cz, fma(cy, cy, cx * cx)), cs = fma(cz, S2, fma(cy, S1, cx * S0));
+                const double a = c2 * invT;
+                const double e = exp_neg(-a, etab);
+                const double g = (Ar * e) * fma(cs, fma(a, 2.0, -5.0), 1.0);
+                const T st = (T)fma(-dt, (double)div, fma(c1r, (double)f0[v], g));
+                bst(ws, koff[v], st);
+                const double n0 = (double)st;
+                const double wh = wk[v] * n0, wE = c2 * wh;
+                const double tx_ = cx * wh, ty_ = cy * wh, tz_ = cz * wh;
+                m[0] += wh;
+                m[1] += tx_;
+                m[2] += ty_;
+                m[3] += tz_;
+                m[4] += wE;
+                m[5] = fma(cx, wE, m[5]);
+                m[6] = fma(cy, wE, m[6]);
+                m[7] = fma(cz, wE, m[7]);
+                m[8] = fma(cx, tx_, m[8]);
+                m[9] = fma(cy, tx_, m[9]);
+                m[10] = fma(cz, tx_, m[10]);
+                m[11] = fma(cy, ty_, m[11]);
+                m[12] = fma(cz, ty_, m[12]);
+                m[13] = fma(cz, tz_, m[13]);
+            }
+            if (NEAR) __builtin_amdgcn_s_waitcnt(0);
+        };
+        if ((FL0 | FL1) & NEARALL)
+            body(std::true_type{});
+        else
+            body(std::false_type{});
+        // cell record of the next plane
+        ldrec(k + 1, P, fup);
+        // partial record: m0, m1[3], m2, m3[3], M2 (xx, xy, xz, yy, yz, zz)
+        double r[2];
+        reduce16(m, r);
+        const brsrc rp = mk_rsrc(d.part + ((size_t)c * ncv + ch) * kPartialStride, upd ? 8 * kPartialWords3 : 0);
+        const u32x2 lo = __builtin_bit_cast(u32x2, r[0]), hi = __builtin_bit_cast(u32x2, r[1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4{lo.x, lo.y, hi.x, hi.y}, rp, (lane & 7) == 7 ? (lane >> 3) * 16 : kOob, 0, 0);
+        FL0 = FL1;
+    };
+
+    for (;;) {
+        plane(std::integral_constant<int, 0>{});
+        if (++k >= k1) break;
+        plane(std::integral_constant<int, 1>{});
+        if (++k >= k1) break;
+        plane(std::integral_constant<int, 2>{});
+        if (++k >= k1) break;
+        plane(std::integral_constant<int, 3>{});
+        if (++k >= k1) break;
+    }
+}
+
 // ---------------------------------------------------------------- forces
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
@@ -1365,6 +1782,29 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
         U2D(float, 1, 4) U2D(float, 1, 8) U2D(float, 2, 4) U2D(float, 2, 8)
     }
 #undef U2D
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s)
+{
+    const int W = 64 * t.V;
+    const int ntx = (d.n[0] + kT3 - 1) / kT3, nty = (d.n[1] + kT3 - 1) / kT3, nzs = (d.n[2] + t.LY - 1) / t.LY;
+    const int ncv = (d.NV + W - 1) / W;
+    long long nblk = (long long)ntx * nty * nzs * ncv;
+    nblk = (nblk + 7) / 8 * 8;
+    if (t.TX != kT3 || nblk >= (1ll << 31)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(64 * kT3 * kT3);
+#define U3D(TT, VV)                                                                                          \
+    if (t.V == VV) {                                                                                         \
+        hipLaunchKernelGGL((k_update3d<TT, VV>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nty, nzs, ncv); \
+        return hipGetLastError();                                                                            \
+    }
+    if (storage == 0) {
+        U3D(double, 1) U3D(double, 2)
+    } else {
+        U3D(float, 1) U3D(float, 2)
+    }
+#undef U3D
     return hipErrorInvalidValue;
 }
 

@@ -6,14 +6,16 @@
 
 namespace ibdvm {
 
-// tile of the 2D marching update: V velocity nodes per lane, TX columns per
-// workgroup, LY rows per workgroup
+// tile of the marching updates: V velocity nodes per lane; 2D: TX columns
+// per workgroup and LY rows per segment; 3D: TX = 4 (a 4 x 4 tile of
+// columns) and LY planes per segment
 struct Tile {
     int V, TX, LY;
 };
 
 hipError_t launch_update(const Dev &d, int storage, int cur, int slot, hipStream_t s);
 hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
+hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
 hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, hipStream_t s);
 hipError_t launch_force(const Dev &d, int storage, int cur, hipStream_t s);
