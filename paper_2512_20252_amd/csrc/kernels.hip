@@ -1,11 +1,13 @@
 // kernels.hip -- gfx950 kernels of the immersed-boundary Shakhov-DVM step
-// (arXiv 2512.20252).  One wavefront owns one cell and 64 consecutive
-// velocity nodes (node index innermost in memory, so every load and store of
-// the distribution is a contiguous 512-byte (FP64) or 256-byte (FP32) run).
+// (arXiv 2512.20252).  The velocity node index is innermost in memory, so a
+// wavefront's 64 lanes read and write contiguous 512-byte (FP64) or 256-byte
+// (FP32) runs of one cell's distribution.
 //
-//   k_update    Section 2.2 upwind MUSCL fluxes with the van Leer limiter,
-//               Shakhov relaxation (Sections 2.1, 4), forward Euler; emits
-//               partial moments of the new state per (cell, 64 nodes).
+//   k_update2d  Section 2.2 upwind MUSCL fluxes with the van Leer limiter,
+//   k_update3d  Shakhov relaxation (Sections 2.1, 4), forward Euler; each
+//               workgroup marches a tile of grid columns along y (2D) or z
+//               (3D) and emits partial moments of the new state per (cell,
+//               velocity chunk).
 //   k_fill_*    Section 3.2.1 ghost construction with the upwind weights of
 //               3.2.2 and the cut-cell wall density/distribution of 3.2.3,
 //               over (ghost-donor pair, node chunk) workgroups in three
@@ -593,157 +595,6 @@ __device__ __forceinline__ void reduce16(const double S[16], double out[2])
         c += dpp<kRowRor2>(c);
         c += dpp<kRowRor1>(c);
         out[i] = c;
-    }
-}
-
-// ---------------------------------------------------------------- generic update
-// One wavefront per (cell, 64-node chunk), neighbours read directly; the 3D
-// update (the 2D one marches, below).
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_update(Dev d, int cur, int slot)
-{
-    constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
-    const int lane = threadIdx.x & 63;
-    const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
-    const double dt = d.cfl / (d.adv + 1.0 / tmin);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        d.ctrl->tau_bits[slot ^ 1] = kInfBits;
-        d.ctrl->dt = dt;
-        d.ctrl->time += dt;
-        d.ctrl->step += 1;
-    }
-    // one wavefront per (cell, chunk of 64 nodes), grid-stride over the cells
-    const long long nw = (long long)d.Nc * d.nchunk;
-    for (long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); wave < nw; wave += (long long)gridDim.x * 4) {
-        const int c = (int)(wave / d.nchunk), chunk = (int)(wave - (long long)c * d.nchunk);
-        const int fl = d.cflag[c];
-        const int NV = d.NV;
-        const int k = chunk * kChunk + lane;
-        const bool act = k < NV;
-        const int kk = act ? k : NV - 1;
-        if (fl & 1) {
-            // solid cells are not advanced; carry their value into the new buffer
-            if (act)
-                for (int A = 0; A < d.NA; ++A)
-                    ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = ((const T *)d.f[cur][A])[(size_t)c * NV + k];
-            continue;
-        }
-        int ijk[3];
-        ijk[0] = c % d.n[0];
-        ijk[1] = (c / d.n[0]) % d.n[1];
-        ijk[2] = D == 3 ? c / (d.n[0] * d.n[1]) : 0;
-
-        const double *cp = d.cellp + (size_t)c * kCellWords;
-        double cc[3] = {0, 0, 0}, c2 = 0.0, cs = 0.0, xi[3] = {0, 0, 0};
-        for (int a = 0; a < D; ++a) {
-            xi[a] = d.xi[a][kk];
-            cc[a] = xi[a] - cp[CW_U + a];
-            c2 += cc[a] * cc[a];
-            cs += cc[a] * cp[CW_S + a];
-        }
-        const double invT = cp[CW_INVT];
-        const double H = cp[CW_A] * exp(-c2 * invT);
-        double gS[2];
-        if (D == 2) {
-            gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 4.0));
-            gS[1] = cp[CW_TH] * H * (1.0 + cs * (2.0 * c2 * invT - 2.0));
-        } else {
-            gS[0] = H * (1.0 + cs * (2.0 * c2 * invT - 5.0));
-            gS[1] = 0.0;
-        }
-        const double rate = dt * cp[CW_INVTAU];
-        double fnew[2] = {0.0, 0.0};
-        for (int A = 0; A < d.NA; ++A) {
-            const T *f = (const T *)d.f[cur][A];
-            const T v0 = f[(size_t)c * NV + kk];
-            T div = T(0);
-            for (int a = 0; a < D; ++a) {
-                T vm2, vm1, vp1, vp2;
-                int km1 = NB_FLUID, kp1 = NB_FLUID, pm1 = -1, pp1 = -1;
-                if (!(fl & 2)) {
-                    const size_t s = (size_t)d.stride[a] * NV, o = (size_t)c * NV + kk;
-                    vm2 = f[o - 2 * s];
-                    vm1 = f[o - s];
-                    vp1 = f[o + s];
-                    vp2 = f[o + 2 * s];
-                } else {
-                    int nm, np, dummy, kind2;
-                    vm1 = neighbour(d, f, A, kk, c, ijk, a, -1, km1, nm, pm1);
-                    vp1 = neighbour(d, f, A, kk, c, ijk, a, +1, kp1, np, pp1);
-                    vm2 = vm1;
-                    vp2 = vp1;
-                    if (km1 == NB_FLUID) {
-                        int j2[3] = {ijk[0], ijk[1], ijk[2]};
-                        j2[a] = (ijk[a] - 1 + d.n[a]) % d.n[a];
-                        vm2 = neighbour(d, f, A, kk, nm, j2, a, -1, kind2, dummy, dummy);
-                    }
-                    if (kp1 == NB_FLUID) {
-                        int j2[3] = {ijk[0], ijk[1], ijk[2]};
-                        j2[a] = (ijk[a] + 1) % d.n[a];
-                        vp2 = neighbour(d, f, A, kk, np, j2, a, +1, kind2, dummy, dummy);
-                    }
-                }
-                const T s0 = vanleer(v0 - vm1, vp1 - v0);
-                const T xa = (T)xi[a];
-                T fr, fl_;
-                if (xa > T(0)) {
-                    fr = v0 + T(0.5) * s0;
-                    if (km1 == NB_IB)
-                        fl_ = (T)d.face[A][(size_t)pm1 * NV + kk];
-                    else if (km1 == NB_BC)
-                        fl_ = vm1;
-                    else
-                        fl_ = vm1 + T(0.5) * vanleer(vm1 - vm2, v0 - vm1);
-                } else {
-                    fl_ = v0 - T(0.5) * s0;
-                    if (kp1 == NB_IB)
-                        fr = (T)d.face[A][(size_t)pp1 * NV + kk];
-                    else if (kp1 == NB_BC)
-                        fr = vp1;
-                    else
-                        fr = vp1 - T(0.5) * vanleer(vp1 - v0, vp2 - vp1);
-                }
-                div += xa * (fr - fl_) * (T)d.inv_dx[a];
-            }
-            const double fo = (double)v0;
-            const double fn = fo - dt * (double)div + rate * (gS[A] - fo);
-            const T st = (T)fn;
-            if (act) ((T *)d.f[cur ^ 1][A])[(size_t)c * NV + k] = st;
-            fnew[A] = act ? (double)st : 0.0;
-        }
-        // partial moments of the new state about U^n
-        const double wk = act ? d.w[k] : 0.0;
-        const double h = fnew[0];
-        const double E = c2 * h + (D == 2 ? fnew[1] : 0.0);
-        double S[PW];
-        S[0] = wk * h;
-        for (int a = 0; a < D; ++a) {
-            S[1 + a] = wk * cc[a] * h;
-            S[2 + D + a] = wk * cc[a] * E;
-        }
-        S[1 + D] = wk * E;
-        int o = 2 + 2 * D;
-        for (int a = 0; a < D; ++a)
-            for (int b = a; b < D; ++b) S[o++] = wk * cc[a] * cc[b] * h;
-        double *pp = d.part + ((size_t)c * d.nchunk + chunk) * kPartialStride;
-        if (D == 3) {
-            // 14 words, transposed: lane 8 g + 7 holds words 2 g and 2 g + 1
-            double S16[16], r[2];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) S16[j] = j < PW ? S[j] : 0.0;
-            reduce16(S16, r);
-            const int g = lane >> 3;
-            if ((lane & 7) == 7 && 2 * g < PW) pp[2 * g] = r[0];
-            if ((lane & 7) == 7 && 2 * g + 1 < PW) pp[2 * g + 1] = r[1];
-        } else {
-            double mine = 0.0;
-#pragma unroll
-            for (int j = 0; j < PW; ++j) {
-                double v = wave_sum(S[j]);
-                if (lane == j) mine = v;
-            }
-            if (lane < PW) pp[lane] = mine;
-        }
     }
 }
 
@@ -1755,13 +1606,6 @@ static inline unsigned stride_blocks(long long n, int bs)
 {
     const long long b = (n + bs - 1) / bs;
     return (unsigned)(b < (1ll << 20) ? (b > 0 ? b : 1) : (1ll << 20));
-}
-
-hipError_t launch_update(const Dev &d, int storage, int cur, int slot, hipStream_t s)
-{
-    long long waves = (long long)d.Nc * d.nchunk;
-    DISPATCH(d.D, storage, hipLaunchKernelGGL((k_update<DD, TT>), dim3(stride_blocks(waves, 4)), dim3(256), 0, s, d, cur, slot));
-    return hipGetLastError();
 }
 
 hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s)

@@ -13,7 +13,6 @@ struct Tile {
     int V, TX, LY;
 };
 
-hipError_t launch_update(const Dev &d, int storage, int cur, int slot, hipStream_t s);
 hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
