@@ -198,16 +198,18 @@ ibdvm_status ibdvm_wall_state(ibdvm_ctx *ctx, double *ghost, double *face, doubl
  * advancing each context alone. */
 ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps);
 
-/* Tile of the 2D update kernel: V velocity nodes per lane (1 or 2), TX grid
- * columns per workgroup (4 or 8) and LY rows marched per workgroup (1..256).
- * The tile fixes the order of the velocity sums, so results are
- * bit-identical only between runs with the same tile.  2D only. */
+/* Tile of the marching update kernel: V velocity nodes per lane (1 or 2),
+ * TX grid columns per workgroup and LY rows (2D) or planes (3D) marched per
+ * workgroup (1..256).  2D: TX = 4 or 8 adjacent columns.  3D: TX = 16 (a
+ * 4 x 4 tile of columns) or 8 (4 x 2).  Unsupported values return
+ * IBDVM_E_INVALID_ARG.  The tile fixes the order of the velocity sums, so
+ * results are bit-identical only between runs with the same tile. */
 ibdvm_status ibdvm_set_tile(ibdvm_ctx *ctx, int32_t V, int32_t TX, int32_t LY);
 ibdvm_status ibdvm_get_tile(const ibdvm_ctx *ctx, int32_t out[3]);
 
 /* Autotuner: times reps launches of the update kernel for every supported
  * tile on the current state (without advancing it), keeps the fastest and
- * returns it in out (may be NULL).  Synchronises.  2D only. */
+ * returns it in out (may be NULL).  Synchronises. */
 ibdvm_status ibdvm_autotune(ibdvm_ctx *ctx, int32_t reps, int32_t out[3]);
 
 /* Kernel timing with HIP events (tracing aid).  While enabled, every
@@ -262,7 +264,7 @@ typedef struct {
     double C_D, C_L;
     double t_submit, t_admit, t_done; /* seconds on the server clock */
     int64_t updates;                  /* fluid cells x velocity nodes x steps */
-    int32_t tile[3];                  /* 2D update tile used */
+    int32_t tile[3];                  /* update tile used */
 } ibdvm_result;
 
 ibdvm_status ibdvm_server_create(void *workspace, size_t bytes, int32_t max_active, int32_t steps_per_replay,

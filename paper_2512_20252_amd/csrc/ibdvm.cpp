@@ -447,7 +447,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (D == 2)
         c->tile = c->precision == IBDVM_F32_STORE ? ibdvm::Tile{2, 8, 64} : ibdvm::Tile{1, 8, 64};
     else
-        c->tile = ibdvm::Tile{1, 4, 256};
+        c->tile = ibdvm::Tile{1, 16, 256};
     d.nchunk = (NV + 64 * c->tile.V - 1) / (64 * c->tile.V);
     d.Nc = g.Nc;
     d.npairs = (int)np;
@@ -839,10 +839,11 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
 }
 
 namespace {
-// 2D: TX 4 or 8 columns; 3D: a 4 x 4 tile of columns (TX = 4)
+// TX grid columns per workgroup: 2D 4 or 8 (a row of columns); 3D 16 or 8
+// (a 4 x 4 or 4 x 2 tile of columns)
 bool tile_supported(int dim, const ibdvm::Tile &t)
 {
-    bool tx = dim == 2 ? (t.TX == 4 || t.TX == 8) : t.TX == 4;
+    bool tx = dim == 2 ? (t.TX == 4 || t.TX == 8) : (t.TX == 16 || t.TX == 8);
     bool v = t.V == 1 || t.V == 2;
     return tx && v && t.LY >= 1 && t.LY <= 256;
 }
@@ -897,7 +898,7 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
     HIP_CHECK(hipEventCreate(&e0));
     HIP_CHECK(hipEventCreate(&e1));
     const int dim = c->prob.dim;
-    const int Vs[2] = {1, 2}, TXs[2] = {4, 8};
+    const int Vs[2] = {1, 2}, TXs[2] = {dim == 2 ? 4 : 16, 8};
     const int LYs[3] = {dim == 2 ? 32 : 16, dim == 2 ? 64 : 48, dim == 2 ? 120 : 256};
     for (int V : Vs)
         for (int TX : TXs)

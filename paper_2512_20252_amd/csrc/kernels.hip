@@ -1086,29 +1086,34 @@ __device__ __forceinline__ float ostate(float h, float f, double xi)
     return f + __builtin_bit_cast(float, __builtin_bit_cast(unsigned, h) ^ s);
 }
 
-constexpr int kT3 = 4;  // tile edge along x and y
+constexpr int kT3 = 4;  // tile edge along x
 
-// staged plane: slot of tile position (x, y), x, y in [-2, 6), on the cross
-// (rows 0..3 with two halo columns per side: 8 slots each; then the two halo
-// rows below and above, 4 slots each)
+// staged plane of a 4 x TY tile: slot of tile position (x, y), x in [-2, 6),
+// y in [-2, TY + 2), on the cross (rows 0..TY-1 with two halo columns per
+// side: 8 slots each; then the two halo rows below and above, 4 slots each)
+template <int TY>
 __device__ __forceinline__ int xslot(int x, int y)
 {
-    return (y >= 0 && y < kT3) ? y * (kT3 + 4) + x + 2 : kT3 * (kT3 + 4) + (y < 0 ? y + 2 : y - kT3 + 2) * kT3 + x;
+    return (y >= 0 && y < TY) ? y * (kT3 + 4) + x + 2 : TY * (kT3 + 4) + (y < 0 ? y + 2 : y - TY + 2) * kT3 + x;
 }
-constexpr int kXSlots = kT3 * (kT3 + 4) + 4 * kT3;
 
-template <typename T, int V>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+template <typename T, int V, int TY>
+__global__ __launch_bounds__(64 * kT3 * TY) __attribute__((amdgpu_waves_per_eu(TY == 4 || V == 1 ? 4 : 2)))
 void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int ncv)
 {
+    constexpr int NW = kT3 * TY;                    // wavefronts
+    constexpr int NHL = kT3 * TY + 4 * kT3;         // halo cells staged per plane
+    constexpr int NQ = (NHL + NW - 1) / NW;         // ... per wavefront
+    constexpr int NHO = 2 * TY + 2 * kT3;           // halo cells whose outgoing state is formed
+    constexpr int NO = (NHO + NW - 1) / NW;         // ... per wavefront
     constexpr int W = 64 * V;
     constexpr int ST = (int)sizeof(T);
     constexpr int NEAROWN = CF_SOLID | CF_XM | CF_XP | CF_YM | CF_YP;
     constexpr int NEARALL = NEAROWN | CF_ZM | CF_ZP;
-    __shared__ T fb[kXSlots][W];
-    __shared__ T obx[kT3][kT3 + 2][W];  // outgoing x states, x in [-1, 4]
-    __shared__ T oby[kT3 + 2][kT3][W];  // outgoing y states, y in [-1, 4]
-    __shared__ int flw[kT3 * kT3];
+    __shared__ T fb[TY * (kT3 + 4) + 4 * kT3][W];
+    __shared__ T obx[TY][kT3 + 2][W];  // outgoing x states, x in [-1, 4]
+    __shared__ T oby[TY + 2][kT3][W];  // outgoing y states, y in [-1, TY]
+    __shared__ int flw[NW];
     __shared__ double etab[32];
     if (threadIdx.x < 32) etab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 32));
 
@@ -1126,7 +1131,7 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
     if (L >= ntx * nty * nzs * ncv) return;
     const int tX = L % ntx, tY = (L / ntx) % nty, zs = (L / (ntx * nty)) % nzs, ch = L / (ntx * nty * nzs);
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2], NV = d.NV;
-    const int i0 = tX * kT3, j0 = tY * kT3, k0 = zs * LZ, k1 = min(k0 + LZ, nz);
+    const int i0 = tX * kT3, j0 = tY * TY, k0 = zs * LZ, k1 = min(k0 + LZ, nz);
     const int lane = threadIdx.x & 63;
     const int w = uni(threadIdx.x >> 6);
     const int tx = w & 3, ty = w >> 2;
@@ -1189,22 +1194,31 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
     char *fnext = (char *)d.f[cur ^ 1][0];
     bool cfs;
     const size_t ccol = column(i, j, cfs);
-    // halo cells staged by this wavefront: one of the x halo (columns -2, -1,
-    // 4, 5 of row ty) and one of the y halo (rows -2, -1, 4, 5 of column tx)
-    const int hxx = (tx < 2 ? tx - 2 : tx + 2), hyy = (ty < 2 ? ty - 2 : ty + 2);
-    bool hxfs, hyfs;
-    const size_t hxcol = column(i0 + hxx, j, hxfs), hycol = column(i, j0 + hyy, hyfs);
-    const int sown = xslot(tx, ty), shx = xslot(hxx, ty), shy = xslot(tx, hyy);
-    // halo cell whose outgoing state this wavefront forms: w < 8 the x halo
-    // cell (-1 or 4, w & 3), else the y halo cell (w & 3, -1 or 4); adj is the
-    // tile cell next to it
-    const bool hox = w < 8;
-    const int hside = (w >> 2) & 1, hq = w & 3;
-    const int hx = hox ? (hside ? kT3 : -1) : hq, hy = hox ? hq : (hside ? kT3 : -1);
-    const int adj = hox ? hq * kT3 + (hside ? kT3 - 1 : 0) : (hside ? kT3 - 1 : 0) * kT3 + hq;
-    const int hdc = hox ? (hside ? 1 : -1) : (hside ? nx : -nx);  // halo cell - adjacent cell
+    // halo cells staged by this wavefront: items w, w + NW, ... of the list
+    // of x halo cells (columns -2, -1, 4, 5 of each tile row) followed by the
+    // y halo cells (rows -2, -1, TY, TY + 1 of each tile column)
+    size_t hcol[NQ];
+    bool hfs[NQ], hon[NQ];
+    int hsl[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int h = w + q * NW;
+        hon[q] = h < NHL;
+        int x, y;
+        if (h < kT3 * TY) {
+            x = (h & 3) < 2 ? (h & 3) - 2 : (h & 3) + 2;
+            y = h >> 2;
+        } else {
+            const int h2 = min(h, NHL - 1) - kT3 * TY;
+            x = h2 & 3;
+            y = (h2 >> 2) < 2 ? (h2 >> 2) - 2 : TY + (h2 >> 2) - 2;
+        }
+        hcol[q] = column(i0 + x, j0 + y, hfs[q]);
+        hsl[q] = xslot<TY>(x, y);
+    }
+    const int sown = xslot<TY>(tx, ty);
 
-    T R[4][V], OZ[2][V], FD[2][V], HX[2][V], HY[2][V];
+    T R[4][V], OZ[2][V], FD[2][V], HH[2][NQ][V];
     double P[9];
     int FL0, fup;
     {
@@ -1214,8 +1228,6 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
         const brsrc r2 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0), rowb);
         const brsrc r3 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 + 1), rowb);
         const brsrc r4 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k0 + 2), rowb);
-        const brsrc rx = mk_rsrc(planep(fcur, hxcol, hxfs, fsr, k0), rowb);
-        const brsrc ry = mk_rsrc(planep(fcur, hycol, hyfs, fsr, k0), rowb);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             fm2[v] = bld(r0, koff[v], T());
@@ -1223,8 +1235,12 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
             R[0][v] = bld(r2, koff[v], T());
             R[1][v] = bld(r3, koff[v], T());
             R[2][v] = bld(r4, koff[v], T());
-            HX[0][v] = bld(rx, koff[v], T());
-            HY[0][v] = bld(ry, koff[v], T());
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const brsrc rh = mk_rsrc(planep(fcur, hcol[q], hfs[q], fsr, k0), hon[q] ? rowb : 0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) HH[0][q][v] = bld(rh, koff[v], T());
         }
         const int flm1 = uni(ldflag(k0 - 1));
         FL0 = uni(ldflag(k0));
@@ -1267,31 +1283,30 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
         T(&oz1)[V] = OZ[(S + 1) & 1];
         T(&Fdn)[V] = FD[S & 1];
         T(&Fup)[V] = FD[(S + 1) & 1];
-        T(&hxc)[V] = HX[S & 1];
-        T(&hxn)[V] = HX[(S + 1) & 1];
-        T(&hyc)[V] = HY[S & 1];
-        T(&hyn)[V] = HY[(S + 1) & 1];
+        T(&hc)[NQ][V] = HH[S & 1];
+        T(&hn)[NQ][V] = HH[(S + 1) & 1];
         const int c = (int)((size_t)i + (size_t)nx * j + nxy * k);
 
         // prefetch: own column plane k+3, halo cells plane k+1
         {
             const brsrc r3 = mk_rsrc(planep(fcur, ccol, cfs, fsr, k + 3), rowb);
-            const brsrc rx = mk_rsrc(planep(fcur, hxcol, hxfs, fsr, k + 1), rowb);
-            const brsrc ry = mk_rsrc(planep(fcur, hycol, hyfs, fsr, k + 1), rowb);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                f3[v] = bld(r3, koff[v], T());
-                hxn[v] = bld(rx, koff[v], T());
-                hyn[v] = bld(ry, koff[v], T());
+            for (int v = 0; v < V; ++v) f3[v] = bld(r3, koff[v], T());
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const brsrc rh = mk_rsrc(planep(fcur, hcol[q], hfs[q], fsr, k + 1), hon[q] ? rowb : 0);
+#pragma unroll
+                for (int v = 0; v < V; ++v) hn[q][v] = bld(rh, koff[v], T());
             }
         }
         // stage plane k
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            fb[sown][v * 64 + lane] = f0[v];
-            fb[shx][v * 64 + lane] = hxc[v];
-            fb[shy][v * 64 + lane] = hyc[v];
-        }
+        for (int v = 0; v < V; ++v) fb[sown][v * 64 + lane] = f0[v];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (hon[q])
+#pragma unroll
+                for (int v = 0; v < V; ++v) fb[hsl[q]][v * 64 + lane] = hc[q][v];
         if (lane == 0) flw[w] = FL0;
         lds_barrier();
 
@@ -1310,8 +1325,8 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
                 if (NEAR && (FL0 & CF_SOLID)) h = T(0);
                 ox[v] = ostate(h, fc, xv[0][v]);
                 obx[ty][tx + 1][v * 64 + lane] = ox[v];
-                fm = fb[xslot(tx, ty - 1)][v * 64 + lane];
-                fp = fb[xslot(tx, ty + 1)][v * 64 + lane];
+                fm = fb[xslot<TY>(tx, ty - 1)][v * 64 + lane];
+                fp = fb[xslot<TY>(tx, ty + 1)][v * 64 + lane];
                 if (NEAR && (FL0 & CF_YM)) fm = ghost_at<T>(d, 0, c, 2, k8);
                 if (NEAR && (FL0 & CF_YP)) fp = ghost_at<T>(d, 0, c, 3, k8);
                 h = vl_half(fc - fm, fp - fc);
@@ -1325,9 +1340,19 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
             own(std::true_type{});
         else
             own(std::false_type{});
-        // outgoing state of one halo cell, with flags from the adjacent tile cell
-        {
-            const int fa = uni(flw[adj]);
+        // outgoing states of the halo cells next to the tile (items w, w + NW,
+        // ... of: x = -1 and x = 4 for each tile row, y = -1 and y = TY for
+        // each tile column), with flags from the adjacent tile cell
+#pragma unroll
+        for (int q = 0; q < NO; ++q) {
+            const int h = w + q * NW;
+            if (h >= NHO) break;
+            const bool hox = h < 2 * TY;
+            const bool hside = hox ? h >= TY : h >= 2 * TY + kT3;
+            const int hq = hox ? (hside ? h - TY : h) : (hside ? h - 2 * TY - kT3 : h - 2 * TY);
+            const int hx = hox ? (hside ? kT3 : -1) : hq, hy = hox ? hq : (hside ? TY : -1);
+            const int ax_ = hox ? (hside ? kT3 - 1 : 0) : hq, ay_ = hox ? hq : (hside ? TY - 1 : 0);
+            const int fa = uni(flw[ay_ * kT3 + ax_]);
             int flh;
             if (hox)
                 flh = hside ? (((fa & CF_XP) ? CF_SOLID : 0) | ((fa & CF_SOLID) ? CF_XM : 0) | ((fa & CF_XP2) ? CF_XP : 0))
@@ -1335,14 +1360,15 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
             else
                 flh = hside ? (((fa & CF_YP) ? CF_SOLID : 0) | ((fa & CF_SOLID) ? CF_YM : 0) | ((fa & CF_YP2) ? CF_YP : 0))
                             : (((fa & CF_YM) ? CF_SOLID : 0) | ((fa & CF_YM2) ? CF_YM : 0) | ((fa & CF_SOLID) ? CF_YP : 0));
-            const int sm = hox ? xslot(hx - 1, hy) : xslot(hx, hy - 1);
-            const int sc = xslot(hx, hy);
-            const int sp = hox ? xslot(hx + 1, hy) : xslot(hx, hy + 1);
+            const int sm = hox ? xslot<TY>(hx - 1, hy) : xslot<TY>(hx, hy - 1);
+            const int sc = xslot<TY>(hx, hy);
+            const int sp = hox ? xslot<TY>(hx + 1, hy) : xslot<TY>(hx, hy + 1);
             T *dst = hox ? &obx[hy][hx + 1][0] : &oby[hy + 1][hx][0];
             const int dm = hox ? 0 : 2;
             auto halo = [&](auto near_tag) {
                 constexpr bool NEAR = decltype(near_tag)::value;
-                const int ch_ = c + ((adj & 3) - tx) + ((adj >> 2) - ty) * nx + hdc;  // halo cell index
+                // grid index of the halo cell: the adjacent tile cell one step out
+                const int ch_ = c + (ax_ - tx) + (ay_ - ty) * nx + (hox ? (hside ? 1 : -1) : (hside ? nx : -nx));
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int k8 = koff[v] * (8 / ST);
@@ -1631,22 +1657,24 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
 
 hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s)
 {
+    // t.TX = grid columns per workgroup: 16 (a 4 x 4 tile) or 8 (4 x 2)
+    const int TY = t.TX / kT3;
     const int W = 64 * t.V;
-    const int ntx = (d.n[0] + kT3 - 1) / kT3, nty = (d.n[1] + kT3 - 1) / kT3, nzs = (d.n[2] + t.LY - 1) / t.LY;
+    const int ntx = (d.n[0] + kT3 - 1) / kT3, nty = (d.n[1] + TY - 1) / TY, nzs = (d.n[2] + t.LY - 1) / t.LY;
     const int ncv = (d.NV + W - 1) / W;
     long long nblk = (long long)ntx * nty * nzs * ncv;
     nblk = (nblk + 7) / 8 * 8;
-    if (t.TX != kT3 || nblk >= (1ll << 31)) return hipErrorInvalidValue;
-    dim3 grid((unsigned)nblk), block(64 * kT3 * kT3);
-#define U3D(TT, VV)                                                                                          \
-    if (t.V == VV) {                                                                                         \
-        hipLaunchKernelGGL((k_update3d<TT, VV>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nty, nzs, ncv); \
-        return hipGetLastError();                                                                            \
+    if ((t.TX != 16 && t.TX != 8) || nblk >= (1ll << 31)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(64 * t.TX);
+#define U3D(TT, VV, YY)                                                                                          \
+    if (t.V == VV && TY == YY) {                                                                                 \
+        hipLaunchKernelGGL((k_update3d<TT, VV, YY>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nty, nzs, ncv); \
+        return hipGetLastError();                                                                                \
     }
     if (storage == 0) {
-        U3D(double, 1) U3D(double, 2)
+        U3D(double, 1, 4) U3D(double, 2, 4) U3D(double, 1, 2) U3D(double, 2, 2)
     } else {
-        U3D(float, 1) U3D(float, 2)
+        U3D(float, 1, 4) U3D(float, 2, 4) U3D(float, 1, 2) U3D(float, 2, 2)
     }
 #undef U3D
     return hipErrorInvalidValue;

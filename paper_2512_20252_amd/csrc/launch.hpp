@@ -6,9 +6,9 @@
 
 namespace ibdvm {
 
-// tile of the marching updates: V velocity nodes per lane; 2D: TX columns
-// per workgroup and LY rows per segment; 3D: TX = 4 (a 4 x 4 tile of
-// columns) and LY planes per segment
+// tile of the marching updates: V velocity nodes per lane, TX grid columns
+// per workgroup (2D: a row of 4 or 8; 3D: a 4 x 4 or 4 x 2 tile, TX = 16 or
+// 8) and LY rows (2D) or planes (3D) per segment
 struct Tile {
     int V, TX, LY;
 };

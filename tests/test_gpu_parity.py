@@ -272,13 +272,14 @@ def test_tiles_agree_with_oracle(oracle_mod, torch_cuda, precision, tile):
             assert np.max(np.abs(mg[ok, j] - mo[ok, j])) / np.max(np.abs(mo[ok, j])) <= 1e-6
 
 
-TILES3 = [("f64", (1, 4, 256)), ("f64", (1, 4, 5)), ("f64", (2, 4, 3)), ("f32", (1, 4, 4)), ("f32", (2, 4, 256))]
+TILES3 = [("f64", (1, 16, 256)), ("f64", (1, 16, 5)), ("f64", (2, 16, 3)), ("f64", (2, 8, 256)), ("f64", (1, 8, 7)),
+          ("f32", (1, 16, 4)), ("f32", (2, 16, 256)), ("f32", (2, 8, 6))]
 
 
 @pytest.mark.parametrize("precision,tile", TILES3)
 def test_tiles_3d_agree_with_oracle(oracle_mod, torch_cuda, precision, tile):
-    """The 3D marching update (4 x 4 columns per workgroup, plane segments of
-    LY planes) on an off-centre sphere in a grid whose sides are not multiples
+    """The 3D marching update (4 x 4 or 4 x 2 columns per workgroup, plane
+    segments of LY planes) on an off-centre sphere in a grid whose sides are not multiples
     of the tile, with segments that do not divide the grid and a ragged
     velocity tail (210 nodes), reproduces the oracle."""
     c = cases.case(dim=3, n=(18, 15, 13), lo=(-1.8, -1.5, -1.3), hi=(1.8, 1.5, 1.3), vn=(7, 6, 5),
