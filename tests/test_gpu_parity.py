@@ -243,6 +243,65 @@ def test_full_size_cylinder_step(oracle_mod, torch_cuda):
     assert _rel(hg, ho) <= TOL64 and _rel(bg, bo) <= TOL64
 
 
+def _mirror_errors(m, n):
+    """Largest deviation of the moment field m (cells x 8: rho, U, T, q) of a
+    body centred in a cube from its mirror images in y and z and from the
+    y <-> z exchange, relative to each quantity's scale."""
+    f = m.reshape(n, n, n, 8)  # [k][j][i]
+    ok = np.isfinite(f[..., 0])
+    scale = np.nanmax(np.abs(f), axis=(0, 1, 2))
+    scale[1:4] = max(scale[1:4].max(), np.sqrt(np.nanmax(f[..., 4])))
+    scale[5:8] = max(scale[5:8].max(), 1e-30)
+    errs = []
+    sy = np.array([1, 1, -1, 1, 1, 1, -1, 1])  # U_y, q_y change sign under y -> -y
+    sz = np.array([1, 1, 1, -1, 1, 1, 1, -1])
+    for g, sign in ((f[:, ::-1, :], sy), (f[::-1, :, :], sz)):
+        assert np.array_equal(ok, np.isfinite(g[..., 0]))
+        errs.append(np.max(np.abs(f[ok] - sign * g[ok]) / scale))
+    t = f.transpose(1, 0, 2, 3)[..., [0, 1, 3, 2, 4, 5, 7, 6]]  # y <-> z: cells and components
+    errs.append(np.max(np.abs(f[ok] - t[ok]) / scale))
+    return errs
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_full_size_sphere_far_field_and_symmetry(oracle_mod, torch_cuda, precision):
+    """The 96^3 x 24^3 sphere at full size, too large for the oracle: from the
+    unperturbed freestream, after one step every cell farther than 4 cells
+    from the body equals the oracle's step of a body-free 4^3 box with the
+    same spacing, velocity grid and time step (a uniform field evolves the
+    same way everywhere); after two steps the field of the centred sphere in
+    a flow along x is mirror symmetric in y and in z and symmetric under
+    y <-> z, as the problem is.  A mirror repeats the same arithmetic on
+    mirrored values, so it holds to the rounding of the FP64 velocity sums in
+    both forms.  The y <-> z exchange also swaps the order in which the y and
+    z fluxes enter the divergence; in FP32 storage that order is rounded in
+    FP32, so there it holds to FP32 rounding (1e-6)."""
+    n = 96
+    c = cases.sphere(n=n, vn=24)
+    s = ibdvm.Solver(c, precision=precision, stream=torch_cuda.cuda.Stream())
+    s.init_freestream(None, 0.0)
+    s.step(1)
+    m = s.moments()
+    box = cases.case(dim=3, n=(4, 4, 4), lo=(0.0, 0.0, 0.0), hi=(4 * 8.0 / n,) * 3, vn=(24, 24, 24),
+                     vlo=(-6.0, -6.0, -6.0), vhi=(6.0, 6.0, 6.0), Kn=c["Kn"], Ma=c["Ma"])
+    o = oracle_mod.Oracle(box)
+    o.init_freestream(None, 0.0)
+    o.step(1)
+    ref = o.moments()[0]
+    x = -4.0 + (np.arange(n) + 0.5) * 8.0 / n
+    r = np.sqrt(x[None, None, :] ** 2 + x[None, :, None] ** 2 + x[:, None, None] ** 2).reshape(-1)
+    far = r > 0.5 + 4 * 8.0 / n
+    tol = TOL64 if precision == "f64" else 1e-6
+    scale = np.array([ref[0], 1, 1, 1, ref[4], 1, 1, 1])
+    assert np.max(np.abs(m[far] - ref) / scale) <= tol
+    s.step(1)
+    errs = _mirror_errors(s.moments(), n)
+    assert max(errs[:2]) <= 1e-12, errs
+    assert errs[2] <= (1e-12 if precision == "f64" else 1e-6), errs
+    del s
+    torch_cuda.cuda.empty_cache()
+
+
 TILES64 = [(1, 4, 32), (1, 8, 64), (2, 4, 16), (2, 8, 64), (1, 8, 7)]
 TILES32 = [(1, 8, 64), (2, 4, 32), (2, 8, 5), (1, 4, 3)]
 
