@@ -479,9 +479,10 @@ __global__ __launch_bounds__(256) void k_moments_direct(Dev d, int cur, int slot
 // Workgroup = TX wavefronts; wavefront w owns grid column i0 + w and its lanes
 // own velocity nodes k0 + lane + 64 v (v < V).  The workgroup marches up a
 // segment of rows.  Rows j-2..j+2 of the own column live in registers; row j
-// of the TX columns plus two halo columns per side is exchanged through LDS
-// (double-buffered by row parity), the x slopes of the TX + 2 cells the faces
-// need are computed once per row and shared through LDS, and the y slope of
+// of the TX columns plus two halo columns per side is exchanged through LDS,
+// the x slopes of the TX + 2 cells the faces need are computed once per row
+// (the two halo cells' by wavefronts 0..3, one array each) and shared
+// through LDS, and the y slope of
 // row j+1 and the flux state of face j+1/2 are carried to the next row.  Outer
 // freestream ghosts are the freestream values (zero slope follows from the
 // limiter); periodic ghosts wrap.  Solid face neighbours are replaced by the
@@ -728,6 +729,7 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
     __shared__ T fb[2][TX + 4][W];
     __shared__ T ob[2][TX + 2][W];
     __shared__ double etab[32];
+    __shared__ int flw[TX];
     if (threadIdx.x < 32) etab[threadIdx.x] = exp2((double)threadIdx.x * (1.0 / 32));
 
     const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
@@ -809,13 +811,17 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 
     bool cfs;
     const int ie = colmap(i, cfs);
-    // halo columns staged by wavefronts 0..3; the halo x states are made by
-    // the edge wavefronts 0 (column i0-1) and TX-1 (column i0+TX)
+    // halo columns staged by wavefronts 0..3
     const int hcol = w < 2 ? i0 - 2 + w : i0 + TX + (w - 2);
     const int hpos = w < 2 ? w : TX + 2 + (w - 2);
     const bool hload = w < 4;
-    const bool sleft = w == 0, sright = w == TX - 1;
-    const int spos = sleft ? 0 : TX + 1;
+    // outgoing x states of the two halo cells next to the tile, one (side,
+    // array) unit per wavefront 0..3: side = w >> 1 (column i0 - 1 or
+    // i0 + TX), array = w & 1; flags from the adjacent tile cell's word
+    const bool hunit = w < 4;
+    const bool hright = (w >> 1) & 1;
+    const int hA = w & 1;
+    const int spos = hright ? TX + 1 : 0;
     bool hfs;
     const int he = colmap(hcol, hfs);
     const char *fcol[2], *hcolp[2], *fsr[2];
@@ -918,6 +924,7 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
                 fb[A][w + 2][v * 64 + lane] = f0[A][v];
                 if (hload) fb[A][hpos][v * 64 + lane] = hcur[A][v];
             }
+        if (lane == 0) flw[w] = FL0;
         lds_barrier();
 
         // outgoing x states of the own cell and of the halo cells
@@ -947,17 +954,34 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
             xstate(std::true_type{}, FL0, c, w + 1, ox, true);
         else
             xstate(std::false_type{}, 0, c, w + 1, ox, true);
-        if (sleft || sright) {
-            // flag word of the halo cell, from the own cell's flags
-            const int flh = sleft ? (((FL0 & CF_XM) ? CF_SOLID : 0) | ((FL0 & CF_XM2) ? CF_XM : 0) |
-                                     ((FL0 & CF_SOLID) ? CF_XP : 0))
-                                  : (((FL0 & CF_XP) ? CF_SOLID : 0) | ((FL0 & CF_SOLID) ? CF_XM : 0) |
-                                     ((FL0 & CF_XP2) ? CF_XP : 0));
-            T dummy[2][V];
+        if (hunit) {
+            // flag word of the halo cell, from the adjacent tile cell's flags
+            const int fa = uni(flw[hright ? TX - 1 : 0]);
+            const int flh = hright ? (((fa & CF_XP) ? CF_SOLID : 0) | ((fa & CF_SOLID) ? CF_XM : 0) |
+                                      ((fa & CF_XP2) ? CF_XP : 0))
+                                   : (((fa & CF_XM) ? CF_SOLID : 0) | ((fa & CF_XM2) ? CF_XM : 0) |
+                                      ((fa & CF_SOLID) ? CF_XP : 0));
+            // grid index of the halo cell: the adjacent tile cell one step out
+            const int ch_ = c + ((hright ? TX - 1 : 0) - w) + (hright ? 1 : -1);
+            auto hstate = [&](auto near_tag) {
+                constexpr bool NEAR = decltype(near_tag)::value;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    T fm = fb[hA][spos][v * 64 + lane];
+                    const T fc = fb[hA][spos + 1][v * 64 + lane];
+                    T fp = fb[hA][spos + 2][v * 64 + lane];
+                    if (NEAR && (flh & CF_XM)) fm = ghost_at<T>(d, hA, ch_, 0, koff[v] * (8 / ST));
+                    if (NEAR && (flh & CF_XP)) fp = ghost_at<T>(d, hA, ch_, 1, koff[v] * (8 / ST));
+                    T h = vl_half(fc - fm, fp - fc);
+                    if (NEAR && (flh & CF_SOLID)) h = T(0);
+                    ob[hA][spos][v * 64 + lane] = fma(sx[v], h, fc);
+                }
+                if (NEAR) __builtin_amdgcn_s_waitcnt(0);
+            };
             if (flh)
-                xstate(std::true_type{}, flh, sleft ? c - 1 : c + 1, spos, dummy, false);
+                hstate(std::true_type{});
             else
-                xstate(std::false_type{}, 0, 0, spos, dummy, false);
+                hstate(std::false_type{});
         }
         lds_barrier();
 
