@@ -76,11 +76,12 @@ def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     return out
 
 
-def sphere3d(n, steps, warmup):
+def sphere3d(n, steps, warmup, tiles):
     """Full-distribution 3D sphere leg (R=0.5 in [-4,4]^3, n^3 cells, 24^3
     velocity nodes on [-6,6]^3, Kn 0.1, Ma 1.5): FP64 and FP32-storage update
     rates, algorithmic HBM bytes per update launch over its HIP-event duration,
-    and the C_D difference of the two forms after the same steps.  The initial
+    HBM bytes from committed counter runs of the same kernel and tile, and
+    the C_D difference of the two forms after the same steps.  The initial
     state is drawn on the device from a counter-based generator (a host array
     of the 96^3 x 24^3 state would be 98 GB)."""
     import torch
@@ -92,7 +93,11 @@ def sphere3d(n, steps, warmup):
     for prec in ("f64", "f32"):
         s = ibdvm.Solver(case, precision=prec, stream=torch.cuda.Stream())
         s.init_freestream_hashed(0, 1e-3)
-        tile = s.autotune(reps=2)
+        if tiles[prec]:
+            s.set_tile(*tiles[prec])
+            tile = s.get_tile()
+        else:
+            tile = s.autotune(reps=2)
         s.step(warmup)
         s.profile(True)
         t = time.perf_counter()
@@ -106,6 +111,7 @@ def sphere3d(n, steps, warmup):
         out[prec] = {"updates_per_s": upd * steps / wall, "ms_per_step": wall * 1e3 / steps,
                      "update_avg_launch_ms": avg, "update_GBs_alg": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1), "tile": list(tile),
+                     "traffic": _traffic(f"sphere_{n}x{n}x{n}_v24x24x24", prec, tile),
                      "CD": cd, "fluid_cells": s.nfluid, "velocity_nodes": s.NV,
                      "footprint_GB": ibdvm.footprint(case, prec) / 1e9}
         del s
@@ -180,6 +186,8 @@ def main():
     ap.add_argument("--serving-cap", type=int, default=2000, help="step cap per serving request")
     ap.add_argument("--sphere", type=int, default=96, help="cells per side of the 3D sphere leg (0: skip)")
     ap.add_argument("--sphere-steps", type=int, default=10)
+    ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
+    ap.add_argument("--sphere-tile32", type=str, default="2,16,256", help="V,TX,LY of the FP32 3D update")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -247,7 +255,9 @@ def main():
                                   "CD_f64": r64["cd"], "update_avg_launch_ms": avg32,
                                   "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9}
     if args.sphere > 0:
-        line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2)
+        parse = lambda t: tuple(int(x) for x in t.split(",")) if t else None
+        line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2,
+                                    {"f64": parse(args.sphere_tile), "f32": parse(args.sphere_tile32)})
     if args.serving > 0:
         line["serving"] = serving(args.serving, args.serving_cap, 1e-4, 0.5)
     if not args.no_cpu:

@@ -193,9 +193,23 @@ ibdvm_status ibdvm_pair_geometry(const ibdvm_ctx *ctx, double *g9, double *wg);
  * [arrays][npairs][nodes] and rho_w[npairs].  Synchronises. */
 ibdvm_status ibdvm_wall_state(ibdvm_ctx *ctx, double *ghost, double *face, double *rho_w);
 
-/* Advances several contexts that share one stream by nsteps each, interleaving
- * their launches step by step (serving form).  Results equal those of
- * advancing each context alone. */
+/* Rebinds the context to another stream of the same device (NULL: the
+ * legacy default stream) after the work queued on its current stream has
+ * finished (synchronises that stream).  Graphs captured earlier replay on
+ * the new stream.  Serving uses it to move a solve prepared on its own
+ * stream into a batch. */
+ibdvm_status ibdvm_set_stream(ibdvm_ctx *ctx, void *stream);
+
+/* Advances n contexts that share one stream and device by nsteps each
+ * (serving form).  Each step is fused across the contexts: every ghost-fill
+ * phase is one launch per (dimension, storage) group and the 2D update one
+ * launch per (storage, V, TX) tile group, over the workgroups of all the
+ * group's solves (at most 16 solves per launch); the 3D update is launched
+ * per context.  Every solve does the same arithmetic as alone, so results
+ * equal those of advancing each context alone bit for bit.  IBDVM_E_INVALID_ARG
+ * if the contexts do not share a stream or one appears twice.  Only
+ * enqueues; kernel timing (ibdvm_profile) is not recorded for these
+ * launches. */
 ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps);
 
 /* Tile of the marching update kernel: V velocity nodes per lane (1 or 2),
@@ -241,6 +255,11 @@ ibdvm_status ibdvm_init_freestream_hashed(ibdvm_ctx *ctx, uint64_t seed, double 
  * The graph must be destroyed before its context. */
 typedef struct ibdvm_graph ibdvm_graph;
 ibdvm_status ibdvm_graph_create(ibdvm_ctx *ctx, int32_t nsteps, ibdvm_graph **out);
+/* The same for the fused steps of ibdvm_batch_step over n contexts sharing
+ * a stream: one graph of nsteps fused steps; a replay advances every
+ * context by nsteps and gives the bits of ibdvm_batch_step(ctxs, n, nsteps).
+ * The graph must be destroyed before any of its contexts. */
+ibdvm_status ibdvm_batch_graph_create(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps, ibdvm_graph **out);
 ibdvm_status ibdvm_graph_launch(ibdvm_graph *graph);
 void ibdvm_graph_destroy(ibdvm_graph *graph);
 
@@ -249,10 +268,17 @@ void ibdvm_graph_destroy(ibdvm_graph *graph);
  * footprint from the caller's workspace (256-byte aligned, kept by the
  * caller until ibdvm_server_destroy).  Requests are admitted in submission
  * order as soon as a block of their footprint and one of max_active slots
- * are free; each active solve has its own stream and a captured graph of
- * steps_per_replay steps (even), replayed until |C_D(n) - C_D(n - K)| < tol
- * (tol <= 0: never) or max_steps steps are done; then its memory and slot
- * go back to the queue.  A tile shape per (grid, velocity grid, precision)
+ * are free.  Solves below the fusion limit (ibdvm_server_set_fusion) form
+ * the fused group on the server's stream: one captured graph of
+ * steps_per_replay (K, even) fused steps over the group
+ * (ibdvm_batch_graph_create) is replayed, and captured again whenever a
+ * member joins or leaves.  Larger solves run standalone, each with its own
+ * stream and captured graph of K steps, concurrently with the group.  A new
+ * solve is created on its own stream while replays run and joins the group
+ * at its next replay.  After each replay the C_D of every solve in it is
+ * checked; a solve finishes when |C_D(n) - C_D(n - K)| < tol (tol <= 0:
+ * never) or max_steps steps are done, and its memory and slot go back to the
+ * queue.  A tile shape per (grid, velocity grid, precision)
  * is chosen once by ibdvm_autotune and reused.  Single-threaded: one thread
  * submits and polls. */
 typedef struct ibdvm_server ibdvm_server;
@@ -286,6 +312,10 @@ ibdvm_status ibdvm_server_poll(ibdvm_server *srv, int32_t block, ibdvm_result *d
 /* out = queued, active, finished, workspace bytes in use, workspace bytes. */
 ibdvm_status ibdvm_server_info(const ibdvm_server *srv, int64_t out[5]);
 double ibdvm_server_clock(const ibdvm_server *srv);
+/* Solves with fewer than updates_per_step cell x node updates per step join
+ * the fused group; larger ones run standalone (default 2^24; 0: none fused).
+ * Applies to solves admitted afterwards. */
+ibdvm_status ibdvm_server_set_fusion(ibdvm_server *srv, int64_t updates_per_step);
 const char *ibdvm_server_error(const ibdvm_server *srv);
 /* Waits for the active solves and releases them; queued ones are dropped. */
 void ibdvm_server_destroy(ibdvm_server *srv);

@@ -80,4 +80,17 @@ struct Dev {
     Ctrl *ctrl;
 };
 
+// argument block of a launch over several solves (serving form): solve s
+// owns workgroups blk0[s] .. blk0[s+1]-1 of the launch; its parameter block
+// is dev[s] (a copy of its Dev in its own workspace)
+constexpr int kMaxBatch = 16;
+struct BatchArgs {
+    int n;
+    int cur[kMaxBatch], slot[kMaxBatch];
+    int LY[kMaxBatch], ntx[kMaxBatch], nys[kMaxBatch], ncv[kMaxBatch];
+    int nfill[kMaxBatch];
+    long long blk0[kMaxBatch + 1];
+    const Dev *dev[kMaxBatch];
+};
+
 }  // namespace ibdvm

@@ -31,6 +31,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
     size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, fwall, rhow, fillpart, pforce, ctrl;
+    size_t devcopy;  // the context's Dev, read by launches over several solves
     size_t total;
     size_t state_bytes;  // one array of one buffer
 };
@@ -76,6 +77,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * 4 * 8);
     L.ctrl = take(sizeof(ibdvm::Ctrl));
+    L.devcopy = take(sizeof(ibdvm::Dev));
     L.total = off;
     return L;
 }
@@ -240,6 +242,14 @@ ibdvm_status mark(ibdvm_ctx *c, int kind)
     return IBDVM_OK;
 }
 
+// the device copy of the context's Dev (launches over several solves read it)
+ibdvm_status put_dev(ibdvm_ctx *c)
+{
+    HIP_CHECK(hipMemcpyAsync(c->ws + c->L.devcopy, &c->dev, sizeof(c->dev), hipMemcpyHostToDevice, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    return IBDVM_OK;
+}
+
 ibdvm_status one_step(ibdvm_ctx *c)
 {
     const int slot = (int)(c->step & 1);
@@ -263,6 +273,105 @@ ibdvm_status finish_pending(ibdvm_ctx *c)
     if (!c->pending) return IBDVM_OK;
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), false, true, c->stream));
     c->pending = false;
+    return IBDVM_OK;
+}
+
+// ---- launches over several contexts that share one stream (serving form).
+// Every fill phase is one launch per (dimension, storage) group and the 2D
+// update one launch per (storage, V, TX) group, each over the workgroups of
+// all the group's solves (at most kMaxBatch per launch); the 3D update is
+// launched per context.  Each solve's arithmetic is that of one_step.
+
+void batch_entry(ibdvm::BatchArgs &a, int q, const ibdvm_ctx *c)
+{
+    a.dev[q] = (const ibdvm::Dev *)(c->ws + c->L.devcopy);
+    a.cur[q] = c->cur;
+    a.slot[q] = (int)(c->step & 1);
+}
+
+// the fill phases (fill) and the moment finish of pending contexts
+ibdvm_status fused_fill(ibdvm_ctx *const *cs, int n, bool fill, hipStream_t stream)
+{
+    for (int D = 2; D <= 3; ++D)
+        for (int prec = 0; prec < 2; ++prec) {
+            std::vector<ibdvm_ctx *> grp;
+            for (int i = 0; i < n; ++i)
+                if (cs[i]->prob.dim == D && cs[i]->precision == prec) grp.push_back(cs[i]);
+            for (size_t b = 0; b < grp.size(); b += ibdvm::kMaxBatch) {
+                const int m = (int)std::min<size_t>(ibdvm::kMaxBatch, grp.size() - b);
+                ibdvm::BatchArgs fin{}, spec{}, ghost{};
+                fin.n = spec.n = ghost.n = m;
+                for (int q = 0; q < m; ++q) {
+                    const ibdvm_ctx *c = grp[b + q];
+                    const int nfc = (c->geo.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk;
+                    const int nfill = fill ? c->dev.npairs * nfc : 0;
+                    const int nfin = c->pending ? (c->geo.Nc + 3) / 4 : 0;
+                    for (ibdvm::BatchArgs *a : {&fin, &spec, &ghost}) {
+                        batch_entry(*a, q, c);
+                        a->nfill[q] = nfill;
+                    }
+                    fin.blk0[q + 1] = fin.blk0[q] + nfill + nfin;
+                    spec.blk0[q + 1] = spec.blk0[q] + (c->dev.alpha < 1.0 ? nfill : 0);
+                    ghost.blk0[q + 1] = ghost.blk0[q] + nfill;
+                }
+                HIP_CHECK(ibdvm::launch_fill_batch(D, prec, fin, spec, ghost, stream));
+            }
+        }
+    for (int i = 0; i < n; ++i) cs[i]->pending = false;
+    return IBDVM_OK;
+}
+
+ibdvm_status fused_step(ibdvm_ctx *const *cs, int n, hipStream_t stream)
+{
+    ibdvm_status st = fused_fill(cs, n, true, stream);
+    if (st) return st;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int V = 1; V <= 2; ++V)
+            for (int TX = 4; TX <= 8; TX += 4) {
+                std::vector<ibdvm_ctx *> grp;
+                for (int i = 0; i < n; ++i) {
+                    const ibdvm_ctx *c = cs[i];
+                    if (c->prob.dim == 2 && c->precision == prec && c->tile.V == V && c->tile.TX == TX)
+                        grp.push_back(cs[i]);
+                }
+                for (size_t b = 0; b < grp.size(); b += ibdvm::kMaxBatch) {
+                    const int m = (int)std::min<size_t>(ibdvm::kMaxBatch, grp.size() - b);
+                    ibdvm::BatchArgs a{};
+                    a.n = m;
+                    for (int q = 0; q < m; ++q) {
+                        const ibdvm_ctx *c = grp[b + q];
+                        batch_entry(a, q, c);
+                        a.LY[q] = c->tile.LY;
+                        a.ntx[q] = (c->prob.n[0] + TX - 1) / TX;
+                        a.nys[q] = (c->prob.n[1] + c->tile.LY - 1) / c->tile.LY;
+                        a.ncv[q] = (c->geo.NV + 64 * V - 1) / (64 * V);
+                        a.blk0[q + 1] = a.blk0[q] + (long long)a.ntx[q] * a.nys[q] * a.ncv[q];
+                    }
+                    HIP_CHECK(ibdvm::launch_update2d_batch(prec, V, TX, a, stream));
+                }
+            }
+    for (int i = 0; i < n; ++i) {
+        ibdvm_ctx *c = cs[i];
+        if (c->prob.dim == 3)
+            HIP_CHECK(ibdvm::launch_update3d(c->dev, c->precision, c->cur, (int)(c->step & 1), c->tile, stream));
+        c->cur ^= 1;
+        c->step += 1;
+        c->pending = true;
+    }
+    return IBDVM_OK;
+}
+
+ibdvm_status check_batch(ibdvm_ctx *const *ctxs, int32_t n)
+{
+    if (!ctxs || n < 0) return fail(IBDVM_E_INVALID_ARG, "bad batch arguments");
+    for (int32_t i = 0; i < n; ++i) {
+        ibdvm_status st = require_device(ctxs[i]);
+        if (st) return st;
+        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
+            return fail(IBDVM_E_INVALID_ARG, "batched contexts must share one stream and device");
+        for (int32_t j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(IBDVM_E_INVALID_ARG, "a context appears twice in the batch");
+    }
     return IBDVM_OK;
 }
 
@@ -558,6 +667,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
         return fail(IBDVM_E_DEVICE, std::string("table upload: ") + hipGetErrorString(e));
     }
     st = reset_clock(c);
+    if (!st) st = put_dev(c);
     const double *no_noise[2] = {nullptr, nullptr};
     if (!st) st = upload_state(c, nullptr, no_noise, 0.0);
     if (!st) st = refresh_moments(c);
@@ -657,44 +767,59 @@ ibdvm_status ibdvm_step(ibdvm_ctx *c, int32_t nsteps)
 }
 
 struct ibdvm_graph {
-    ibdvm_ctx *ctx = nullptr;
+    std::vector<ibdvm_ctx *> ctxs;
+    std::vector<int> cur0, parity0;  // buffer and tau slot the captured launches address
     int32_t nsteps = 0;
-    int cur0 = 0, parity0 = 0;  // buffer and tau slot the captured launches address
+    bool fused = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
 
-ibdvm_status ibdvm_graph_create(ibdvm_ctx *c, int32_t nsteps, ibdvm_graph **out)
+namespace {
+// captures nsteps steps of the contexts (one context: its own launches; more:
+// the fused launches) on their stream, starting and ending with the moments
+// finished, as ibdvm_step and ibdvm_batch_step leave them
+ibdvm_status capture(ibdvm_ctx *const *cs, int32_t n, int32_t nsteps, bool fused, ibdvm_graph **out)
 {
-    ibdvm_status st = require_device(c);
-    if (st) return st;
     if (!out) return fail(IBDVM_E_INVALID_ARG, "null output");
     *out = nullptr;
+    if (n < 1) return fail(IBDVM_E_INVALID_ARG, "empty batch");
     if (nsteps < 2 || (nsteps & 1)) return fail(IBDVM_E_INVALID_ARG, "graph step count must be even and >= 2");
-    if (c->profiling) return fail(IBDVM_E_STATE, "profiling is on; turn it off before capturing");
-    if (!c->stream) return fail(IBDVM_E_STATE, "capture needs a stream other than the legacy default stream");
-    HIP_CHECK(hipSetDevice(c->device));
-    // the capture starts and ends with the moments finished, as ibdvm_step leaves them
-    if ((st = finish_pending(c))) return st;
-    HIP_CHECK(hipStreamSynchronize(c->stream));
-    const int cur0 = c->cur;
-    const long long step0 = c->step;
+    for (int32_t i = 0; i < n; ++i)
+        if (cs[i]->profiling) return fail(IBDVM_E_STATE, "profiling is on; turn it off before capturing");
+    hipStream_t stream = cs[0]->stream;
+    if (!stream) return fail(IBDVM_E_STATE, "capture needs a stream other than the legacy default stream");
+    HIP_CHECK(hipSetDevice(cs[0]->device));
+    ibdvm_status st = IBDVM_OK;
+    if (fused)
+        st = fused_fill(cs, n, false, stream);
+    else
+        st = finish_pending(cs[0]);
+    if (st) return st;
+    HIP_CHECK(hipStreamSynchronize(stream));
     auto *g = new ibdvm_graph;
-    g->ctx = c;
     g->nsteps = nsteps;
-    g->cur0 = cur0;
-    g->parity0 = (int)(step0 & 1);
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    g->fused = fused;
+    std::vector<long long> step0(n);
+    for (int32_t i = 0; i < n; ++i) {
+        g->ctxs.push_back(cs[i]);
+        g->cur0.push_back(cs[i]->cur);
+        g->parity0.push_back((int)(cs[i]->step & 1));
+        step0[i] = cs[i]->step;
+    }
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int32_t i = 0; i < nsteps && !st; ++i) st = one_step(c);
-        if (!st) st = finish_pending(c);
-        hipError_t e2 = hipStreamEndCapture(c->stream, &g->graph);
+        for (int32_t k = 0; k < nsteps && !st; ++k) st = fused ? fused_step(cs, n, stream) : one_step(cs[0]);
+        if (!st) st = fused ? fused_fill(cs, n, false, stream) : finish_pending(cs[0]);
+        hipError_t e2 = hipStreamEndCapture(stream, &g->graph);
         if (!st && e2 != hipSuccess) e = e2;
     }
     // capturing records the launches without running them
-    c->cur = cur0;
-    c->step = step0;
-    c->pending = false;
+    for (int32_t i = 0; i < n; ++i) {
+        cs[i]->cur = g->cur0[i];
+        cs[i]->step = step0[i];
+        cs[i]->pending = false;
+    }
     if (e == hipSuccess && !st) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
     if (e != hipSuccess || st) {
         (void)hipGetLastError();  // leave no stale error for the next launch check
@@ -704,18 +829,38 @@ ibdvm_status ibdvm_graph_create(ibdvm_ctx *c, int32_t nsteps, ibdvm_graph **out)
     *out = g;
     return IBDVM_OK;
 }
+}  // namespace
+
+ibdvm_status ibdvm_graph_create(ibdvm_ctx *c, int32_t nsteps, ibdvm_graph **out)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    return capture(&c, 1, nsteps, false, out);
+}
+
+ibdvm_status ibdvm_batch_graph_create(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps, ibdvm_graph **out)
+{
+    ibdvm_status st = check_batch(ctxs, n);
+    if (st) return st;
+    return capture(ctxs, n, nsteps, true, out);
+}
 
 ibdvm_status ibdvm_graph_launch(ibdvm_graph *g)
 {
     if (!g || !g->exec) return fail(IBDVM_E_INVALID_ARG, "null graph");
-    ibdvm_status st = require_device(g->ctx);
+    const int n = (int)g->ctxs.size();
+    for (int i = 0; i < n; ++i) {
+        ibdvm_ctx *c = g->ctxs[i];
+        ibdvm_status st = require_device(c);
+        if (st) return st;
+        if (c->cur != g->cur0[i] || (int)(c->step & 1) != g->parity0[i])
+            return fail(IBDVM_E_STATE, "context advanced by an odd number of steps since the capture");
+    }
+    HIP_CHECK(hipSetDevice(g->ctxs[0]->device));
+    ibdvm_status st = g->fused ? fused_fill(g->ctxs.data(), n, false, g->ctxs[0]->stream) : finish_pending(g->ctxs[0]);
     if (st) return st;
-    if (g->ctx->cur != g->cur0 || (int)(g->ctx->step & 1) != g->parity0)
-        return fail(IBDVM_E_STATE, "context advanced by an odd number of steps since the capture");
-    HIP_CHECK(hipSetDevice(g->ctx->device));
-    if ((st = finish_pending(g->ctx))) return st;
-    HIP_CHECK(hipGraphLaunch(g->exec, g->ctx->stream));
-    g->ctx->step += g->nsteps;
+    HIP_CHECK(hipGraphLaunch(g->exec, g->ctxs[0]->stream));
+    for (ibdvm_ctx *c : g->ctxs) c->step += g->nsteps;
     return IBDVM_OK;
 }
 
@@ -727,27 +872,27 @@ void ibdvm_graph_destroy(ibdvm_graph *g)
     delete g;
 }
 
+ibdvm_status ibdvm_set_stream(ibdvm_ctx *c, void *stream)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->stream = (hipStream_t)stream;
+    return IBDVM_OK;
+}
+
 ibdvm_status ibdvm_batch_step(ibdvm_ctx *const *ctxs, int32_t n, int32_t nsteps)
 {
-    if (!ctxs || n < 0 || nsteps < 0) return fail(IBDVM_E_INVALID_ARG, "bad batch arguments");
-    for (int32_t i = 0; i < n; ++i) {
-        ibdvm_status st = require_device(ctxs[i]);
-        if (st) return st;
-        if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device)
-            return fail(IBDVM_E_INVALID_ARG, "batched contexts must share one stream and device");
-    }
+    ibdvm_status st = check_batch(ctxs, n);
+    if (st) return st;
+    if (nsteps < 0) return fail(IBDVM_E_INVALID_ARG, "negative step count");
     if (n == 0) return IBDVM_OK;
     HIP_CHECK(hipSetDevice(ctxs[0]->device));
-    for (int32_t s = 0; s < nsteps; ++s)
-        for (int32_t i = 0; i < n; ++i) {
-            ibdvm_status st = one_step(ctxs[i]);
-            if (st) return st;
-        }
-    for (int32_t i = 0; i < n; ++i) {
-        ibdvm_status st = finish_pending(ctxs[i]);
-        if (st) return st;
-    }
-    return IBDVM_OK;
+    for (int32_t k = 0; k < nsteps; ++k)
+        if ((st = fused_step(ctxs, n, ctxs[0]->stream))) return st;
+    return fused_fill(ctxs, n, false, ctxs[0]->stream);
 }
 
 ibdvm_status ibdvm_moments(ibdvm_ctx *c, double *out, int32_t out_is_device)
@@ -866,7 +1011,7 @@ ibdvm_status ibdvm_set_tile(ibdvm_ctx *c, int32_t V, int32_t TX, int32_t LY)
     if ((st = finish_pending(c))) return st;
     c->tile = t;
     c->dev.nchunk = (c->geo.NV + 64 * V - 1) / (64 * V);
-    return IBDVM_OK;
+    return put_dev(c);
 }
 
 ibdvm_status ibdvm_get_tile(const ibdvm_ctx *c, int32_t out[3])
@@ -914,7 +1059,7 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
                 HIP_CHECK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) {
+                if (ms < 0.99f * best_ms) {  // ties within 1 % keep the earlier candidate, so repeated runs agree
                     best_ms = ms;
                     best = t;
                 }
@@ -924,6 +1069,7 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *c, int32_t reps, int32_t out[3])
     HIP_CHECK(hipMemcpy(c->ws + c->L.ctrl, &saved, sizeof(saved), hipMemcpyHostToDevice));
     c->tile = best;
     c->dev.nchunk = (c->geo.NV + 64 * best.V - 1) / (64 * best.V);
+    if ((st = put_dev(c))) return st;
     if (out) {
         out[0] = best.V;
         out[1] = best.TX;

@@ -82,7 +82,8 @@ __device__ __forceinline__ T neighbour(const Dev &d, const T *f, int A, int k, i
 }
 
 // the cell parameters of one fluid cell from its moments; returns tau
-__device__ double write_cell(const Dev &d, int c, double rho, const double U[3], double T, const double q[3], int D)
+template <typename DR>
+__device__ double write_cell(const DR &d, int c, double rho, const double U[3], double T, const double q[3], int D)
 {
     double tau = d.mu0 * pow(T, d.omega) / (0.5 * rho * T);
     double *cp = d.cellp + (size_t)c * kCellWords;
@@ -128,7 +129,8 @@ __device__ double write_cell(const Dev &d, int c, double rho, const double U[3],
     return bad ? INFINITY : tau;
 }
 
-__device__ __forceinline__ void tau_min_commit(const Dev &d, int slot, double tau)
+template <typename DR>
+__device__ __forceinline__ void tau_min_commit(const DR &d, int slot, double tau)
 {
     __shared__ double red[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -161,7 +163,8 @@ __device__ __forceinline__ double block_sum(double v)
 }
 
 // multilinear interpolation on the velocity nodes, zero outside the node hull
-__device__ double vel_interp(const Dev &d, const double *g, const double v[3], int D)
+template <typename DR>
+__device__ double vel_interp(const DR &d, const double *g, const double v[3], int D)
 {
     int i0[3] = {0, 0, 0};
     double t[3] = {0, 0, 0};
@@ -199,11 +202,12 @@ __device__ double vel_interp(const Dev &d, const double *g, const double v[3], i
 // (3) the wall density from all partials, the wall distribution, the ghost
 // value and the ghost-side face value.
 
-__device__ __forceinline__ int fill_chunks(const Dev &d) { return (d.NV + kFillChunk - 1) / kFillChunk; }
+template <typename DR>
+__device__ __forceinline__ int fill_chunks(const DR &d) { return (d.NV + kFillChunk - 1) / kFillChunk; }
 
 // reflected node velocity xi - 2 (xi . n) n and the normal component xi . n
-template <int D>
-__device__ __forceinline__ double reflect(const Dev &d, int k, const double nw[3], double v[3])
+template <int D, typename DR>
+__device__ __forceinline__ double reflect(const DR &d, int k, const double nw[3], double v[3])
 {
     double dn = 0.0;
     for (int b = 0; b < D; ++b) dn += d.xi[b][k] * nw[b];
@@ -211,8 +215,8 @@ __device__ __forceinline__ double reflect(const Dev &d, int k, const double nw[3
     return dn;
 }
 
-template <int D, typename T>
-__device__ void fill_incident(const Dev &d, int cur, int p, int chunk)
+template <int D, typename T, typename DR>
+__device__ void fill_incident(const DR &d, int cur, int p, int chunk)
 {
     const DPair &P = d.pairs[p];
     const int dc = P.dc, ac = P.ac, ns = P.ns;
@@ -282,8 +286,8 @@ __device__ void fill_incident(const Dev &d, int cur, int p, int chunk)
     if (threadIdx.x == 0) d.fillpart[((size_t)p * fill_chunks(d) + chunk) * 2] = num;
 }
 
-template <int D>
-__device__ void fill_specular(const Dev &d, int p, int chunk)
+template <int D, typename DR>
+__device__ void fill_specular(const DR &d, int p, int chunk)
 {
     const DPair &P = d.pairs[p];
     const size_t po = (size_t)p * d.NV;
@@ -303,8 +307,8 @@ __device__ void fill_specular(const Dev &d, int p, int chunk)
     if (threadIdx.x == 0) d.fillpart[((size_t)p * fill_chunks(d) + chunk) * 2 + 1] = num;
 }
 
-template <int D>
-__device__ void fill_ghost(const Dev &d, int p, int chunk)
+template <int D, typename DR>
+__device__ void fill_ghost(const DR &d, int p, int chunk)
 {
     const DPair &P = d.pairs[p];
     const double ygc = P.ygc, yw = P.yw, ysp = P.ysp, yface = P.yface;
@@ -343,8 +347,8 @@ __device__ void fill_ghost(const Dev &d, int p, int chunk)
 }
 
 // ---------------------------------------------------------------- moments
-template <int D>
-__device__ void fin_cells(const Dev &d, int slot, int blk)
+template <int D, typename DR>
+__device__ void fin_cells(const DR &d, int slot, int blk)
 {
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -426,6 +430,53 @@ __global__ __launch_bounds__(256) void k_fill_ghost(Dev d)
 {
     const int nfc = fill_chunks(d);
     fill_ghost<D>(d, blockIdx.x / nfc, blockIdx.x % nfc);
+}
+
+// workgroups are dispatched round-robin over the 8 XCDs; each XCD gets a
+// contiguous run of tiles so that x-neighbouring tiles share its L2
+__device__ __forceinline__ long long xcd_run(int nb) { return (long long)(blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3); }
+
+// wavefront-uniform position of workgroup run index L in a batch: the solve
+// s with blk0[s] <= L < blk0[s + 1]
+__device__ __forceinline__ int batch_solve(const BatchArgs &a, long long L)
+{
+    int s = 0;
+    while (s + 1 < a.n && L >= a.blk0[s + 1]) ++s;
+    return s;
+}
+typedef const __attribute__((address_space(4))) Dev *cdev_p;
+
+// the three fill phases over the (pair, chunk) workgroups of several solves
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_fill_fin_batch(BatchArgs a)
+{
+    const int s = batch_solve(a, blockIdx.x);
+    const auto &d = *(cdev_p)a.dev[s];
+    const int b = blockIdx.x - (int)a.blk0[s];
+    if (b < a.nfill[s]) {
+        const int nfc = fill_chunks(d);
+        fill_incident<D, T>(d, a.cur[s], b / nfc, b % nfc);
+        return;
+    }
+    fin_cells<D>(d, a.slot[s], b - a.nfill[s]);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_specular_batch(BatchArgs a)
+{
+    const int s = batch_solve(a, blockIdx.x);
+    const auto &d = *(cdev_p)a.dev[s];
+    const int b = blockIdx.x - (int)a.blk0[s], nfc = fill_chunks(d);
+    fill_specular<D>(d, b / nfc, b % nfc);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_fill_ghost_batch(BatchArgs a)
+{
+    const int s = batch_solve(a, blockIdx.x);
+    const auto &d = *(cdev_p)a.dev[s];
+    const int b = blockIdx.x - (int)a.blk0[s], nfc = fill_chunks(d);
+    fill_ghost<D>(d, b / nfc, b % nfc);
 }
 
 // direct two-pass moments of the current state (after create / set_state)
@@ -690,14 +741,14 @@ __device__ __forceinline__ double exp_neg(double x, const double *tab)
 
 // ghost value / ghost-side face value of the pair seen from fluid cell c in
 // direction dir (2 axis + side), at byte offset k8 = 8 k of node k
-template <typename T>
-__device__ __forceinline__ T ghost_at(const Dev &d, int A, int c, int dir, int k8)
+template <typename T, typename DR>
+__device__ __forceinline__ T ghost_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     return (T)bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
 }
-template <typename T>
-__device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int k8)
+template <typename T, typename DR>
+__device__ __forceinline__ T facev_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     return (T)bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
@@ -718,9 +769,8 @@ __device__ __forceinline__ T facev_at(const Dev &d, int A, int c, int dir, int k
 // near path with the pair ghost and face values; every other row runs a
 // branch-free path whose only memory traffic is the prefetch, the stores, the
 // partial record and the next row's cell record, so loads stay in flight.
-template <typename T, int V, int TX>
-__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
-void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
+template <typename T, int V, int TX, typename DR>
+__device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, int LY, int ntx, int nys, int ncv, int L)
 {
     constexpr int W = 64 * V;
     constexpr int ST = (int)sizeof(T);
@@ -734,17 +784,12 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 
     const double tmin = __longlong_as_double((long long)d.ctrl->tau_bits[slot]);
     const double dt = d.cfl / (d.adv + 1.0 / tmin);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (L == 0 && threadIdx.x == 0) {
         d.ctrl->tau_bits[slot ^ 1] = kInfBits;
         d.ctrl->dt = dt;
         d.ctrl->time += dt;
         d.ctrl->step += 1;
     }
-    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous run of tiles so that x-neighbouring tiles share its L2
-    const int nb = gridDim.x;
-    const int L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
-    if (L >= ntx * nys * ncv) return;
     const int tx = L % ntx, ys = (L / ntx) % nys, ch = L / (ntx * nys);
     const int nx = d.n[0], ny = d.n[1], NV = d.NV;
     const int i0 = tx * TX, j0 = ys * LY, j1 = min(j0 + LY, ny);
@@ -1081,6 +1126,30 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
         row(std::integral_constant<int, 3>{});
         if (++j >= j1) break;
     }
+}
+
+
+template <typename T, int V, int TX>
+__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
+void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
+{
+    const long long L = xcd_run(gridDim.x);
+    if (L >= (long long)ntx * nys * ncv) return;
+    update2d_tile<T, V, TX>(d, cur, slot, LY, ntx, nys, ncv, (int)L);
+}
+
+// one launch over the tiles of several solves (serving form): the solves'
+// parameter blocks live in their workspaces, the per-solve launch values in
+// the argument block
+template <typename T, int V, int TX>
+__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
+void k_update2d_batch(BatchArgs a)
+{
+    const long long L = xcd_run(gridDim.x);
+    if (L >= a.blk0[a.n]) return;
+    const int s = batch_solve(a, L);
+    const auto &d = *(cdev_p)a.dev[s];
+    update2d_tile<T, V, TX>(d, a.cur[s], a.slot[s], a.LY[s], a.ntx[s], a.nys[s], a.ncv[s], (int)(L - a.blk0[s]));
 }
 
 // ---------------------------------------------------------------- 3D update, marching in z
@@ -1677,6 +1746,52 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     }
 #undef U2D
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_update2d_batch(int storage, int V, int TX, const BatchArgs &a, hipStream_t s)
+{
+    long long nblk = a.blk0[a.n];
+    if (nblk == 0) return hipSuccess;
+    nblk = (nblk + 7) / 8 * 8;
+    if (nblk >= (1ll << 31)) return hipErrorInvalidValue;
+    dim3 grid((unsigned)nblk), block(64 * TX);
+#define U2B(TT, VV, XX)                                                                \
+    if (V == VV && TX == XX) {                                                      \
+        hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX>), grid, block, 0, s, a); \
+        return hipGetLastError();                                                   \
+    }
+    if (storage == 0) {
+        U2B(double, 1, 4) U2B(double, 1, 8) U2B(double, 2, 4) U2B(double, 2, 8)
+    } else {
+        U2B(float, 1, 4) U2B(float, 1, 8) U2B(float, 2, 4) U2B(float, 2, 8)
+    }
+#undef U2B
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
+                             hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (fin.blk0[fin.n] > 0) {
+        DISPATCH(D, storage, hipLaunchKernelGGL((k_fill_fin_batch<DD, TT>), dim3((unsigned)fin.blk0[fin.n]), dim3(256), 0, s, fin));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (spec.blk0[spec.n] > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL((k_fill_specular_batch<2>), dim3((unsigned)spec.blk0[spec.n]), dim3(256), 0, s, spec);
+        else
+            hipLaunchKernelGGL((k_fill_specular_batch<3>), dim3((unsigned)spec.blk0[spec.n]), dim3(256), 0, s, spec);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (ghost.blk0[ghost.n] > 0) {
+        if (D == 2)
+            hipLaunchKernelGGL((k_fill_ghost_batch<2>), dim3((unsigned)ghost.blk0[ghost.n]), dim3(256), 0, s, ghost);
+        else
+            hipLaunchKernelGGL((k_fill_ghost_batch<3>), dim3((unsigned)ghost.blk0[ghost.n]), dim3(256), 0, s, ghost);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s)

@@ -2,12 +2,20 @@
 // on one device.  Requests of different grids, velocity grids and physics
 // queue up, are admitted in arrival order whenever a block of the server's
 // workspace large enough for their footprint and an active slot are free,
-// keep their state resident, and advance concurrently: each active solve owns
-// a stream and a captured HIP graph of K steps, replayed until the drag
-// coefficient settles (|C_D(n) - C_D(n - K)| < tol) or a step cap is reached.
-// Finished solves release their memory and slot to the queue at once.
+// and keep their state resident.  Solves smaller than a fusion limit (cell
+// x node updates per step) form the fused group: they advance together on
+// the server's stream, where one captured HIP graph of K fused steps over
+// the group (each step one launch per fill phase and per update tile group,
+// spanning the workgroups of all members) is replayed and captured again
+// when a member joins or leaves.  Larger solves fill the device on their own
+// and run standalone: each has its own stream and captured graph of K
+// steps, concurrent with the group.  A new solve is prepared on its own
+// stream while replays run and joins the group at the group's next replay.
+// After each replay the drag coefficient of every solve in it is checked; a
+// solve ends when |C_D(n) - C_D(n - K)| < tol or a step cap is reached, and
+// releases its memory and slot to the queue.
 //
-// Built on the public C ABI only (ibdvm_create, ibdvm_graph_*, ...).
+// Built on the public C ABI only (ibdvm_create, ibdvm_batch_graph_create, ...).
 #include <hip/hip_runtime_api.h>
 
 #include <chrono>
@@ -93,11 +101,13 @@ struct Request {
 struct Active {
     Request rq;
     size_t off = 0;
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
     ibdvm_ctx *ctx = nullptr;
-    ibdvm_graph *graph = nullptr;
-    bool inflight = false;
+    bool fused = false;           // member of the fused group
+    bool joined = false;          // fused: on the server stream, in the group graph
+    hipStream_t stream = nullptr; // standalone solves; fused ones until they join
+    hipEvent_t done = nullptr;    // standalone: end of its replay in flight
+    ibdvm_graph *graph = nullptr; // standalone: K captured steps
+    bool inflight = false;        // standalone
     int64_t steps = 0, updates_per_step = 0;
     double cd_prev = NAN, cd = NAN, cl = NAN;
     double t_admit = 0;
@@ -111,6 +121,11 @@ struct ibdvm_server {
     Arena arena;
     int32_t max_active = 1, K = 100;
     int device = 0;
+    int64_t fuse_below = 1 << 24;   // solves with fewer updates per step join the fused group
+    hipStream_t stream = nullptr;   // the fused group's stream
+    hipEvent_t done = nullptr;      // end of the group replay in flight
+    ibdvm_graph *graph = nullptr;   // K fused steps of the group; null when the group changed
+    bool inflight = false;
     int64_t next_id = 1, finished = 0;
     std::deque<Request> queue;
     std::vector<Active> active;
@@ -129,8 +144,16 @@ ibdvm_status hip_fail(ibdvm_server *s, hipError_t e, const char *what)
     return IBDVM_E_DEVICE;
 }
 
+// the active set changes: the captured graph addresses its contexts
+void drop_graph(ibdvm_server *s)
+{
+    if (s->graph) ibdvm_graph_destroy(s->graph);
+    s->graph = nullptr;
+}
+
 void release(ibdvm_server *s, Active &a)
 {
+    if (a.joined) drop_graph(s);
     if (a.graph) ibdvm_graph_destroy(a.graph);
     if (a.ctx) ibdvm_destroy(a.ctx);
     if (a.done) (void)hipEventDestroy(a.done);
@@ -162,12 +185,13 @@ void retire(ibdvm_server *s, Active &a, ibdvm_status status, int converged)
     s->finished += 1;
 }
 
-// creates the context of a request in its workspace block and captures its graph
+// creates the context of a request in its workspace block on a stream of its
+// own (overlapping the replays in flight); standalone solves also capture
+// their graph
 ibdvm_status admit(ibdvm_server *s, Active &a)
 {
     hipError_t e = hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(s, e, "stream");
-    if ((e = hipEventCreateWithFlags(&a.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(s, e, "event");
     ibdvm_opts o = a.rq.opts;
     o.workspace = s->ws + a.off;
     o.workspace_bytes = a.rq.bytes;
@@ -191,58 +215,77 @@ ibdvm_status admit(ibdvm_server *s, Active &a)
         if ((st = ibdvm_set_tile(a.ctx, it->second[0], it->second[1], it->second[2]))) return st;
         if ((st = ibdvm_get_tile(a.ctx, a.tile))) return st;
     }
+    a.fused = a.updates_per_step < s->fuse_below;
+    if (a.fused) return IBDVM_OK;
+    if ((e = hipEventCreateWithFlags(&a.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(s, e, "event");
     return ibdvm_graph_create(a.ctx, s->K, &a.graph);
 }
 
-ibdvm_status launch(ibdvm_server *s, Active &a)
+// after a replay: C_D, convergence, retirement; false if the solve ended
+bool harvest(ibdvm_server *s, Active &a)
 {
-    ibdvm_status st = ibdvm_graph_launch(a.graph);
-    if (st) return st;
-    hipError_t e = hipEventRecord(a.done, a.stream);
-    if (e != hipSuccess) return hip_fail(s, e, "event record");
-    a.inflight = true;
-    return IBDVM_OK;
+    a.steps += s->K;
+    double F[3];
+    int32_t np = 0;
+    ibdvm_status st = ibdvm_surface_forces(a.ctx, F, &a.cd, &a.cl, nullptr, 0, &np);
+    if (st) {
+        retire(s, a, st, 0);
+        return false;
+    }
+    const bool conv = a.rq.tol > 0.0 && std::isfinite(a.cd_prev) && std::fabs(a.cd - a.cd_prev) < a.rq.tol;
+    a.cd_prev = a.cd;
+    if (conv || a.steps >= a.rq.max_steps) {
+        retire(s, a, IBDVM_OK, conv ? 1 : 0);
+        return false;
+    }
+    return true;
 }
 
-// one pass: harvest finished replays, check convergence, admit, relaunch
-ibdvm_status pass(ibdvm_server *s, bool wait_one)
+// one pass: harvest finished replays, check convergence, admit, relaunch.
+// wait: block on one replay in flight (the group's first) before harvesting
+ibdvm_status pass(ibdvm_server *s, bool wait)
 {
     bool waited = false;
-    for (size_t i = 0; i < s->active.size();) {
-        Active &a = s->active[i];
-        if (a.inflight) {
-            hipError_t q;
-            if (wait_one && !waited) {
-                q = hipEventSynchronize(a.done);
-                waited = true;
-            } else {
-                q = hipEventQuery(a.done);
-            }
-            if (q == hipErrorNotReady) {
-                (void)hipGetLastError();  // not an error: keep it out of the next launch check
-                ++i;
-                continue;
-            }
-            if (q != hipSuccess) return hip_fail(s, q, "replay");
-            a.inflight = false;
-            a.steps += s->K;
-            double F[3];
-            int32_t np = 0;
-            ibdvm_status st = ibdvm_surface_forces(a.ctx, F, &a.cd, &a.cl, nullptr, 0, &np);
-            if (st) {
-                retire(s, a, st, 0);
+    auto ready = [&](hipEvent_t ev, hipError_t &q) {
+        q = (wait && !waited) ? hipEventSynchronize(ev) : hipEventQuery(ev);
+        waited = waited || wait;
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();  // not an error: keep it out of the next launch check
+            return false;
+        }
+        return true;
+    };
+    hipError_t q;
+    if (s->inflight && ready(s->done, q)) {
+        if (q != hipSuccess) return hip_fail(s, q, "group replay");
+        s->inflight = false;
+        for (size_t i = 0; i < s->active.size();) {
+            Active &a = s->active[i];
+            if (a.joined && !harvest(s, a)) {
                 s->active.erase(s->active.begin() + (long)i);
                 continue;
             }
-            const bool conv = a.rq.tol > 0.0 && std::isfinite(a.cd_prev) && std::fabs(a.cd - a.cd_prev) < a.rq.tol;
-            a.cd_prev = a.cd;
-            if (conv || a.steps >= a.rq.max_steps) {
-                retire(s, a, IBDVM_OK, conv ? 1 : 0);
+            ++i;
+        }
+    }
+    for (size_t i = 0; i < s->active.size();) {
+        Active &a = s->active[i];
+        if (a.inflight && ready(a.done, q)) {
+            if (q != hipSuccess) return hip_fail(s, q, "replay");
+            a.inflight = false;
+            if (!harvest(s, a)) {
                 s->active.erase(s->active.begin() + (long)i);
                 continue;
             }
         }
         ++i;
+    }
+    // the group's stream and event are made at the first admission, so
+    // creating a server and queueing requests touch no device
+    if (!s->stream && !s->queue.empty()) {
+        hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(s, e, "server stream");
     }
     // admission in arrival order: the head waits until its block fits
     while (!s->queue.empty() && (int32_t)s->active.size() < s->max_active) {
@@ -262,11 +305,51 @@ ibdvm_status pass(ibdvm_server *s, bool wait_one)
         }
         s->active.push_back(a);
     }
+    // relaunch: standalone solves, then the group (new members join now)
     for (Active &a : s->active)
-        if (!a.inflight) {
-            ibdvm_status st = launch(s, a);
-            if (st) return st;
+        if (!a.fused && !a.inflight) {
+            ibdvm_status st = ibdvm_graph_launch(a.graph);
+            if (st) {
+                s->err = ibdvm_last_error();
+                return st;
+            }
+            hipError_t e = hipEventRecord(a.done, a.stream);
+            if (e != hipSuccess) return hip_fail(s, e, "event record");
+            a.inflight = true;
         }
+    if (s->inflight) return IBDVM_OK;
+    std::vector<ibdvm_ctx *> group;
+    for (Active &a : s->active) {
+        if (!a.fused) continue;
+        if (!a.joined) {
+            ibdvm_status st = ibdvm_set_stream(a.ctx, s->stream);
+            if (st) {
+                s->err = ibdvm_last_error();
+                return st;
+            }
+            (void)hipStreamDestroy(a.stream);
+            a.stream = nullptr;
+            a.joined = true;
+            drop_graph(s);
+        }
+        group.push_back(a.ctx);
+    }
+    if (group.empty()) return IBDVM_OK;
+    if (!s->graph) {
+        ibdvm_status st = ibdvm_batch_graph_create(group.data(), (int32_t)group.size(), s->K, &s->graph);
+        if (st) {
+            s->err = ibdvm_last_error();
+            return st;
+        }
+    }
+    ibdvm_status st = ibdvm_graph_launch(s->graph);
+    if (st) {
+        s->err = ibdvm_last_error();
+        return st;
+    }
+    hipError_t e = hipEventRecord(s->done, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "event record");
+    s->inflight = true;
     return IBDVM_OK;
 }
 
@@ -363,15 +446,26 @@ ibdvm_status ibdvm_server_info(const ibdvm_server *s, int64_t out[5])
 
 double ibdvm_server_clock(const ibdvm_server *s) { return s ? s->now() : 0.0; }
 
+ibdvm_status ibdvm_server_set_fusion(ibdvm_server *s, int64_t updates_per_step)
+{
+    if (!s || updates_per_step < 0) return IBDVM_E_INVALID_ARG;
+    s->fuse_below = updates_per_step;
+    return IBDVM_OK;
+}
+
 const char *ibdvm_server_error(const ibdvm_server *s) { return s ? s->err.c_str() : ""; }
 
 void ibdvm_server_destroy(ibdvm_server *s)
 {
     if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (Active &a : s->active) {
         if (a.stream) (void)hipStreamSynchronize(a.stream);
         release(s, a);
     }
+    drop_graph(s);
+    if (s->done) (void)hipEventDestroy(s->done);
+    if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
 

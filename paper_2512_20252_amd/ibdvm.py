@@ -64,9 +64,10 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_set_state", "ibdvm_get_state", "ibdvm_step", "ibdvm_moments", "ibdvm_surface_forces",
            "ibdvm_clock", "ibdvm_index_sets", "ibdvm_pair_geometry", "ibdvm_wall_state", "ibdvm_batch_step",
            "ibdvm_profile", "ibdvm_profile_read", "ibdvm_set_tile", "ibdvm_get_tile", "ibdvm_autotune",
-           "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_graph_launch",
+           "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_batch_graph_create", "ibdvm_graph_launch",
            "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
-           "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy"]
+           "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy", "ibdvm_set_stream",
+           "ibdvm_server_set_fusion"]
 _NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
                "ibdvm_server_error", "ibdvm_server_destroy")
 
@@ -105,6 +106,9 @@ def lib():
         L.ibdvm_last_error.restype = ctypes.c_char_p
         L.ibdvm_init_freestream_hashed.argtypes = [c_void_p, ctypes.c_uint64, c_double]
         L.ibdvm_graph_create.argtypes = [c_void_p, c_int32, P(c_void_p)]
+        L.ibdvm_batch_graph_create.argtypes = [P(c_void_p), c_int32, c_int32, P(c_void_p)]
+        L.ibdvm_set_stream.argtypes = [c_void_p, c_void_p]
+        L.ibdvm_server_set_fusion.argtypes = [c_void_p, ctypes.c_int64]
         L.ibdvm_graph_launch.argtypes = [c_void_p]
         L.ibdvm_graph_destroy.argtypes = [c_void_p]
         L.ibdvm_graph_destroy.restype = None
@@ -227,6 +231,11 @@ class Solver:
         u1 = np.ascontiguousarray(u[1], dtype=np.float64).reshape(-1) if (u is not None and self.NA == 2) else None
         check(lib().ibdvm_init_freestream(self._h, _dp(u0), _dp(u1), float(amp)))
 
+    def set_stream(self, stream):
+        """Rebind to another torch stream (after the queued work finished)."""
+        self.stream = stream
+        check(lib().ibdvm_set_stream(self._h, c_void_p(stream.cuda_stream if stream is not None else 0)))
+
     def init_freestream_hashed(self, seed, amp):
         check(lib().ibdvm_init_freestream_hashed(self._h, int(seed), float(amp)))
 
@@ -324,12 +333,17 @@ def batch_step(solvers, n):
 
 
 class Graph:
-    """nsteps captured steps of one solver, replayed on its stream."""
+    """nsteps captured steps of one solver, or of the fused steps of several
+    solvers sharing a stream (a list), replayed on their stream."""
 
     def __init__(self, solver, nsteps):
         self.solver = solver
         h = c_void_p(0)
-        check(lib().ibdvm_graph_create(solver.handle, int(nsteps), ctypes.byref(h)))
+        if isinstance(solver, (list, tuple)):
+            arr = (c_void_p * len(solver))(*[s.handle for s in solver])
+            check(lib().ibdvm_batch_graph_create(arr, len(solver), int(nsteps), ctypes.byref(h)))
+        else:
+            check(lib().ibdvm_graph_create(solver.handle, int(nsteps), ctypes.byref(h)))
         self._h = h
 
     def launch(self):
@@ -348,7 +362,7 @@ class Server:
     """Continuous batching of 2D solves in one device workspace (a torch
     uint8 tensor of ``nbytes``)."""
 
-    def __init__(self, nbytes, max_active=4, steps_per_replay=100):
+    def __init__(self, nbytes, max_active=4, steps_per_replay=100, fuse_below=None):
         import torch
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
         h = c_void_p(0)
@@ -358,6 +372,8 @@ class Server:
             raise IbdvmError(code, "server_create")
         self._h = h
         self._outs = {}
+        if fuse_below is not None:
+            self._check(lib().ibdvm_server_set_fusion(self._h, int(fuse_below)))
 
     def _check(self, code):
         if code != OK:

@@ -141,6 +141,8 @@ def test_server_argument_checks():
     assert L.ibdvm_server_submit(h, ctypes.byref(g3), ctypes.byref(v3), ctypes.byref(ge3), c3["Kn"], c3["Ma"], c3["Pr"],
                                  c3["gamma"], c3["alpha"], c3["Tw"], ctypes.byref(o3), 1, 1e-3, 1e-6, 100, None,
                                  ctypes.byref(rid)) == ibdvm.E_UNSUPPORTED
+    assert L.ibdvm_server_set_fusion(h, -1) == ibdvm.E_INVALID_ARG
+    assert L.ibdvm_server_set_fusion(h, 1 << 20) == ibdvm.OK
     info = (ctypes.c_int64 * 5)()
     assert L.ibdvm_server_info(h, info) == ibdvm.OK
     assert list(info)[:3] == [0, 0, 0] and info[4] == 1 << 20

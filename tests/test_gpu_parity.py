@@ -217,6 +217,46 @@ def test_batch_alone_vs_mix(torch_cuda):
             assert np.array_equal(a, b)
 
 
+def test_fused_batch_groups_and_graph(torch_cuda):
+    """Fused steps over a mixed batch on one stream: both storage forms,
+    several update tiles (separate tile groups and shared ones), partial
+    accommodation (the specular fill phase) and a 3D solve.  Eager fused
+    steps followed by replays of a captured fused graph give, for every
+    solve, the bits of that solve stepped alone."""
+    import torch
+    side = torch.cuda.Stream()
+    small = cases.cylinder_small()
+    rect = cases.case(dim=2, n=(20, 28), lo=(-1.0, -1.4), hi=(1.0, 1.4), vn=(10, 14), vlo=(-5.0, -5.0),
+                      vhi=(5.0, 5.0), geometry="circle", size=(0.35, 0.0, 0.0), Kn=0.05, Ma=1.2)
+    specs = [(small, "f64", (1, 8, 64)), (dict(small, alpha=0.7), "f32", (2, 4, 16)), (rect, "f64", (2, 4, 7)),
+             (dict(rect, alpha=0.6, Kn=0.2), "f64", (2, 4, 9)), (rect, "f32", (2, 8, 5)),
+             (cases.sphere(n=14, vn=6), "f64", None)]
+
+    def make(c, prec, tile, i):
+        s = ibdvm.Solver(c, precision=prec, stream=side)
+        if tile:
+            s.set_tile(*tile)
+        s.init_freestream(cases.noise(c, 10 + i), 1e-3)
+        return s
+
+    alone = []
+    for i, (c, prec, tile) in enumerate(specs):
+        s = make(c, prec, tile, i)
+        s.step(8)
+        alone.append((s.get_state(), s.surface_forces()[1]))
+        del s
+    mix = [make(c, prec, tile, i) for i, (c, prec, tile) in enumerate(specs)]
+    ibdvm.batch_step(mix, 4)
+    g = ibdvm.Graph(mix, 2)
+    g.launch()
+    g.launch()
+    for s, (ref, cd) in zip(mix, alone):
+        for a, b in zip(s.get_state(), ref):
+            assert np.array_equal(a, b)
+        assert s.surface_forces()[1] == cd
+    g.close()
+
+
 def test_nan_state_reported(torch_cuda):
     c = cases.cylinder_small()
     s = ibdvm.Solver(c)
@@ -442,15 +482,22 @@ SERVE_CASES = [cases.cylinder_small(),
                           aoa=0.3, Kn=0.1, Ma=0.8)]
 
 
+# fusion limits: every solve in the fused group, none, and the first case
+# (262k updates per step) standalone beside a fused group of the others
+FUSION = {"fused": 1 << 62, "standalone": 0, "mixed": 150000}
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_server_alone_vs_mix(torch_cuda, precision):
+@pytest.mark.parametrize("mode", sorted(FUSION))
+def test_server_alone_vs_mix(torch_cuda, precision, mode):
     """Serving form: solves of different sizes and physics admitted into one
-    workspace (two active slots, so the others queue and start as slots free
-    up) give bitwise the same moments as each solve stepped alone with the
-    tile the server chose."""
-    srv = ibdvm.Server(sum(ibdvm.footprint(c, precision) for c in SERVE_CASES) + (1 << 20), max_active=2,
-                       steps_per_replay=4)
+    workspace (two or three active slots, so the others queue and start as
+    slots free up), in the fused group, standalone or both, give bitwise the
+    same moments as each solve stepped alone with the tile the server
+    chose."""
+    srv = ibdvm.Server(sum(ibdvm.footprint(c, precision) for c in SERVE_CASES) + (1 << 20),
+                       max_active=3 if mode == "mixed" else 2, steps_per_replay=4, fuse_below=FUSION[mode])
     ids = [srv.submit(c, precision, seed=11 + i, amp=1e-3, tol=0.0, max_steps=12, keep_moments=True)
            for i, c in enumerate(SERVE_CASES)]
     done = {}
@@ -462,7 +509,7 @@ def test_server_alone_vs_mix(torch_cuda, precision):
     for i, (rid, c) in enumerate(zip(ids, SERVE_CASES)):
         r = done[rid]
         assert r["status"] == ibdvm.OK and r["steps"] == 12 and not r["converged"]
-        if i >= 2:  # admitted only after an earlier solve finished
+        if i >= (3 if mode == "mixed" else 2):  # admitted only after an earlier solve finished
             assert r["t_admit"] >= t_done[0]
         s = ibdvm.Solver(c, precision=precision)
         s.init_freestream_hashed(11 + i, 1e-3)
