@@ -109,13 +109,22 @@ typedef struct {
     void *stream;           /* hipStream_t */
 } ibdvm_opts;
 
-/* one wall point per ghost-donor pair: intersect point, unit normal (into the
- * gas), wall density rho_w and wall pressure p_w = sum w xi_n^2 f*_w */
+/* one wall point per ghost-donor pair: intersect point, unit normal n (into
+ * the gas), wall density rho_w (Section 3.2.3), and moments of the wall
+ * distribution f*_w (wall at rest, xi_n = xi . n): pressure p_w = sum w
+ * xi_n^2 f*_w, shear stress tau_w = sum w xi_n (xi - xi_n n) f*_w (the
+ * tangential part of the momentum flux), normal heat flux q_n = 1/2 sum w
+ * xi_n (|xi|^2 h + b) (2D; 3D: |xi|^2 f), and the pressure coefficient of
+ * Section 4, C_p = 2 (p_w - p_0) / (rho_0 U_0^2) with the freestream p_0 =
+ * rho_0 T_0 / 2 = 1/2 (NaN when U_0 = 0) */
 typedef struct {
     double xw[3];
     double nw[3];
     double rho_w;
     double p_w;
+    double tau_w[3];
+    double q_n;
+    double C_p;
 } ibdvm_wall_point;
 
 /* Bytes of device workspace a problem needs (state double buffer, per-cell
@@ -192,6 +201,15 @@ ibdvm_status ibdvm_pair_geometry(const ibdvm_ctx *ctx, double *g9, double *wg);
  * buffers to host: ghost values and ghost-side face values
  * [arrays][npairs][nodes] and rho_w[npairs].  Synchronises. */
 ibdvm_status ibdvm_wall_state(ibdvm_ctx *ctx, double *ghost, double *face, double *rho_w);
+
+/* Convergence residual of the last step (Section 4): for each conservative
+ * variable W_i = rho, rho U_x, rho U_y, rho U_z, rho E (rho E = rho |U|^2 / 2
+ * + 3 rho T / 4), res[i] = sqrt(sum_cells (W_i^{n+1} - W_i^n)^2) /
+ * sum_cells |W_i^{n+1}| over the fluid cells (0 for a component that is zero
+ * everywhere), and res[5] = max_i res[i].  Sums in a fixed order.
+ * IBDVM_E_STATE before the first step after the state was set.
+ * Synchronises. */
+ibdvm_status ibdvm_residual(ibdvm_ctx *ctx, double res[6]);
 
 /* Rebinds the context to another stream of the same device (NULL: the
  * legacy default stream) after the work queued on its current stream has

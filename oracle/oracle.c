@@ -1138,8 +1138,14 @@ void or_clock(void *h, double *out3)
 }
 
 /* body force from the momentum flux through the immersed-boundary faces
- * (reading R16) and drag/lift coefficients; wall records per pair:
- * x_w[3], n_w[3], rho_w, p_w */
+ * (reading R16) and drag/lift coefficients; wall records per pair (13
+ * doubles): x_w[3], n_w[3], rho_w, p_w, tau_w[3], q_n, C_p.  With the wall
+ * distribution f*_w (at rest) and n into the gas: p_w = sum w (xi.n)^2 f*_w,
+ * the shear tau_w = sum w (xi.n) (xi - (xi.n) n) f*_w (the tangential part of
+ * the momentum flux through the wall), the normal heat flux q_n = 1/2 sum w
+ * (xi.n) (|xi|^2 h + b) (2D reduced; 3D: |xi|^2 f), and the pressure
+ * coefficient of Section 4, C_p = 2 (p_w - p_0) / (rho_0 U_0^2) with the
+ * freestream p_0 = rho_0 T_0 / 2 = 1/2 and U_0 the freestream speed */
 void or_forces(void *h, double *F3, double *cdcl, double *wall)
 {
     or_state *s = (or_state *)h;
@@ -1161,19 +1167,30 @@ void or_forces(void *h, double *F3, double *cdcl, double *wall)
         }
         for (int b = 0; b < D; ++b) F[b] += dS * Fp[b];
         if (wall) {
-            double pw = 0.0;
+            double pw = 0.0, tau[3] = {0, 0, 0}, qn = 0.0;
             for (int k = 0; k < NV; ++k) {
-                double dn = 0.0;
-                for (int b = 0; b < D; ++b) dn += s->xi[3 * k + b] * p->nw[b];
-                pw += s->w[k] * dn * dn * s->fw[0][(size_t)ip * NV + k];
+                const double *x = &s->xi[3 * k];
+                double dn = 0.0, x2 = 0.0;
+                for (int b = 0; b < D; ++b) {
+                    dn += x[b] * p->nw[b];
+                    x2 += x[b] * x[b];
+                }
+                const double fw = s->fw[0][(size_t)ip * NV + k];
+                pw += s->w[k] * dn * dn * fw;
+                for (int b = 0; b < D; ++b) tau[b] += s->w[k] * dn * (x[b] - dn * p->nw[b]) * fw;
+                const double e = x2 * fw + (s->NA == 2 ? s->fw[1][(size_t)ip * NV + k] : 0.0);
+                qn += 0.5 * s->w[k] * dn * e;
             }
-            double *wr = &wall[8 * ip];
+            double *wr = &wall[13 * ip];
             for (int b = 0; b < 3; ++b) {
                 wr[b] = p->xw[b];
                 wr[3 + b] = p->nw[b];
+                wr[8 + b] = tau[b];
             }
             wr[6] = s->rhow[ip];
             wr[7] = pw;
+            wr[11] = qn;
+            wr[12] = s->Uinf > 0 ? 2.0 * (pw - 0.5) / (s->Uinf * s->Uinf) : NAN;
         }
     }
     for (int b = 0; b < 3; ++b) F3[b] = F[b];

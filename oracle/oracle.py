@@ -192,7 +192,7 @@ class Oracle:
     def forces(self):
         F = np.empty(3)
         cdcl = np.empty(2)
-        wall = np.empty((max(self.npairs, 1), 8))
+        wall = np.empty((max(self.npairs, 1), 13))
         lib().or_forces(self._h, _dp(F), _dp(cdcl), _dp(wall))
         return F, cdcl[0], cdcl[1], wall[: self.npairs]
 
@@ -277,3 +277,22 @@ class Oracle:
         w1 = np.empty(self.NV) if self.NA == 2 else None
         rw = lib().or_wall_distribution(self._h, _dp(n3), _dp(f0), _dp(f1), _dp(w0), _dp(w1))
         return rw, ((w0, w1) if self.NA == 2 else (w0,))
+
+
+def residual(m_prev, m_next):
+    """Convergence residual of Section 4 between the moment fields of two
+    consecutive steps (rows rho, U[3], T, q[3]; NaN rows for solid cells):
+    for each conservative variable W_i = rho, rho U_x, rho U_y, rho U_z,
+    rho E with rho E = rho |U|^2 / 2 + 3 rho T / 4 (p = rho T / 2),
+    res_i = sqrt(sum_j (W_i^{n+1} - W_i^n)^2) / sum_j |W_i^{n+1}| over the
+    fluid cells j (0 where the variable vanishes everywhere); returns the
+    five values and their maximum."""
+    def cons(m):
+        rho, U, T = m[:, 0], m[:, 1:4], m[:, 4]
+        return np.column_stack([rho, rho[:, None] * U, rho * (0.5 * (U * U).sum(axis=1) + 0.75 * T)])
+    ok = np.isfinite(m_next[:, 0])
+    a, b = cons(m_prev[ok]), cons(m_next[ok])
+    num = np.sqrt(((b - a) ** 2).sum(axis=0))
+    den = np.abs(b).sum(axis=0)
+    res = np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+    return res, float(res.max())

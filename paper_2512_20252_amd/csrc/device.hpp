@@ -25,6 +25,13 @@ enum CellWord { CW_U = 0, CW_A = 3, CW_INVT = 4, CW_S = 5, CW_TH = 8, CW_INVTAU 
 // 1/T, s[3], 1/tau, then the flag word of the cell above in z (word 9).
 constexpr int kQWords = 10;
 
+// convergence residual: conservative variables rho, rho U[3], rho E; per
+// moment-finish workgroup the sums of squared changes, then of magnitudes
+constexpr int kResVars = 5;
+// per pair: momentum flux through the face F[3], then at the wall point p_w,
+// tau_w[3], q_n
+constexpr int kForceWords = 8;
+
 constexpr int kChunk = 64;       // velocity nodes per wavefront
 constexpr int kFillChunk = 256;  // velocity nodes per ghost-fill workgroup
 constexpr int kMaxVn = 128;
@@ -77,6 +84,7 @@ struct Dev {
     double *rhow;
     double *fillpart;  // [pair][fill chunk][2]: incident and specular partial wall fluxes
     double *pforce;
+    double *respart;  // [moment-finish workgroup][2 kResVars]
     Ctrl *ctrl;
 };
 

@@ -31,6 +31,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
     size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, fwall, rhow, fillpart, pforce, ctrl;
+    size_t respart;  // moment-finish workgroups x 2 kResVars
     size_t devcopy;  // the context's Dev, read by launches over several solves
     size_t total;
     size_t state_bytes;  // one array of one buffer
@@ -75,7 +76,8 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.fwall = take((size_t)NA * np * g.NV * 8);
     L.rhow = take(np * 8);
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
-    L.pforce = take(np * 4 * 8);
+    L.pforce = take(np * ibdvm::kForceWords * 8);
+    L.respart = take((size_t)((g.Nc + 3) / 4) * 2 * ibdvm::kResVars * 8);
     L.ctrl = take(sizeof(ibdvm::Ctrl));
     L.devcopy = take(sizeof(ibdvm::Dev));
     L.total = off;
@@ -152,6 +154,7 @@ struct ibdvm_ctx {
     int cur = 0;
     long long step = 0;
     bool pending = false;
+    bool res_valid = false;  // a step has run since the state was set: residual partials hold its change
     double Uinf = 0, mu0 = 0, Lref = 1;
     ibdvm::Tile tile{1, 8, 64};
     bool profiling = false;
@@ -190,6 +193,7 @@ ibdvm_status refresh_moments(ibdvm_ctx *c)
 {
     HIP_CHECK(ibdvm::launch_moments_direct(c->dev, c->precision, c->cur, (int)(c->step & 1), c->stream));
     c->pending = false;
+    c->res_valid = false;
     return IBDVM_OK;
 }
 
@@ -265,6 +269,7 @@ ibdvm_status one_step(ibdvm_ctx *c)
     c->cur ^= 1;
     c->step += 1;
     c->pending = true;
+    c->res_valid = true;
     return IBDVM_OK;
 }
 
@@ -357,6 +362,7 @@ ibdvm_status fused_step(ibdvm_ctx *const *cs, int n, hipStream_t stream)
         c->cur ^= 1;
         c->step += 1;
         c->pending = true;
+        c->res_valid = true;
     }
     return IBDVM_OK;
 }
@@ -612,6 +618,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.rhow = (double *)(ws + L.rhow);
     d.fillpart = (double *)(ws + L.fillpart);
     d.pforce = (double *)(ws + L.pforce);
+    d.respart = (double *)(ws + L.respart);
     d.ctrl = (ibdvm::Ctrl *)(ws + L.ctrl);
 
     auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
@@ -860,7 +867,10 @@ ibdvm_status ibdvm_graph_launch(ibdvm_graph *g)
     ibdvm_status st = g->fused ? fused_fill(g->ctxs.data(), n, false, g->ctxs[0]->stream) : finish_pending(g->ctxs[0]);
     if (st) return st;
     HIP_CHECK(hipGraphLaunch(g->exec, g->ctxs[0]->stream));
-    for (ibdvm_ctx *c : g->ctxs) c->step += g->nsteps;
+    for (ibdvm_ctx *c : g->ctxs) {
+        c->step += g->nsteps;
+        c->res_valid = true;
+    }
     return IBDVM_OK;
 }
 
@@ -870,6 +880,35 @@ void ibdvm_graph_destroy(ibdvm_graph *g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+ibdvm_status ibdvm_residual(ibdvm_ctx *c, double res[6])
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!res) return fail(IBDVM_E_INVALID_ARG, "null output");
+    if (!c->res_valid) return fail(IBDVM_E_STATE, "no step since the state was set");
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    constexpr int R = ibdvm::kResVars;
+    const size_t nb = (size_t)((c->geo.Nc + 3) / 4);
+    std::vector<double> part(nb * 2 * R);
+    HIP_CHECK(hipMemcpyAsync(part.data(), c->dev.respart, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    if ((st = sync_and_check(c))) return st;
+    double num[R] = {0, 0, 0, 0, 0}, den[R] = {0, 0, 0, 0, 0};
+    for (size_t b = 0; b < nb; ++b)
+        for (int i = 0; i < R; ++i) {
+            num[i] += part[b * 2 * R + i];
+            den[i] += part[b * 2 * R + R + i];
+        }
+    double mx = 0.0;
+    for (int i = 0; i < R; ++i) {
+        // a momentum component that vanishes everywhere (U_z in 2D) has no residual
+        res[i] = den[i] > 0.0 ? std::sqrt(num[i]) / den[i] : 0.0;
+        mx = std::max(mx, res[i]);
+    }
+    res[R] = mx;
+    return IBDVM_OK;
 }
 
 ibdvm_status ibdvm_set_stream(ibdvm_ctx *c, void *stream)
@@ -954,15 +993,16 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
     const size_t np = c->geo.pairs.size();
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), true, false, c->stream));
     HIP_CHECK(ibdvm::launch_force(c->dev, c->precision, c->cur, c->stream));
-    std::vector<double> pf(np * 4), rw(np);
+    constexpr int KW = ibdvm::kForceWords;
+    std::vector<double> pf(np * KW), rw(np);
     if (np) {
-        HIP_CHECK(hipMemcpyAsync(pf.data(), c->dev.pforce, np * 4 * 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_CHECK(hipMemcpyAsync(pf.data(), c->dev.pforce, np * KW * 8, hipMemcpyDeviceToHost, c->stream));
         HIP_CHECK(hipMemcpyAsync(rw.data(), c->dev.rhow, np * 8, hipMemcpyDeviceToHost, c->stream));
     }
     if ((st = sync_and_check(c))) return st;
     double F[3] = {0, 0, 0};
     for (size_t p = 0; p < np; ++p)
-        for (int b = 0; b < 3; ++b) F[b] += pf[4 * p + b];
+        for (int b = 0; b < 3; ++b) F[b] += pf[KW * p + b];
     if (force)
         for (int b = 0; b < 3; ++b) force[b] = F[b];
     double qd = 0.5 * c->Uinf * c->Uinf * c->Lref;
@@ -977,7 +1017,11 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
                 pts[m].nw[b] = g.nw[b];
             }
             pts[m].rho_w = rw[p];
-            pts[m].p_w = pf[4 * p + 3];
+            pts[m].p_w = pf[KW * p + 3];
+            for (int b = 0; b < 3; ++b) pts[m].tau_w[b] = pf[KW * p + 4 + b];
+            pts[m].q_n = pf[KW * p + 7];
+            // Section 4: C_p = 2 (p_w - p_0) / (rho_0 U_0^2), freestream p_0 = rho_0 T_0 / 2 = 1/2
+            pts[m].C_p = c->Uinf > 0 ? 2.0 * (pts[m].p_w - 0.5) / (c->Uinf * c->Uinf) : NAN;
         }
     if (n_pts) *n_pts = pts ? m : (int32_t)np;
     return IBDVM_OK;

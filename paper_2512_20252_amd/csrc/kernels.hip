@@ -353,6 +353,14 @@ __device__ void fin_cells(const DR &d, int slot, int blk)
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     double tmin = INFINITY;
+    // convergence residual of Section 4, per conservative variable W = (rho,
+    // rho U[3], rho E) with rho E = rho |U|^2 / 2 + 3 rho T / 4: the block's
+    // sums of (W^{n+1} - W^n)^2 and of |W^{n+1}| (W^n: the parameters about
+    // to be replaced)
+    __shared__ double rsum[4][2 * kResVars];
+    double rv[2 * kResVars];
+#pragma unroll
+    for (int i = 0; i < 2 * kResVars; ++i) rv[i] = 0.0;
     // one cell per wavefront: the cell's partial records are contiguous, lane
     // l sums word l % 16 of records l / 16, l / 16 + 4, ... in coalesced loads
     const int c = blk * 4 + wv;
@@ -374,6 +382,7 @@ __device__ void fin_cells(const DR &d, int slot, int blk)
         for (int j = 0; j < PW; ++j) S[j] = __shfl(acc, j, 64);
         const double *cp = d.cellp + (size_t)c * kCellWords;
         double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
+        const double rho_old = cp[CW_RHO], T_old = cp[CW_T];
         double m0 = S[0], m1[3] = {0, 0, 0}, m3[3] = {0, 0, 0}, M[3][3] = {};
         for (int a = 0; a < D; ++a) {
             m1[a] = S[1 + a];
@@ -400,10 +409,27 @@ __device__ void fin_cells(const DR &d, int slot, int blk)
             for (int b = 0; b < D; ++b) Md += M[a][b] * del[b];
             q[a] = 0.5 * (m3[a] - 2.0 * Md - del[a] * m2 + 2.0 * dd * m1[a]);
         }
+        const double Wo[kResVars] = {rho_old, rho_old * Uref[0], rho_old * Uref[1], rho_old * Uref[2],
+                                     rho_old * (0.5 * (Uref[0] * Uref[0] + Uref[1] * Uref[1] + Uref[2] * Uref[2]) +
+                                                0.75 * T_old)};
+        const double Wn[kResVars] = {m0, m0 * U[0], m0 * U[1], m0 * U[2],
+                                     m0 * (0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + 0.75 * T)};
+#pragma unroll
+        for (int i = 0; i < kResVars; ++i) {
+            rv[i] = (Wn[i] - Wo[i]) * (Wn[i] - Wo[i]);
+            rv[kResVars + i] = fabs(Wn[i]);
+        }
         double tau = INFINITY;
         if (lane == 0) tau = write_cell(d, c, m0, U, T, q, D);
         tmin = fmin(tmin, tau);
     }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 2 * kResVars; ++i) rsum[wv][i] = rv[i];
+    __syncthreads();
+    if (threadIdx.x < 2 * kResVars)
+        d.respart[(size_t)blk * 2 * kResVars + threadIdx.x] =
+            (rsum[0][threadIdx.x] + rsum[1][threadIdx.x]) + (rsum[2][threadIdx.x] + rsum[3][threadIdx.x]);
     tau_min_commit(d, slot, tmin);
 }
 
@@ -1594,7 +1620,8 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
     ijk[0] = dc % d.n[0];
     ijk[1] = (dc / d.n[0]) % d.n[1];
     ijk[2] = D == 3 ? dc / (d.n[0] * d.n[1]) : 0;
-    double acc[4] = {0, 0, 0, 0};
+    // F[3] (momentum flux through the face), p_w, tau_w[3], q_n
+    double acc[kForceWords] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = threadIdx.x; k < NV; k += 256) {
         double xa = d.xi[a][k], st;
         if (side * xa > 0.0) {
@@ -1606,16 +1633,22 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
         } else {
             st = d.face[0][(size_t)p * NV + k];
         }
-        double xn = side * xa, dn = 0.0;
+        double xn = side * xa, dn = 0.0, x2 = 0.0;
         for (int b = 0; b < D; ++b) {
             acc[b] += d.w[k] * d.xi[b][k] * xn * st;
             dn += d.xi[b][k] * P.nw[b];
+            x2 += d.xi[b][k] * d.xi[b][k];
         }
-        acc[3] += d.w[k] * dn * dn * d.fwall[0][(size_t)p * NV + k];
+        // wall distribution: pressure, tangential stress and normal heat flux
+        const double fw = d.fwall[0][(size_t)p * NV + k];
+        const double wdf = d.w[k] * dn * fw;
+        acc[3] += wdf * dn;
+        for (int b = 0; b < D; ++b) acc[4 + b] += wdf * (d.xi[b][k] - dn * P.nw[b]);
+        acc[7] += 0.5 * d.w[k] * dn * (x2 * fw + (d.NA == 2 ? d.fwall[1][(size_t)p * NV + k] : 0.0));
     }
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < kForceWords; ++b) {
         double s = block_sum(acc[b]);
-        if (threadIdx.x == 0) d.pforce[4 * p + b] = b < 3 ? P.dS * s : s;
+        if (threadIdx.x == 0) d.pforce[kForceWords * p + b] = b < 3 ? P.dS * s : s;
     }
 }
 

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
 
 
 class WallPoint(ctypes.Structure):
-    _fields_ = [("xw", c_double * 3), ("nw", c_double * 3), ("rho_w", c_double), ("p_w", c_double)]
+    _fields_ = [("xw", c_double * 3), ("nw", c_double * 3), ("rho_w", c_double), ("p_w", c_double),
+                ("tau_w", c_double * 3), ("q_n", c_double), ("C_p", c_double)]
 
 
 class Result(ctypes.Structure):
@@ -67,7 +68,7 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_batch_graph_create", "ibdvm_graph_launch",
            "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
            "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy", "ibdvm_set_stream",
-           "ibdvm_server_set_fusion"]
+           "ibdvm_server_set_fusion", "ibdvm_residual"]
 _NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
                "ibdvm_server_error", "ibdvm_server_destroy")
 
@@ -108,6 +109,7 @@ def lib():
         L.ibdvm_graph_create.argtypes = [c_void_p, c_int32, P(c_void_p)]
         L.ibdvm_batch_graph_create.argtypes = [P(c_void_p), c_int32, c_int32, P(c_void_p)]
         L.ibdvm_set_stream.argtypes = [c_void_p, c_void_p]
+        L.ibdvm_residual.argtypes = [c_void_p, P(c_double)]
         L.ibdvm_server_set_fusion.argtypes = [c_void_p, ctypes.c_int64]
         L.ibdvm_graph_launch.argtypes = [c_void_p]
         L.ibdvm_graph_destroy.argtypes = [c_void_p]
@@ -276,8 +278,16 @@ class Solver:
         n = c_int32(0)
         check(lib().ibdvm_surface_forces(self._h, _dp(F), ctypes.byref(cd), ctypes.byref(cl), pts, cap,
                                          ctypes.byref(n)))
-        wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] for p in pts[: n.value]]).reshape(-1, 8)
+        wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] + list(p.tau_w) + [p.q_n, p.C_p]
+                         for p in pts[: n.value]]).reshape(-1, 13)
         return F, cd.value, cl.value, wall
+
+    def residual(self):
+        """Convergence residual of the last step: per variable (rho, rho U[3],
+        rho E) and the maximum."""
+        r = np.empty(6)
+        check(lib().ibdvm_residual(self._h, _dp(r)))
+        return r[:5], float(r[5])
 
     def wall_state(self):
         n = max(self.npairs, 1) * self.NV

@@ -401,6 +401,39 @@ def test_rest_state_stationary(oracle_mod):
         assert np.max(np.abs(a[~solid] - b[~solid])) <= 1e-12 * np.max(a)
 
 
+def test_rest_state_wall_diagnostics(oracle_mod):
+    """At rest around a diffuse wall at T_w the wall distribution is the rest
+    Maxwellian: no shear and no normal heat flux at any wall point, and the
+    wall pressure is the gas pressure rho T / 2 = 1/2 whatever the normal
+    (to the quadrature accuracy of the 48^2 grid); C_p is undefined
+    (no freestream speed)."""
+    c = cases.case(dim=2, n=(24, 24), lo=(-1.0, -1.0), hi=(1.0, 1.0), vn=(48, 48), vlo=(-6.0, -6.0),
+                   vhi=(6.0, 6.0), geometry="circle", size=(0.3, 0.0, 0.0), Kn=0.1, Ma=0.0)
+    o = oracle_mod.Oracle(c)
+    o.init_freestream()
+    o.step(3)
+    _, _, _, wall = o.forces()
+    assert len(wall) > 8
+    assert np.max(np.abs(wall[:, 8:11])) < 1e-13
+    assert np.max(np.abs(wall[:, 11])) < 1e-13
+    assert np.max(np.abs(wall[:, 7] - 0.5)) < 1e-10
+    assert np.all(np.isnan(wall[:, 12]))
+
+
+def test_residual_hand_example(oracle_mod):
+    """Section 4 residual on two cells worked by hand: W = (rho, rho U,
+    rho E) goes from (1, 0, 0.75) and (2, 0, 3) to (1.1, 0.22, 0.847) and
+    (2, 0, 3.3); res_rho = 0.1 / 3.1, res_rhoUx = 0.22 / 0.22 = 1,
+    res_rhoUy = res_rhoUz = 0, res_rhoE = sqrt(0.097^2 + 0.3^2) / 4.147."""
+    nan = np.full(8, np.nan)
+    prev = np.array([[1.0, 0, 0, 0, 1.0, 0, 0, 0], [2.0, 0, 0, 0, 2.0, 0, 0, 0], nan])
+    nxt = np.array([[1.1, 0.2, 0, 0, 1.0, 0, 0, 0], [2.0, 0, 0, 0, 2.2, 0, 0, 0], nan])
+    res, mx = oracle_mod.residual(prev, nxt)
+    assert np.allclose(res, [0.03225806451612903, 1.0, 0.0, 0.0, 0.07602891927150053], rtol=1e-14, atol=0)
+    assert mx == 1.0
+    assert oracle_mod.residual(nxt, nxt)[1] == 0.0
+
+
 # ---------------------------------------------------------------- P9 closed box conservation
 def test_periodic_box_conservation(oracle_mod):
     """The finite-volume step is conservative (fluxes telescope, Section 2.2)
