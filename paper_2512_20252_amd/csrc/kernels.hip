@@ -1248,7 +1248,12 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
     const int nb = gridDim.x;
     const int L = (blockIdx.x & 7) * (nb >> 3) + (blockIdx.x >> 3);
     if (L >= ntx * nty * nzs * ncv) return;
-    const int tX = L % ntx, tY = (L / ntx) % nty, zs = (L / (ntx * nty)) % nzs, ch = L / (ntx * nty * nzs);
+    // tiles go out in stripes of 4 tile rows, x slowest within a stripe: the
+    // 32 workgroups an XCD runs at once cover an 8 x 4 block of tiles whose
+    // shared halo cells they load from its L2 at about the same plane
+    const int Lt = L % (ntx * nty), zs = (L / (ntx * nty)) % nzs, ch = L / (ntx * nty * nzs);
+    const int stripe = Lt / (4 * ntx), rows = min(4, nty - 4 * stripe), q = Lt - stripe * 4 * ntx;
+    const int tX = q / rows, tY = 4 * stripe + q % rows;
     const int nx = d.n[0], ny = d.n[1], nz = d.n[2], NV = d.NV;
     const int i0 = tX * kT3, j0 = tY * TY, k0 = zs * LZ, k1 = min(k0 + LZ, nz);
     const int lane = threadIdx.x & 63;
