@@ -37,7 +37,8 @@ def _traffic(workload, precision, tile):
     """HBM bytes per update launch from committed rocprofv3 counter runs
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None
     when they are missing or were taken on another kernel source or tile."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+    tag = "-".join(str(int(x)) for x in tile)
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}_tile{tag}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))

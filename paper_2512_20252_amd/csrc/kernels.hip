@@ -742,6 +742,19 @@ __device__ __forceinline__ float vl_half(float d1, float d2)
     return p > 0.0f ? p * __builtin_amdgcn_rcpf(den) : 0.0f;
 }
 
+// outgoing state f + sign(xi) h toward the downwind face: the sign bit of
+// the node velocity is XORed into h instead of multiplying by a stored +-1
+__device__ __forceinline__ double ostate(double h, double f, double xi)
+{
+    const unsigned long long s = __builtin_bit_cast(unsigned long long, xi) & 0x8000000000000000ull;
+    return f + __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, h) ^ s);
+}
+__device__ __forceinline__ float ostate(float h, float f, double xi)
+{
+    const unsigned s = (unsigned)(__builtin_bit_cast(unsigned long long, xi) >> 32) & 0x80000000u;
+    return f + __builtin_bit_cast(float, __builtin_bit_cast(unsigned, h) ^ s);
+}
+
 // exp(x) for x <= 0: x = (32 m + j) ln2/32 + r with |r| <= ln2/64, so
 // exp(x) = 2^m 2^(j/32) exp(r); 2^(j/32) comes from a 32-entry table and
 // exp(r) from its degree-6 Taylor polynomial (truncation below 4e-18
@@ -846,6 +859,11 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     };
     int koff[V];
     double xx[V], xy[V], wk[V];
+    // FP64 keeps fewer per-lane values, so its V = 2 form runs three
+    // wavefronts per SIMD: the sign of the node velocity is XORed into the
+    // half slope (ostate), |xi|/dx is formed where used, and the cell record
+    // lives in scalar registers; FP32 keeps them in vector registers
+    constexpr bool LEAN = sizeof(T) == 8;
     T axp[V], ayq[V], sx[V], sy[V];
     bool pos[V], py[V];
     const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1];
@@ -859,25 +877,47 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         wk[v] = k < NV ? d.w[kc] : 0.0;
         pos[v] = xx[v] > 0.0;
         py[v] = xy[v] > 0.0;
-        axp[v] = (T)fabs(xx[v]) * idx;
-        ayq[v] = (T)xy[v] * idy;
-        sx[v] = pos[v] ? T(1) : T(-1);
-        sy[v] = py[v] ? T(1) : T(-1);
+        if constexpr (!LEAN) {
+            axp[v] = (T)fabs(xx[v]) * idx;
+            ayq[v] = (T)xy[v] * idy;
+            sx[v] = pos[v] ? T(1) : T(-1);
+            sy[v] = py[v] ? T(1) : T(-1);
+        }
     }
+    // outgoing states toward the downwind x / y face
+    auto ostx = [&](T h, T f, int v) -> T {
+        if constexpr (LEAN)
+            return ostate(h, f, xx[v]);
+        else
+            return fma(sx[v], h, f);
+    };
+    auto osty = [&](T h, T f, int v) -> T {
+        if constexpr (LEAN)
+            return ostate(h, f, xy[v]);
+        else
+            return fma(sy[v], h, f);
+    };
 
     // cell record of (i, jr): parameters of the update and the flag word of
     // the cell above
     auto ldrec = [&](int jr, double (&P)[8], int &fup) {
         const bool in = col_in && jr < ny;
         const size_t cc = in ? (size_t)(i + nx * jr) : 0;
-        const brsrc r = mk_rsrc(d.cellq + cc * kQWords, in ? 8 * kQWords : 0);
+        if constexpr (LEAN) {
+            const cdbl_p q = (cdbl_p)(d.cellq + cc * kQWords);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, 16 * m, 0, 0);
-            P[2 * m] = __builtin_bit_cast(double, u32x2{u.x, u.y});
-            P[2 * m + 1] = __builtin_bit_cast(double, u32x2{u.z, u.w});
+            for (int m = 0; m < 8; ++m) P[m] = q[m];
+            fup = in ? ((cint_p)q)[16] : 0;
+        } else {
+            const brsrc r = mk_rsrc(d.cellq + cc * kQWords, in ? 8 * kQWords : 0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const u32x4 u = __builtin_amdgcn_raw_buffer_load_b128(r, 16 * m, 0, 0);
+                P[2 * m] = __builtin_bit_cast(double, u32x2{u.x, u.y});
+                P[2 * m + 1] = __builtin_bit_cast(double, u32x2{u.z, u.w});
+            }
+            fup = (int)__builtin_amdgcn_raw_buffer_load_b32(r, 64, 0, 0);
         }
-        fup = (int)__builtin_amdgcn_raw_buffer_load_b32(r, 64, 0, 0);
     };
 
     bool cfs;
@@ -943,13 +983,13 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                 if (flm1 & CF_YM) fm = ghost_at<T>(d, A, c0 - nx, 2, koff[v] * (8 / ST));
                 if (flm1 & CF_YP) fp = ghost_at<T>(d, A, c0 - nx, 3, koff[v] * (8 / ST));
                 const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[A][v] - fm, fp - fm1[A][v]);
-                const T oym = fma(sy[v], hm, fm1[A][v]);
+                const T oym = osty(hm, fm1[A][v], v);
                 fm = fm1[A][v];
                 fp = R[1][A][v];
                 if (FL0 & CF_YM) fm = ghost_at<T>(d, A, c0, 2, koff[v] * (8 / ST));
                 if (FL0 & CF_YP) fp = ghost_at<T>(d, A, c0, 3, koff[v] * (8 / ST));
                 const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][A][v] - fm, fp - R[0][A][v]);
-                OY[0][A][v] = fma(sy[v], h0, R[0][A][v]);
+                OY[0][A][v] = osty(h0, R[0][A][v], v);
                 T F;
                 if (py[v])
                     F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0, 2, koff[v] * (8 / ST)));
@@ -1013,7 +1053,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     if (NEAR && (fl & CF_XP)) fp = ghost_at<T>(d, A, cc, 1, koff[v] * (8 / ST));
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (fl & CF_SOLID)) h = T(0);
-                    const T o = fma(sx[v], h, fc);
+                    const T o = ostx(h, fc, v);
                     if (keep) out[A][v] = o;
                     ob[A][p0][v * 64 + lane] = o;
                 }
@@ -1045,7 +1085,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     if (NEAR && (flh & CF_XP)) fp = ghost_at<T>(d, hA, ch_, 1, koff[v] * (8 / ST));
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (flh & CF_SOLID)) h = T(0);
-                    ob[hA][spos][v * 64 + lane] = fma(sx[v], h, fc);
+                    ob[hA][spos][v * 64 + lane] = ostx(h, fc, v);
                 }
                 if (NEAR) __builtin_amdgcn_s_waitcnt(0);
             };
@@ -1079,7 +1119,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T>(d, A, c + nx, 3, koff[v] * (8 / ST));
                     T h1 = vl_half(f1[A][v] - fm, fp - f1[A][v]);
                     if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
-                    oy1[A][v] = fma(sy[v], h1, f1[A][v]);
+                    oy1[A][v] = osty(h1, f1[A][v], v);
                     T F = py[v] ? oy0[A][v] : oy1[A][v];
                     if (NEAR) {
                         if (py[v]) {
@@ -1093,7 +1133,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     T nbs = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
                     if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T>(d, A, c, 0, koff[v] * (8 / ST));
                     if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T>(d, A, c, 1, koff[v] * (8 / ST));
-                    div[A] = fma(axp[v], ox[A][v] - nbs, ayq[v] * (F - Fdn[A][v]));
+                    const T ax = LEAN ? (T)fabs(xx[v]) * idx : axp[v], ay = LEAN ? (T)xy[v] * idy : ayq[v];
+                    div[A] = fma(ax, ox[A][v] - nbs, ay * (F - Fdn[A][v]));
                 }
                 if (NEAR && !upd) {
                     // solid cells are not advanced; carry their value
@@ -1156,7 +1197,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
 
 
 template <typename T, int V, int TX>
-__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
+__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 3)))
 void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 {
     const long long L = xcd_run(gridDim.x);
@@ -1168,7 +1209,7 @@ void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 // parameter blocks live in their workspaces, the per-solve launch values in
 // the argument block
 template <typename T, int V, int TX>
-__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : (sizeof(T) == 4 ? 3 : 2))))
+__global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 3)))
 void k_update2d_batch(BatchArgs a)
 {
     const long long L = xcd_run(gridDim.x);
@@ -1192,19 +1233,6 @@ void k_update2d_batch(BatchArgs a)
 // flags follow from those of the adjacent tile cell), and the faces take the
 // upwind neighbour's state from LDS.  Immersed-boundary substitutions are
 // those of the 2D update with the z pair directions 4 and 5 added.
-// outgoing state f + sign(xi) h toward the downwind face: the sign bit of
-// the node velocity is XORed into h instead of multiplying by a stored +-1
-__device__ __forceinline__ double ostate(double h, double f, double xi)
-{
-    const unsigned long long s = __builtin_bit_cast(unsigned long long, xi) & 0x8000000000000000ull;
-    return f + __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, h) ^ s);
-}
-__device__ __forceinline__ float ostate(float h, float f, double xi)
-{
-    const unsigned s = (unsigned)(__builtin_bit_cast(unsigned long long, xi) >> 32) & 0x80000000u;
-    return f + __builtin_bit_cast(float, __builtin_bit_cast(unsigned, h) ^ s);
-}
-
 constexpr int kT3 = 4;  // tile edge along x
 
 // staged plane of a 4 x TY tile: slot of tile position (x, y), x in [-2, 6),
