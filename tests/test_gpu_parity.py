@@ -134,6 +134,60 @@ def test_ablation_flags_agree_with_oracle(oracle_mod, torch_cuda, flag):
     assert not np.array_equal(r.moments(), s.moments(), equal_nan=True)  # the flag changes the result
 
 
+EDGE = {
+    # fewer velocity nodes than one 64-lane chunk, in every tile shape below
+    "2d_35_nodes": (cases.case(dim=2, n=(20, 18), lo=(-1.0, -0.9), hi=(1.0, 0.9), vn=(7, 5), vlo=(-3.0, -3.0),
+                               vhi=(3.0, 3.0), geometry="circle", size=(0.3, 0.0, 0.0), Kn=0.1, Ma=0.6),
+                    [(1, 4, 3), (2, 8, 64)]),
+    "3d_48_nodes": (cases.case(dim=3, n=(14, 13, 12), lo=(-1.4, -1.3, -1.2), hi=(1.4, 1.3, 1.2), vn=(4, 4, 3),
+                               vlo=(-3.0, -3.0, -3.0), vhi=(3.0, 3.0, 3.0), geometry="sphere",
+                               size=(0.4, 0.0, 0.0), Kn=0.1, Ma=0.6),
+                    [(1, 16, 256), (2, 8, 5)]),
+    # the largest velocity grid per axis the library takes (128 nodes)
+    "2d_128_axis": (cases.case(dim=2, n=(16, 14), lo=(-0.8, -0.7), hi=(0.8, 0.7), vn=(128, 6), vlo=(-6.0, -5.0),
+                               vhi=(6.0, 5.0), geometry="circle", size=(0.22, 0.0, 0.0), Kn=0.2, Ma=0.8),
+                    [(1, 8, 64), (2, 4, 32)]),
+    # the smallest grids the library takes (4 cells per axis): smaller than
+    # one tile and one segment, periodic
+    "2d_tiny_periodic": (cases.case(dim=2, n=(4, 5), lo=(0.0, 0.0), hi=(1.0, 1.0), vn=(9, 7), vlo=(-3.0, -3.0),
+                                    vhi=(3.0, 3.0), outer="periodic", Kn=0.1, Ma=0.4),
+                         [(1, 8, 64), (2, 4, 1)]),
+    "3d_tiny_periodic": (cases.case(dim=3, n=(4, 5, 4), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), vn=(5, 4, 4),
+                                    vlo=(-3.0, -3.0, -3.0), vhi=(3.0, 3.0, 3.0), outer="periodic", Kn=0.1, Ma=0.4),
+                         [(1, 16, 256), (2, 8, 1)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_edge_sizes_agree_with_oracle(oracle_mod, torch_cuda, name):
+    """Degenerate sizes: velocity grids smaller than one node chunk, the
+    maximum nodes per axis, grids smaller than one tile or one segment
+    (periodic wrap onto the same cells), each in two tile shapes."""
+    c, tiles = EDGE[name]
+    o = oracle_mod.Oracle(c)
+    u = cases.noise(c, 5)
+    o.init_freestream(u, 1e-2)
+    o.step(5)
+    for t in tiles:
+        s = ibdvm.Solver(c)
+        s.set_tile(*t)
+        s.init_freestream(u, 1e-2)
+        s.step(5)
+        _compare_state(o, s)
+        _compare_moments(o, s)
+
+
+def test_unsupported_tiles_refused(torch_cuda):
+    s2 = ibdvm.Solver(cases.cylinder_small())
+    s3 = ibdvm.Solver(cases.sphere(n=12, vn=4))
+    for s, bad in ((s2, (3, 4, 32)), (s2, (1, 16, 32)), (s2, (1, 4, 0)), (s2, (1, 4, 257)),
+                   (s3, (1, 4, 32)), (s3, (0, 16, 8))):
+        with pytest.raises(ibdvm.IbdvmError) as e:
+            s.set_tile(*bad)
+        assert e.value.code == ibdvm.E_INVALID_ARG
+    assert tuple(s2.get_tile()) != (3, 4, 32)
+
+
 def test_residual_matches_oracle(oracle_mod, torch_cuda):
     """Section 4 convergence residual of the last step against the oracle's
     moments of the two steps.  The change of W over one step is about 1e-3
