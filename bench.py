@@ -47,6 +47,27 @@ def _traffic(workload, precision, tile):
     return rec.get("hbm_bytes_per_launch")
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs, one wave64 FP64 (or non-packed FP32)
+# VALU instruction per SIMD every 4 cycles at 2.4 GHz
+VALU_PEAK = 1024 * 2.4e9 / 4
+
+
+def _alu(workload, precision, tile, avg_ms):
+    """The update kernel's VALU issue rate: wavefront VALU instructions per
+    launch from a committed rocprofv3 counter run (same kernel source and
+    tile) over the launch duration timed live, against the issue peak."""
+    tag = "-".join(str(int(x)) for x in tile)
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}_{precision}_tile{tag}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha") != _kernel_sha():
+        return None
+    achieved = rec["valu_wave_instr_per_launch"] / (avg_ms * 1e-3)
+    return {"achieved": achieved, "peak": VALU_PEAK, "unit": "wave64 VALU instr/s", "frac": achieved / VALU_PEAK,
+            "lane_instr_per_update": rec["valu_lane_instr_per_update"], "busy_frac_counter": rec["valu_busy_frac"]}
+
+
 def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     import torch
     from paper_2512_20252_amd import cases, ibdvm
@@ -113,6 +134,7 @@ def sphere3d(n, steps, warmup, tiles):
                      "update_avg_launch_ms": avg, "update_GBs_alg": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1), "tile": list(tile),
                      "traffic": _traffic(f"sphere_{n}x{n}x{n}_v24x24x24", prec, tile),
+                     "alu": _alu(f"sphere_{n}x{n}x{n}_v24x24x24", prec, tile, avg),
                      "CD": cd, "fluid_cells": s.nfluid, "velocity_nodes": s.NV,
                      "footprint_GB": ibdvm.footprint(case, prec) / 1e9}
         del s
@@ -241,6 +263,7 @@ def main():
                    "cells": 65536, "fluid_cells": r64["nfluid"], "velocity_nodes": r64["NV"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "alu": _alu(workload, "f64", r64["tile"], avg_ms),
                      "kernel": "k_update2d<double,%d,%d>" % tuple(r64["tile"][:2]),
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
@@ -254,7 +277,9 @@ def main():
         line["precision_form"] = {"dtype": "f32 storage, f64 moments/equilibrium/wall", "value": v32,
                                   "ratio_vs_f64": v32 / value, "dCD_vs_f64": abs(r32["cd"] - r64["cd"]),
                                   "CD_f64": r64["cd"], "update_avg_launch_ms": avg32,
-                                  "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9}
+                                  "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9,
+                                  "update_traffic": _traffic(workload, "f32", r32["tile"]),
+                                  "alu": _alu(workload, "f32", r32["tile"], avg32)}
     if args.sphere > 0:
         parse = lambda t: tuple(int(x) for x in t.split(",")) if t else None
         line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2,
