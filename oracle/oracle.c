@@ -30,6 +30,7 @@
 
 #define OR_FREESTREAM 0
 #define OR_PERIODIC 1
+#define OR_WALLS 2 /* 2D: diffuse walls on all four sides, the side y = hi moving along x */
 
 #define OR_G_NONE 0
 #define OR_G_CIRCLE 1
@@ -65,6 +66,7 @@ typedef struct {
     double aoa;
     double Kn, Ma, Pr, gam, alpha, Tw, cfl, omega, avhs;
     int flags;
+    double lid_u; /* OR_WALLS: velocity of the wall at y = hi, along x */
 } or_case;
 
 typedef struct {
@@ -103,6 +105,9 @@ typedef struct {
     double *fsp[2], *fgc[2], *fiw[2], *fss[2], *fw[2], *gh[2], *fc[2];
     double *rhow; /* [npairs] */
     double Uinf;
+    /* OR_WALLS: ghost rows of the boundary cells, sides x-, x+, y-, y+ in
+     * turn, one row per boundary cell along the wall [2 (nx + ny)][NV] */
+    double *wgh[2];
 } or_state;
 
 /* ------------------------------------------------------------------ */
@@ -577,10 +582,14 @@ void *or_create(const or_case *cs, int *err)
             for (int a = 0; a < D; ++a)
                 if (ijk[a] < 3 || ijk[a] > cs->n[a] - 4) *err = 2;
     }
+    if (cs->outer == OR_WALLS && D != 2) *err = 1;
     if (*err) {
         or_destroy(s);
         return NULL;
     }
+    if (cs->outer == OR_WALLS)
+        for (int A = 0; A < s->NA; ++A)
+            s->wgh[A] = (double *)calloc((size_t)2 * (cs->n[0] + cs->n[1]) * s->NV, sizeof(double));
     /* pairs: one per (ghost, fluid face neighbour), ordered by ghost index,
      * then axis, then side (-1 before +1) */
     s->pnb = (int *)malloc(sizeof(int) * 6 * s->Nc);
@@ -709,6 +718,8 @@ void or_destroy(void *h)
         free(s->fc[A]);
     }
     free(s->rhow);
+    free(s->wgh[0]);
+    free(s->wgh[1]);
     free(s->mom);
     free(s->tau);
     free(s);
@@ -993,8 +1004,59 @@ static void ib_fill(or_state *s)
     }
 }
 
+/* OR_WALLS: ghost row of boundary cell (i, j) for the wall on side `side`
+ * of axis a */
+static size_t wall_row(const or_state *s, int a, int side, const int ijk[3])
+{
+    const int nx = s->c.n[0], ny = s->c.n[1];
+    if (a == 0) return (size_t)(side < 0 ? 0 : ny) + ijk[1];
+    return (size_t)(2 * ny + (side < 0 ? 0 : nx)) + ijk[0];
+}
+
+/* Diffuse outer walls (reading R29: the wall model of Section 2.3 applied at
+ * the domain faces).  For each boundary cell and wall, the ghost layer holds
+ * the wall Maxwellian at (U_wall, T_w) with the density rho_w that makes the
+ * net normal mass flux through the wall face zero for the first-order
+ * outgoing face values f of the boundary cell, on the velocities leaving the
+ * wall, and the cell's own value f on the velocities toward the wall (zero
+ * gradient); both ghost layers are equal and their slope is zero. */
+static void wall_fill(or_state *s)
+{
+    const int NV = s->NV;
+    double *hw = (double *)malloc(sizeof(double) * NV), *bw = (double *)malloc(sizeof(double) * NV);
+    for (int a = 0; a < 2; ++a)
+        for (int sd = -1; sd <= 1; sd += 2) {
+            double U[3] = {(a == 1 && sd > 0) ? s->c.lid_u : 0.0, 0.0, 0.0};
+            maxwellian(s, 1.0, U, s->c.Tw, hw, bw);
+            const int nb = s->c.n[1 - a];
+            for (int b = 0; b < nb; ++b) {
+                int ijk[3] = {0, 0, 0};
+                ijk[a] = sd < 0 ? 0 : s->c.n[a] - 1;
+                ijk[1 - a] = b;
+                const size_t o = (size_t)cell_id(s, ijk) * NV;
+                double out = 0.0, in = 0.0;
+                for (int k = 0; k < NV; ++k) {
+                    const double xn = sd * s->xi[3 * k + a]; /* > 0: toward the wall */
+                    if (xn > 0.0)
+                        out += s->w[k] * xn * s->f[0][o + k];
+                    else if (xn < 0.0)
+                        in -= s->w[k] * xn * hw[k];
+                }
+                const double rw = out / in;
+                const size_t r = wall_row(s, a, sd, ijk) * NV;
+                for (int k = 0; k < NV; ++k) {
+                    const double xn = sd * s->xi[3 * k + a];
+                    s->wgh[0][r + k] = xn < 0.0 ? rw * hw[k] : s->f[0][o + k];
+                    s->wgh[1][r + k] = xn < 0.0 ? rw * bw[k] : s->f[1][o + k];
+                }
+            }
+        }
+    free(hw);
+    free(bw);
+}
+
 /* value seen by fluid cell c at c + side*e_a; kind: 0 fluid, 1 outer
- * freestream ghost, 2 immersed-boundary ghost.  *nbc returns the fluid
+ * freestream or wall ghost, 2 immersed-boundary ghost.  *nbc returns the fluid
  * neighbour index (after periodic wrap) or -1. */
 static double nb_value(const or_state *s, int A, int c, int a, int side, int k, int *kind, int *nbc)
 {
@@ -1006,6 +1068,13 @@ static double nb_value(const or_state *s, int A, int c, int a, int side, int k, 
             *kind = 1;
             *nbc = -1;
             return s->fs[A][k];
+        }
+        if (s->c.outer == OR_WALLS) {
+            int bc[3];
+            cell_ijk(s, c, bc);
+            *kind = 1;
+            *nbc = -1;
+            return s->wgh[A][wall_row(s, a, side, bc) * s->NV + k];
         }
         ijk[a] = (ijk[a] + s->c.n[a]) % s->c.n[a];
     }
@@ -1040,7 +1109,7 @@ static double face_state(const or_state *s, int A, int c, int a, int side, int k
     if (side * xa > 0.0) return s->f[A][(size_t)c * s->NV + k] + side * full_slope(s, A, c, a, k) * (0.5 * h);
     int kind, n;
     double fv = nb_value(s, A, c, a, side, k, &kind, &n);
-    if (kind == 1) return fv; /* outer freestream ghost: zero slope (reading R15) */
+    if (kind == 1) return fv; /* outer freestream or wall ghost: zero slope (readings R15, R29) */
     if (kind == 2) {
         int ip = s->pnb[6 * c + 2 * a + (side > 0)];
         return s->fc[A][(size_t)ip * s->NV + k];
@@ -1097,6 +1166,7 @@ void or_step(void *h, int n)
         all_moments(s);
         double dt = time_step(s);
         ib_fill(s);
+        if (s->c.outer == OR_WALLS) wall_fill(s);
         update(s, dt);
         s->dt = dt;
         s->time += dt;

@@ -12,7 +12,7 @@ import numpy as np
 
 BASE = dict(Pr=2.0 / 3.0, gamma=5.0 / 3.0, alpha=1.0, Tw=1.0, cfl=0.5, omega_vhs=0.81, a_vhs=1.0,
             outer="freestream", rule="midpoint", geometry="none", center=(0.0, 0.0, 0.0),
-            size=(0.0, 0.0, 0.0), aoa=0.0, flags=())
+            size=(0.0, 0.0, 0.0), aoa=0.0, flags=(), lid_u=0.0)
 
 
 def case(**kw):
@@ -60,6 +60,16 @@ def sphere(n=96, vn=24):
     return case(dim=3, n=(n, n, n), lo=(-4.0, -4.0, -4.0), hi=(4.0, 4.0, 4.0), vn=(vn, vn, vn),
                 vlo=(-6.0, -6.0, -6.0), vhi=(6.0, 6.0, 6.0), geometry="sphere", size=(0.5, 0.0, 0.0),
                 Kn=0.1, Ma=1.5)
+
+
+def cavity(n=64, vn=40, Kn=0.075, lid_u=0.15):
+    """Lid-driven cavity with a stationary cylinder (Section 4 convergence
+    test): unit square, n^2 cells, diffuse walls at T_w = 1 with the top wall
+    moving at lid_u along x, cylinder of diameter 0.25 at the centre,
+    vn^2 midpoint velocity grid on [-5,5]^2, gas initially at rest."""
+    return case(dim=2, n=(n, n), lo=(0.0, 0.0), hi=(1.0, 1.0), outer="walls", lid_u=lid_u, vn=(vn, vn),
+                vlo=(-5.0, -5.0), vhi=(5.0, 5.0), geometry="circle", center=(0.5, 0.5, 0.0),
+                size=(0.125, 0.0, 0.0), Kn=Kn, Ma=0.0)
 
 
 def n_cells(c):

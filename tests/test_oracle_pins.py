@@ -631,3 +631,66 @@ def test_manufactured_wall_temperature_order(oracle_mod):
     linf = np.log2(errs[:-1, 1] / errs[1:, 1])
     assert np.all(l1 >= 1.8), l1
     assert linf.mean() >= 1.7, linf
+
+
+# ---------------------------------------------------------------- P15 diffuse outer walls (lid-driven cavity)
+def _cavity_box(n=(16, 16), **kw):
+    base = dict(dim=2, n=n, lo=(0.0, 0.0), hi=(1.0, 1.0), outer="walls", vn=(24, 24), vlo=(-5.0, -5.0),
+                vhi=(5.0, 5.0), Kn=0.075, Ma=0.0)
+    base.update(kw)
+    return cases.case(**base)
+
+
+def test_walls_rest_state_stationary(oracle_mod):
+    """Four diffuse walls at rest at T_w (the wall model of Section 2.3 at
+    the domain faces) around gas at rest at T_w: the wall density equals the
+    gas density, the ghost rows equal the state and the state is steady to
+    round-off.  T_w = 0.7 differs from the reference temperature, so a wall
+    Maxwellian at the wrong temperature fails this (a colder wall keeps the
+    Gaussian tail beyond the velocity box below round-off)."""
+    c = _cavity_box(n=(12, 10), vn=(32, 32), vlo=(-6.0, -6.0), vhi=(6.0, 6.0), Tw=0.7)
+    o = oracle_mod.Oracle(c)
+    h, b = o.maxwellian(1.0, (0.0, 0.0), 0.7)
+    o.set_state((np.tile(h, (o.Nc, 1)), np.tile(b, (o.Nc, 1))))
+    f0 = o.get_state()
+    o.step(40)
+    f1 = o.get_state()
+    for a, z in zip(f0, f1):
+        assert np.max(np.abs(a - z)) <= 1e-13 * np.max(a)
+
+
+@pytest.mark.parametrize("Kn,tol", [(100.0, 1e-14), (0.075, 1e-10)])
+def test_walls_conserve_mass(oracle_mod, Kn, tol):
+    """Diffuse walls pass no mass (the wall density of Section 2.3 zeroes
+    the normal mass flux through each wall face): with the lid moving, the
+    total mass of a closed cavity drifts only at round-off when collisions
+    are negligible (Kn = 100), and by the quadrature defect of the discrete
+    equilibrium otherwise (24^2 velocities)."""
+    o = oracle_mod.Oracle(_cavity_box(Kn=Kn, lid_u=0.3))
+    o.init_freestream()
+    _, w = o.velocity()
+    m0 = (o.get_state()[0] @ w).sum()
+    o.step(50)
+    m1 = (o.get_state()[0] @ w).sum()
+    assert abs(m1 - m0) <= tol * m0
+
+
+def test_cavity_mirror_symmetry_and_sense(oracle_mod):
+    """Reversing the lid velocity mirrors the cavity flow in x (the setup is
+    symmetric about x = 1/2): rho and T are mirrored, U_x changes sign,
+    U_y is mirrored.  With the lid at y = 1 moving along +x the flow below it
+    follows the lid and the vortex turns clockwise: down along x = 1, up
+    along x = 0."""
+    n = 16
+    res = []
+    for u in (0.3, -0.3):
+        o = oracle_mod.Oracle(_cavity_box(n=(n, n), lid_u=u))
+        o.init_freestream()
+        o.step(50)
+        res.append(o.moments().reshape(n, n, 8))
+    a, z = res
+    for q, sg in ((0, 1.0), (1, -1.0), (2, 1.0), (4, 1.0)):
+        assert np.max(np.abs(a[:, :, q] - sg * z[:, ::-1, q])) < 1e-12
+    assert a[-1, :, 1].mean() > 0.05
+    assert a[:, -1, 2].mean() < 0.0 < a[:, 0, 2].mean()
+    assert abs(a[0, :, 1].mean()) < 0.1 * a[-1, :, 1].mean()
