@@ -57,7 +57,12 @@ typedef enum {
     IBDVM_E_STATE = 7        /* context unusable (host-only or previously unstable) */
 } ibdvm_status;
 
-enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1 };
+/* outer boundary of the box: freestream ghost cells (Section 4 external
+ * flows), periodic, or (2D only) diffuse walls at T_w on all four sides with
+ * the wall y = hi moving along +x at lid_u (lid-driven cavity, Section 4):
+ * the wall model of Section 2.3 applied at the domain faces, with the wall
+ * density from zero normal mass flux through each boundary face */
+enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1, IBDVM_OUTER_WALLS = 2 };
 enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1 };
 enum {
     IBDVM_GEOM_NONE = 0,
@@ -79,6 +84,7 @@ typedef struct {
     int32_t n[3];
     double lo[3], hi[3];
     int32_t outer_bc;
+    double lid_u; /* IBDVM_OUTER_WALLS: speed of the wall y = hi along +x (units of sqrt(2 R T_inf)); else ignored */
 } ibdvm_grid;
 
 /* tensor velocity grid (Section 2.2 quadrature): midpoint nodes at

@@ -85,6 +85,11 @@ struct Dev {
     double *fillpart;  // [pair][fill chunk][2]: incident and specular partial wall fluxes
     double *pforce;
     double *respart;  // [moment-finish workgroup][2 kResVars]
+    // outer walls (2D): ghost rows in the storage type, per array; rows
+    // [0, ny) the wall x = lo (row j: cell (0, j)), [ny, 2ny) x = hi,
+    // [2ny, 2ny + nx) y = lo (row 2ny + i: cell (i, 0)), then y = hi
+    void *wallT[2];
+    double lid_u;  // speed of the wall y = hi along +x
     Ctrl *ctrl;
 };
 

@@ -20,6 +20,7 @@ struct Problem {
     int n[3] = {1, 1, 1};
     double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
     int outer = 0;
+    double lid_u = 0;
     int vn[3] = {1, 1, 1};
     double vlo[3] = {0, 0, 0}, vhi[3] = {0, 0, 0};
     int rule = 0;

@@ -32,6 +32,7 @@ constexpr double kPi = 3.14159265358979323846;
 struct Layout {
     size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, fwall, rhow, fillpart, pforce, ctrl;
     size_t respart;  // moment-finish workgroups x 2 kResVars
+    size_t wallT;    // outer walls: NA x 2(nx + ny) ghost rows in the storage type
     size_t devcopy;  // the context's Dev, read by launches over several solves
     size_t total;
     size_t state_bytes;  // one array of one buffer
@@ -39,7 +40,7 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
+Layout make_layout(const ibdvm::Geometry &g, int NA, int precision, const ibdvm::Problem &p)
 {
     Layout L{};
     size_t off = 0;
@@ -78,6 +79,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision)
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * ibdvm::kForceWords * 8);
     L.respart = take((size_t)((g.Nc + 3) / 4) * 2 * ibdvm::kResVars * 8);
+    L.wallT = take(p.outer == IBDVM_OUTER_WALLS ? (size_t)NA * 2 * (p.n[0] + p.n[1]) * g.NV * es : 0);
     L.ctrl = take(sizeof(ibdvm::Ctrl));
     L.devcopy = take(sizeof(ibdvm::Dev));
     L.total = off;
@@ -108,9 +110,15 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
         if (!(vg->hi[a] > 0.0) || vg->lo[a] != -vg->hi[a])
             return fail(IBDVM_E_INVALID_ARG, "velocity box must be symmetric about 0");
     }
-    if (grid->outer_bc != IBDVM_OUTER_FREESTREAM && grid->outer_bc != IBDVM_OUTER_PERIODIC)
+    if (grid->outer_bc != IBDVM_OUTER_FREESTREAM && grid->outer_bc != IBDVM_OUTER_PERIODIC &&
+        grid->outer_bc != IBDVM_OUTER_WALLS)
         return fail(IBDVM_E_INVALID_ARG, "unknown outer boundary condition");
+    if (grid->outer_bc == IBDVM_OUTER_WALLS && grid->dim != 2)
+        return fail(IBDVM_E_UNSUPPORTED, "outer walls are implemented for dim 2 only");
+    if (grid->outer_bc == IBDVM_OUTER_WALLS && !std::isfinite(grid->lid_u))
+        return fail(IBDVM_E_INVALID_ARG, "lid speed must be finite");
     p.outer = grid->outer_bc;
+    p.lid_u = grid->outer_bc == IBDVM_OUTER_WALLS ? grid->lid_u : 0.0;
     if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID) return fail(IBDVM_E_INVALID_ARG, "unknown quadrature rule");
     p.rule = vg->rule;
     int k = geom->kind;
@@ -261,6 +269,7 @@ ibdvm_status one_step(ibdvm_ctx *c)
     if ((st = mark(c, 1))) return st;
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, true, c->pending, c->stream));
     if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
+    HIP_CHECK(ibdvm::launch_wall_fill(c->dev, c->precision, c->cur, c->stream));
     if (c->prob.dim == 2)
         HIP_CHECK(ibdvm::launch_update2d(c->dev, c->precision, c->cur, slot, c->tile, c->stream));
     else
@@ -330,6 +339,7 @@ ibdvm_status fused_step(ibdvm_ctx *const *cs, int n, hipStream_t stream)
 {
     ibdvm_status st = fused_fill(cs, n, true, stream);
     if (st) return st;
+    for (int i = 0; i < n; ++i) HIP_CHECK(ibdvm::launch_wall_fill(cs[i]->dev, cs[i]->precision, cs[i]->cur, stream));
     for (int prec = 0; prec < 2; ++prec)
         for (int V = 1; V <= 2; ++V)
             for (int TX = 4; TX <= 8; TX += 4) {
@@ -391,7 +401,7 @@ ibdvm_status build(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm_ge
     if (code) return fail((ibdvm_status)code, err);
     c.NA = c.prob.dim == 2 ? 2 : 1;
     c.precision = opts->precision;
-    c.L = make_layout(c.geo, c.NA, c.precision);
+    c.L = make_layout(c.geo, c.NA, c.precision, c.prob);
     return IBDVM_OK;
 }
 
@@ -567,6 +577,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.Nc = g.Nc;
     d.npairs = (int)np;
     d.outer = c->prob.outer;
+    d.lid_u = c->prob.lid_u;
     d.flags = c->prob.flags;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = c->prob.n[a];
@@ -619,6 +630,11 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.fillpart = (double *)(ws + L.fillpart);
     d.pforce = (double *)(ws + L.pforce);
     d.respart = (double *)(ws + L.respart);
+    {
+        const size_t wrow = (size_t)2 * (c->prob.n[0] + c->prob.n[1]) * NV * (c->precision == IBDVM_F32_STORE ? 4 : 8);
+        for (int A = 0; A < 2; ++A)
+            d.wallT[A] = c->prob.outer == IBDVM_OUTER_WALLS ? (void *)(ws + L.wallT + (A < c->NA ? A : 0) * wrow) : nullptr;
+    }
     d.ctrl = (ibdvm::Ctrl *)(ws + L.ctrl);
 
     auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {

@@ -60,7 +60,7 @@ __device__ __forceinline__ T neighbour(const Dev &d, const T *f, int A, int k, i
 {
     int i = ijk[a] + side;
     if (i < 0 || i >= d.n[a]) {
-        if (d.outer == 0) {
+        if (d.outer != 1) {
             kind = NB_BC;
             nc = -1;
             pr = -1;
@@ -836,22 +836,34 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     const int w = uni(threadIdx.x >> 6);
     const int i = i0 + w;
     const bool col_in = i < nx;
-    const bool per = d.outer != 0;
+    const bool per = d.outer == 1;
+    const bool walls = d.outer == 2;
     const int rowb = NV * ST;
     const size_t rstride = (size_t)nx * (size_t)rowb;
 
-    // tile column -> grid column (periodic wrap); fs: the freestream row
-    auto colmap = [&](int ic, bool &fs) -> int {
-        fs = !per && (ic < 0 || ic >= nx);
+    // tile column -> grid column (periodic wrap); fs: the freestream row;
+    // xw: side of the x wall whose ghost rows stand in for the column
+    auto colmap = [&](int ic, bool &fs, int &xw) -> int {
+        const bool out = ic < 0 || ic >= nx;
+        fs = d.outer == 0 && out;
+        xw = walls && out ? (ic < 0 ? -1 : 1) : 0;
         return ic < 0 ? ic + nx : (ic >= nx ? ic - nx : ic);
     };
-    // velocity row at row jr of a column whose row 0 starts at col (fs: the
-    // column reads the freestream row fsr)
-    auto rowp = [&](const char *col, const char *fsr, bool cfs, int jr) -> const char * {
+    // velocity row of array A at row jr of a column whose row 0 starts at
+    // col (grid column ic; fs: the column reads the freestream row; walls:
+    // rows of an x-wall column are its ghost rows, rows beyond the grid in
+    // y are the y-wall ghost rows of column ic; both ghost layers of a wall
+    // hold the same row, so the ghost's slope is zero)
+    auto rowp = [&](int A, const char *col, bool cfs, int xw, int ic, int jr) -> const char * {
         const bool in = jr >= 0 && jr < ny;
+        if (walls) {
+            if (xw) return col + (size_t)(unsigned)min(max(jr, 0), ny - 1) * rowb;
+            if (!in) return (const char *)d.wallT[A] + (size_t)(unsigned)(2 * ny + (jr < 0 ? 0 : nx) + ic) * rowb;
+            return col + (size_t)(unsigned)jr * rstride;
+        }
         const int jw = jr < 0 ? jr + ny : (jr >= ny ? jr - ny : jr);
         const bool usefs = cfs || (!in && !per);
-        return usefs ? fsr : col + (size_t)(unsigned)jw * rstride;
+        return usefs ? (const char *)d.fsT[A] : col + (size_t)(unsigned)jw * rstride;
     };
     auto ldflag = [&](int ic, int jr) -> int {
         const bool in = ic >= 0 && ic < nx && jr >= 0 && jr < ny;
@@ -921,7 +933,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     };
 
     bool cfs;
-    const int ie = colmap(i, cfs);
+    int cxw;
+    const int ie = colmap(i, cfs, cxw);
     // halo columns staged by wavefronts 0..3
     const int hcol = w < 2 ? i0 - 2 + w : i0 + TX + (w - 2);
     const int hpos = w < 2 ? w : TX + 2 + (w - 2);
@@ -934,15 +947,16 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     const int hA = w & 1;
     const int spos = hright ? TX + 1 : 0;
     bool hfs;
-    const int he = colmap(hcol, hfs);
-    const char *fcol[2], *hcolp[2], *fsr[2];
+    int hxw;
+    const int he = colmap(hcol, hfs, hxw);
+    const char *fcol[2], *hcolp[2];
     char *gcol[2];
 #pragma unroll
     for (int A = 0; A < 2; ++A) {
-        fcol[A] = (const char *)d.f[cur][A] + (size_t)ie * rowb;
-        hcolp[A] = (const char *)d.f[cur][A] + (size_t)he * rowb;
+        const char *wr = (const char *)d.wallT[A];
+        fcol[A] = cxw ? wr + (size_t)(cxw < 0 ? 0 : ny) * rowb : (const char *)d.f[cur][A] + (size_t)ie * rowb;
+        hcolp[A] = hxw ? wr + (size_t)(hxw < 0 ? 0 : ny) * rowb : (const char *)d.f[cur][A] + (size_t)he * rowb;
         gcol[A] = (char *)d.f[cur ^ 1][A] + (size_t)ie * rowb;
-        fsr[A] = (const char *)d.fsT[A];
     }
 
     // rows in flight, selected modulo 4 by the unrolled row position
@@ -954,12 +968,12 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         T fm2[2][V], fm1[2][V];
 #pragma unroll
         for (int A = 0; A < 2; ++A) {
-            const brsrc r0 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 - 2), rowb);
-            const brsrc r1 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 - 1), rowb);
-            const brsrc r2 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0), rowb);
-            const brsrc r3 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 + 1), rowb);
-            const brsrc r4 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j0 + 2), rowb);
-            const brsrc rh = mk_rsrc(rowp(hcolp[A], fsr[A], hfs, j0), hload ? rowb : 0);
+            const brsrc r0 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j0 - 2), rowb);
+            const brsrc r1 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j0 - 1), rowb);
+            const brsrc r2 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j0), rowb);
+            const brsrc r3 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j0 + 1), rowb);
+            const brsrc r4 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j0 + 2), rowb);
+            const brsrc rh = mk_rsrc(rowp(A, hcolp[A], hfs, hxw, he, j0), hload ? rowb : 0);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 fm2[A][v] = bld(r0, koff[v], T());
@@ -1018,8 +1032,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         // prefetch: own column row j+3, halo column row j+1
 #pragma unroll
         for (int A = 0; A < 2; ++A) {
-            const brsrc r3 = mk_rsrc(rowp(fcol[A], fsr[A], cfs, j + 3), rowb);
-            const brsrc rh = mk_rsrc(rowp(hcolp[A], fsr[A], hfs, j + 1), hload ? rowb : 0);
+            const brsrc r3 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j + 3), rowb);
+            const brsrc rh = mk_rsrc(rowp(A, hcolp[A], hfs, hxw, he, j + 1), hload ? rowb : 0);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 f3[A][v] = bld(r3, koff[v], T());
@@ -1195,6 +1209,66 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     }
 }
 
+// Ghost rows of the diffuse outer walls (2D), one workgroup per boundary
+// cell and wall: the wall model of Section 2.3 at a domain face.  Velocities
+// leaving the wall carry the wall Maxwellian at (U_wall, T_w) scaled by the
+// density that zeroes the normal mass flux through the face against the
+// cell's own h on the velocities toward the wall; those and the tangential
+// velocities keep the cell's value.  The sums run in FP64, the rows are
+// written in the storage type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
+{
+    const int nx = d.n[0], ny = d.n[1], NV = d.NV;
+    const int r = blockIdx.x;
+    int a, sd, cell;
+    if (r < 2 * ny) {
+        const int j = r < ny ? r : r - ny;
+        a = 0;
+        sd = r < ny ? -1 : 1;
+        cell = (sd < 0 ? 0 : nx - 1) + nx * j;
+    } else {
+        const int q = r - 2 * ny, i = q < nx ? q : q - nx;
+        a = 1;
+        sd = q < nx ? -1 : 1;
+        cell = i + nx * (sd < 0 ? 0 : ny - 1);
+    }
+    const double Ux = (a == 1 && sd > 0) ? d.lid_u : 0.0;
+    const double iTw = 1.0 / d.Tw;
+    const T *h = (const T *)d.f[cur][0] + (size_t)cell * NV;
+    const T *b = (const T *)d.f[cur][1] + (size_t)cell * NV;
+    // e^{-c^2/T_w} of the wall Maxwellian at node k
+    auto ew = [&](int k) {
+        const double cx = d.xi[0][k] - Ux, cy = d.xi[1][k];
+        return exp(-(cx * cx + cy * cy) * iTw);
+    };
+    double out = 0.0, in = 0.0;
+    for (int k = threadIdx.x; k < NV; k += 256) {
+        const double xn = sd * d.xi[a][k];
+        if (xn > 0.0)
+            out += d.w[k] * xn * (double)h[k];
+        else if (xn < 0.0)
+            in -= d.w[k] * xn * ew(k);
+    }
+    out = block_sum(out);
+    in = block_sum(in);
+    // in sums e^{-c^2/T_w} without the prefactor A_w, so out / in is
+    // rho_w A_w: the factor of e^{-c^2/T_w} in the ghost
+    const double rA = out / in;
+    T *g0 = (T *)d.wallT[0] + (size_t)r * NV;
+    T *g1 = (T *)d.wallT[1] + (size_t)r * NV;
+    for (int k = threadIdx.x; k < NV; k += 256) {
+        const double xn = sd * d.xi[a][k];
+        if (xn < 0.0) {
+            const double hv = rA * ew(k);
+            g0[k] = (T)hv;
+            g1[k] = (T)(0.5 * d.Tw * hv);
+        } else {
+            g0[k] = h[k];
+            g1[k] = b[k];
+        }
+    }
+}
 
 template <typename T, int V, int TX>
 __global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 3)))
@@ -1905,6 +1979,18 @@ hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fi
         hipLaunchKernelGGL((k_fill_ghost<2>), dim3(nfill), dim3(256), 0, s, d);
     else
         hipLaunchKernelGGL((k_fill_ghost<3>), dim3(nfill), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_fill(const Dev &d, int storage, int cur, hipStream_t s)
+{
+    if (d.outer != 2) return hipSuccess;
+    if (d.D != 2 || !d.wallT[0] || !d.wallT[1]) return hipErrorInvalidValue;
+    const dim3 g((unsigned)(2 * (d.n[0] + d.n[1])));
+    if (storage == 0)
+        hipLaunchKernelGGL((k_wall_fill<double>), g, dim3(256), 0, s, d, cur);
+    else
+        hipLaunchKernelGGL((k_wall_fill<float>), g, dim3(256), 0, s, d, cur);
     return hipGetLastError();
 }
 

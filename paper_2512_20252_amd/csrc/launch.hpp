@@ -21,6 +21,9 @@ hipError_t launch_update2d_batch(int storage, int V, int TX, const BatchArgs &a,
 hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
                              hipStream_t s);
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
+// ghost rows of the diffuse outer walls from buffer cur (no-op unless the
+// outer boundary is walls)
+hipError_t launch_wall_fill(const Dev &d, int storage, int cur, hipStream_t s);
 hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, hipStream_t s);
 hipError_t launch_force(const Dev &d, int storage, int cur, hipStream_t s);
 hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, const double *u, double amp, long long off,

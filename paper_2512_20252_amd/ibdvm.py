@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libibdvm.so")
 
 OK, E_INVALID_ARG, E_GEOMETRY, E_NO_MEMORY, E_DEVICE, E_UNSTABLE, E_UNSUPPORTED, E_STATE = range(8)
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
-OUTER = {"freestream": 0, "periodic": 1}
+OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
 RULE = {"midpoint": 0, "trapezoid": 1}
 PRECISION = {"f64": 0, "f32": 1}
 FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "host_only": 1 << 8}
@@ -26,7 +26,7 @@ c_int32, c_double, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.
 
 class Grid(ctypes.Structure):
     _fields_ = [("dim", c_int32), ("n", c_int32 * 3), ("lo", c_double * 3), ("hi", c_double * 3),
-                ("outer_bc", c_int32)]
+                ("outer_bc", c_int32), ("lid_u", c_double)]
 
 
 class VGrid(ctypes.Structure):
@@ -155,6 +155,7 @@ def structs(case, precision="f64", flags=(), workspace=0, nbytes=0, stream=0):
         v.lo[a] = case["vlo"][a] if a < d else 0.0
         v.hi[a] = case["vhi"][a] if a < d else 0.0
     g.outer_bc = OUTER[case.get("outer", "freestream")]
+    g.lid_u = case.get("lid_u", 0.0)
     v.rule = RULE[case.get("rule", "midpoint")]
     ge = Geom()
     ge.kind = GEOMETRY[case.get("geometry", "none")]

@@ -91,6 +91,18 @@ def test_argument_validation():
     _expect(ibdvm.E_INVALID_ARG, mk(cfl=1.5))
     _expect(ibdvm.E_INVALID_ARG, mk(geometry="sphere"))
     _expect(ibdvm.E_GEOMETRY, mk(size=(0.9, 0.0, 0.0)))
+    _expect(ibdvm.E_INVALID_ARG, mk(outer="walls", lid_u=float("nan")))
+    # outer walls are 2D only
+    sph = dict(cases.sphere(n=14, vn=6), outer="walls")
+    _expect(ibdvm.E_UNSUPPORTED, lambda: ibdvm.Solver(sph, host_only=True))
+    ibdvm.Solver(cases.cavity(n=32, vn=12), host_only=True)
+
+
+def test_walls_footprint_holds_ghost_rows():
+    """Outer walls add 2 (nx + ny) ghost rows per array to the workspace."""
+    c = cases.cavity(n=40, vn=16)
+    extra = ibdvm.footprint(c) - ibdvm.footprint(dict(c, outer="freestream"))
+    assert abs(extra - 2 * 2 * (40 + 40) * 256 * 8) <= 256  # regions are 256-byte aligned
 
 
 def test_host_only_context_refuses_compute():
