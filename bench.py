@@ -11,8 +11,8 @@ cases).
 Prints one JSON line: cell-velocity updates/s of the FP64 step, the
 roofline of the update kernel (algorithmic HBM bytes per launch over its
 HIP-event duration), the FP32-storage form's rate and C_D difference, the
-3D sphere at 96^3 x 24^3 in both forms, the continuous-batching serving leg,
-and the CPU oracle timed on this host over one step of the same workload.
+3D sphere at 96^3 x 24^3 in both forms, the lid-driven cavity at 256^2 x
+100^2 in both forms, the continuous-batching serving leg, and the CPU oracle timed on this host over one step of the same workload.
 """
 import argparse
 import hashlib
@@ -144,6 +144,49 @@ def sphere3d(n, steps, warmup, tiles):
     return out
 
 
+def cavity(n, vn, steps, warmup, tiles):
+    """Lid-driven cavity leg (unit square, n^2 cells, vn^2 velocity nodes on
+    [-5,5]^2, cylinder of diameter 0.25 at the centre, lid 0.15, T_w = 1,
+    Kn 0.075, gas initially at rest): FP64 and FP32-storage update rates,
+    algorithmic HBM bytes per update launch over its HIP-event duration, and
+    the fill phase (immersed-boundary ghosts plus the outer-wall ghost rows)
+    per step."""
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    case = cases.cavity(n=n, vn=vn)
+    out = {"workload": f"2D lid-driven cavity with a cylinder (D=0.25), {n}^2 cells, {vn}^2 velocity nodes on "
+                       "[-5,5]^2, lid 0.15, T_w 1, Kn 0.075, diffuse outer walls", "steps": steps, "warmup": warmup}
+    for prec in ("f64", "f32"):
+        s = ibdvm.Solver(case, precision=prec)
+        s.init_freestream()
+        if tiles[prec]:
+            s.set_tile(*tiles[prec])
+            tile = s.get_tile()
+        else:
+            tile = s.autotune(reps=2)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        s.profile(True)
+        t = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        prof = s.profile_read()
+        upd = s.nfluid * s.NV
+        avg = prof["update_ms"] / max(prof["update_launches"], 1)
+        gbs = upd * B_ALG[(2, prec)] / (avg * 1e-3) / 1e9
+        m = s.moments()
+        out[prec] = {"updates_per_s": upd * steps / wall, "ms_per_step": wall * 1e3 / steps,
+                     "update_avg_launch_ms": avg, "update_GBs_alg": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                     "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1), "tile": list(tile),
+                     "lid_row_mean_Ux": float(m[-n:, 1].mean()), "fluid_cells": s.nfluid, "velocity_nodes": s.NV}
+        del s
+        torch.cuda.empty_cache()
+    out["ratio_f32_vs_f64"] = out["f32"]["updates_per_s"] / out["f64"]["updates_per_s"]
+    return out
+
+
 def cpu_baseline(case, seed=0):
     from oracle import oracle as oracle_mod
     from paper_2512_20252_amd import cases
@@ -211,6 +254,9 @@ def main():
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
     ap.add_argument("--sphere-tile32", type=str, default="2,16,256", help="V,TX,LY of the FP32 3D update")
+    ap.add_argument("--cavity", type=int, default=256, help="cells per side of the lid-driven cavity leg (0: skip)")
+    ap.add_argument("--cavity-vn", type=int, default=100, help="velocity nodes per axis of the cavity leg")
+    ap.add_argument("--cavity-steps", type=int, default=20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -284,6 +330,8 @@ def main():
         parse = lambda t: tuple(int(x) for x in t.split(",")) if t else None
         line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2,
                                     {"f64": parse(args.sphere_tile), "f32": parse(args.sphere_tile32)})
+    if args.cavity > 0:
+        line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
     if args.serving > 0:
         line["serving"] = serving(args.serving, args.serving_cap, 1e-4, 0.5)
     if not args.no_cpu:

@@ -254,8 +254,10 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *ctx, int32_t reps, int32_t out[3]);
  * update launch and every ghost-fill / moment-finish launch of this context
  * is bracketed by a pair of events on the context stream.
  * ibdvm_profile_read synchronises, returns the summed durations in
- * milliseconds (ms[0] update kernel, ms[1] ghost-fill kernel) and launch
- * counts, and clears the record.  Disabling also clears it. */
+ * milliseconds (ms[0] update kernel, ms[1] the ghost-fill phase: the
+ * immersed-boundary fill with the moment finish and, with outer walls, the
+ * wall ghost rows) and launch counts, and clears the record.  Disabling also
+ * clears it. */
 ibdvm_status ibdvm_profile(ibdvm_ctx *ctx, int32_t enable);
 ibdvm_status ibdvm_profile_read(ibdvm_ctx *ctx, double ms[2], int64_t counts[2]);
 

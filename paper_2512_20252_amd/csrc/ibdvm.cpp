@@ -268,8 +268,8 @@ ibdvm_status one_step(ibdvm_ctx *c)
     ibdvm_status st;
     if ((st = mark(c, 1))) return st;
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, true, c->pending, c->stream));
-    if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
     HIP_CHECK(ibdvm::launch_wall_fill(c->dev, c->precision, c->cur, c->stream));
+    if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
     if (c->prob.dim == 2)
         HIP_CHECK(ibdvm::launch_update2d(c->dev, c->precision, c->cur, slot, c->tile, c->stream));
     else
@@ -340,31 +340,33 @@ ibdvm_status fused_step(ibdvm_ctx *const *cs, int n, hipStream_t stream)
     ibdvm_status st = fused_fill(cs, n, true, stream);
     if (st) return st;
     for (int i = 0; i < n; ++i) HIP_CHECK(ibdvm::launch_wall_fill(cs[i]->dev, cs[i]->precision, cs[i]->cur, stream));
-    for (int prec = 0; prec < 2; ++prec)
-        for (int V = 1; V <= 2; ++V)
-            for (int TX = 4; TX <= 8; TX += 4) {
-                std::vector<ibdvm_ctx *> grp;
-                for (int i = 0; i < n; ++i) {
-                    const ibdvm_ctx *c = cs[i];
-                    if (c->prob.dim == 2 && c->precision == prec && c->tile.V == V && c->tile.TX == TX)
-                        grp.push_back(cs[i]);
-                }
-                for (size_t b = 0; b < grp.size(); b += ibdvm::kMaxBatch) {
-                    const int m = (int)std::min<size_t>(ibdvm::kMaxBatch, grp.size() - b);
-                    ibdvm::BatchArgs a{};
-                    a.n = m;
-                    for (int q = 0; q < m; ++q) {
-                        const ibdvm_ctx *c = grp[b + q];
-                        batch_entry(a, q, c);
-                        a.LY[q] = c->tile.LY;
-                        a.ntx[q] = (c->prob.n[0] + TX - 1) / TX;
-                        a.nys[q] = (c->prob.n[1] + c->tile.LY - 1) / c->tile.LY;
-                        a.ncv[q] = (c->geo.NV + 64 * V - 1) / (64 * V);
-                        a.blk0[q + 1] = a.blk0[q] + (long long)a.ntx[q] * a.nys[q] * a.ncv[q];
+    for (int walls = 0; walls < 2; ++walls)
+        for (int prec = 0; prec < 2; ++prec)
+            for (int V = 1; V <= 2; ++V)
+                for (int TX = 4; TX <= 8; TX += 4) {
+                    std::vector<ibdvm_ctx *> grp;
+                    for (int i = 0; i < n; ++i) {
+                        const ibdvm_ctx *c = cs[i];
+                        if (c->prob.dim == 2 && c->precision == prec && c->tile.V == V && c->tile.TX == TX &&
+                            (c->prob.outer == IBDVM_OUTER_WALLS) == (walls == 1))
+                            grp.push_back(cs[i]);
                     }
-                    HIP_CHECK(ibdvm::launch_update2d_batch(prec, V, TX, a, stream));
+                    for (size_t b = 0; b < grp.size(); b += ibdvm::kMaxBatch) {
+                        const int m = (int)std::min<size_t>(ibdvm::kMaxBatch, grp.size() - b);
+                        ibdvm::BatchArgs a{};
+                        a.n = m;
+                        for (int q = 0; q < m; ++q) {
+                            const ibdvm_ctx *c = grp[b + q];
+                            batch_entry(a, q, c);
+                            a.LY[q] = c->tile.LY;
+                            a.ntx[q] = (c->prob.n[0] + TX - 1) / TX;
+                            a.nys[q] = (c->prob.n[1] + c->tile.LY - 1) / c->tile.LY;
+                            a.ncv[q] = (c->geo.NV + 64 * V - 1) / (64 * V);
+                            a.blk0[q + 1] = a.blk0[q] + (long long)a.ntx[q] * a.nys[q] * a.ncv[q];
+                        }
+                        HIP_CHECK(ibdvm::launch_update2d_batch(prec, V, TX, walls == 1, a, stream));
+                    }
                 }
-            }
     for (int i = 0; i < n; ++i) {
         ibdvm_ctx *c = cs[i];
         if (c->prob.dim == 3)

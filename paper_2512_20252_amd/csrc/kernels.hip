@@ -808,7 +808,7 @@ __device__ __forceinline__ T facev_at(const DR &d, int A, int c, int dir, int k8
 // near path with the pair ghost and face values; every other row runs a
 // branch-free path whose only memory traffic is the prefetch, the stores, the
 // partial record and the next row's cell record, so loads stay in flight.
-template <typename T, int V, int TX, typename DR>
+template <typename T, int V, int TX, bool WALLS, typename DR>
 __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, int LY, int ntx, int nys, int ncv, int L)
 {
     constexpr int W = 64 * V;
@@ -836,17 +836,19 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     const int w = uni(threadIdx.x >> 6);
     const int i = i0 + w;
     const bool col_in = i < nx;
-    const bool per = d.outer == 1;
-    const bool walls = d.outer == 2;
+    // WALLS: the outer boundary is the diffuse walls (a separate
+    // instantiation, so the other boundaries keep their row addressing)
+    const bool per = !WALLS && d.outer != 0;
     const int rowb = NV * ST;
     const size_t rstride = (size_t)nx * (size_t)rowb;
 
+    const char *fsr[2] = {(const char *)d.fsT[0], (const char *)d.fsT[1]};
     // tile column -> grid column (periodic wrap); fs: the freestream row;
     // xw: side of the x wall whose ghost rows stand in for the column
     auto colmap = [&](int ic, bool &fs, int &xw) -> int {
         const bool out = ic < 0 || ic >= nx;
-        fs = d.outer == 0 && out;
-        xw = walls && out ? (ic < 0 ? -1 : 1) : 0;
+        fs = !WALLS && !per && out;
+        xw = WALLS && out ? (ic < 0 ? -1 : 1) : 0;
         return ic < 0 ? ic + nx : (ic >= nx ? ic - nx : ic);
     };
     // velocity row of array A at row jr of a column whose row 0 starts at
@@ -856,14 +858,15 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     // hold the same row, so the ghost's slope is zero)
     auto rowp = [&](int A, const char *col, bool cfs, int xw, int ic, int jr) -> const char * {
         const bool in = jr >= 0 && jr < ny;
-        if (walls) {
+        if constexpr (WALLS) {
             if (xw) return col + (size_t)(unsigned)min(max(jr, 0), ny - 1) * rowb;
             if (!in) return (const char *)d.wallT[A] + (size_t)(unsigned)(2 * ny + (jr < 0 ? 0 : nx) + ic) * rowb;
             return col + (size_t)(unsigned)jr * rstride;
+        } else {
+            const int jw = jr < 0 ? jr + ny : (jr >= ny ? jr - ny : jr);
+            const bool usefs = cfs || (!in && !per);
+            return usefs ? fsr[A] : col + (size_t)(unsigned)jw * rstride;
         }
-        const int jw = jr < 0 ? jr + ny : (jr >= ny ? jr - ny : jr);
-        const bool usefs = cfs || (!in && !per);
-        return usefs ? (const char *)d.fsT[A] : col + (size_t)(unsigned)jw * rstride;
     };
     auto ldflag = [&](int ic, int jr) -> int {
         const bool in = ic >= 0 && ic < nx && jr >= 0 && jr < ny;
@@ -953,7 +956,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     char *gcol[2];
 #pragma unroll
     for (int A = 0; A < 2; ++A) {
-        const char *wr = (const char *)d.wallT[A];
+        const char *wr = WALLS ? (const char *)d.wallT[A] : nullptr;
         fcol[A] = cxw ? wr + (size_t)(cxw < 0 ? 0 : ny) * rowb : (const char *)d.f[cur][A] + (size_t)ie * rowb;
         hcolp[A] = hxw ? wr + (size_t)(hxw < 0 ? 0 : ny) * rowb : (const char *)d.f[cur][A] + (size_t)he * rowb;
         gcol[A] = (char *)d.f[cur ^ 1][A] + (size_t)ie * rowb;
@@ -1270,19 +1273,19 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
     }
 }
 
-template <typename T, int V, int TX>
+template <typename T, int V, int TX, bool WALLS>
 __global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 3)))
 void k_update2d(Dev d, int cur, int slot, int LY, int ntx, int nys, int ncv)
 {
     const long long L = xcd_run(gridDim.x);
     if (L >= (long long)ntx * nys * ncv) return;
-    update2d_tile<T, V, TX>(d, cur, slot, LY, ntx, nys, ncv, (int)L);
+    update2d_tile<T, V, TX, WALLS>(d, cur, slot, LY, ntx, nys, ncv, (int)L);
 }
 
 // one launch over the tiles of several solves (serving form): the solves'
 // parameter blocks live in their workspaces, the per-solve launch values in
 // the argument block
-template <typename T, int V, int TX>
+template <typename T, int V, int TX, bool WALLS>
 __global__ __launch_bounds__(TX * 64) __attribute__((amdgpu_waves_per_eu(V == 1 ? 4 : 3)))
 void k_update2d_batch(BatchArgs a)
 {
@@ -1290,7 +1293,7 @@ void k_update2d_batch(BatchArgs a)
     if (L >= a.blk0[a.n]) return;
     const int s = batch_solve(a, L);
     const auto &d = *(cdev_p)a.dev[s];
-    update2d_tile<T, V, TX>(d, a.cur[s], a.slot[s], a.LY[s], a.ntx[s], a.nys[s], a.ncv[s], (int)(L - a.blk0[s]));
+    update2d_tile<T, V, TX, WALLS>(d, a.cur[s], a.slot[s], a.LY[s], a.ntx[s], a.nys[s], a.ncv[s], (int)(L - a.blk0[s]));
 }
 
 // ---------------------------------------------------------------- 3D update, marching in z
@@ -1874,10 +1877,13 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     long long nblk = (long long)ntx * nys * ncv;
     nblk = (nblk + 7) / 8 * 8;
     dim3 grid((unsigned)nblk), block(64 * t.TX);
-#define U2D(TT, VV, XX)                                                                                       \
-    if (t.V == VV && t.TX == XX) {                                                                         \
-        hipLaunchKernelGGL((k_update2d<TT, VV, XX>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv); \
-        return hipGetLastError();                                                                          \
+#define U2D(TT, VV, XX)                                                                                              \
+    if (t.V == VV && t.TX == XX) {                                                                                \
+        if (d.outer == 2)                                                                                         \
+            hipLaunchKernelGGL((k_update2d<TT, VV, XX, true>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv);  \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_update2d<TT, VV, XX, false>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv); \
+        return hipGetLastError();                                                                                 \
     }
     if (storage == 0) {
         U2D(double, 1, 4) U2D(double, 1, 8) U2D(double, 2, 4) U2D(double, 2, 8)
@@ -1888,17 +1894,20 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_update2d_batch(int storage, int V, int TX, const BatchArgs &a, hipStream_t s)
+hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const BatchArgs &a, hipStream_t s)
 {
     long long nblk = a.blk0[a.n];
     if (nblk == 0) return hipSuccess;
     nblk = (nblk + 7) / 8 * 8;
     if (nblk >= (1ll << 31)) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(64 * TX);
-#define U2B(TT, VV, XX)                                                                \
-    if (V == VV && TX == XX) {                                                      \
-        hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX>), grid, block, 0, s, a); \
-        return hipGetLastError();                                                   \
+#define U2B(TT, VV, XX)                                                                       \
+    if (V == VV && TX == XX) {                                                             \
+        if (walls)                                                                         \
+            hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX, true>), grid, block, 0, s, a);  \
+        else                                                                               \
+            hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX, false>), grid, block, 0, s, a); \
+        return hipGetLastError();                                                          \
     }
     if (storage == 0) {
         U2B(double, 1, 4) U2B(double, 1, 8) U2B(double, 2, 4) U2B(double, 2, 8)

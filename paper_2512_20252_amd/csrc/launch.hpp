@@ -16,8 +16,9 @@ struct Tile {
 hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 // launches over several solves: the 2D update of solves sharing (storage, V,
-// TX), and the three fill phases of solves sharing (D, storage)
-hipError_t launch_update2d_batch(int storage, int V, int TX, const BatchArgs &a, hipStream_t s);
+// TX, outer walls or not), and the three fill phases of solves sharing (D,
+// storage)
+hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const BatchArgs &a, hipStream_t s);
 hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
                              hipStream_t s);
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
