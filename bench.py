@@ -310,7 +310,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alu": _alu(workload, "f64", r64["tile"], avg_ms),
-                     "kernel": "k_update2d<double,%d,%d>" % tuple(r64["tile"][:2]),
+                     "kernel": "k_update2d<double, %d, %d, false>" % tuple(r64["tile"][:2]),
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
                      "tile": r64["tile"]},
