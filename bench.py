@@ -187,6 +187,66 @@ def cavity(n, vn, steps, warmup, tiles):
     return out
 
 
+def cavity_velocity_study(n, levels, nref, t_end, block=1000):
+    """Velocity-space convergence of the lid-driven cavity at steady state
+    (the study of Section 4): the cavity on n^2 cells with velocity meshes
+    levels^2, with and without the cut-cell correction, each run from rest
+    to time t_end (past the point where the residual stops falling), against
+    a reference on nref^2 nodes with the correction.  L1 errors relative to
+    the reference: rho, |U| and T over the fluid cells, p_w, tau_w and q_n
+    over the wall points; observed orders are least-squares slopes of
+    log error against log N."""
+    import numpy as np
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    def steady(vn, flags):
+        c = cases.case(**dict(cases.cavity(n=n, vn=vn), flags=flags))
+        s = ibdvm.Solver(c, stream=torch.cuda.Stream())
+        s.init_freestream()
+        g = ibdvm.Graph(s, block)
+        t0, k = time.perf_counter(), 0
+        while s.clock()["time"] < t_end:
+            g.launch()
+            k += 1
+            if k % 20 == 0:
+                print(f"cavity study: {vn}^2 nodes, t = {s.clock()['time']:.1f}", file=sys.stderr, flush=True)
+        s.step(2)
+        r = {"m": s.moments(), "wall": s.surface_forces()[3], "steps": s.clock()["step"],
+             "residual": s.residual()[1], "seconds": time.perf_counter() - t0}
+        print(f"cavity study: {vn}^2 nodes {flags or ''} {r['steps']} steps in {r['seconds']:.1f} s",
+              file=sys.stderr, flush=True)
+        g.close()
+        s.close()
+        torch.cuda.empty_cache()
+        return r
+
+    def l1(a, b):
+        return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+    ref = steady(nref, ())
+    ok = np.isfinite(ref["m"][:, 0])
+    M, W = ref["m"][ok], ref["wall"]
+    out = {"workload": f"2D lid-driven cavity with a cylinder, {n}^2 cells, velocity meshes "
+                       f"{'/'.join(str(v) for v in levels)} squared against {nref}^2 on [-5,5]^2, steady state (t = {t_end})",
+           "reference": {"steps": ref["steps"], "residual": ref["residual"], "seconds": ref["seconds"]}}
+    for tag, flags in (("cutcell", ()), ("no_cutcell", ("no_cutcell",))):
+        errs = {}
+        for vn in levels:
+            r = steady(vn, flags)
+            m, w = r["m"][ok], r["wall"]
+            errs[vn] = {"rho": l1(m[:, 0], M[:, 0]),
+                        "U": float(np.sum(np.linalg.norm(m[:, 1:3] - M[:, 1:3], axis=1)) /
+                                   np.sum(np.linalg.norm(M[:, 1:3], axis=1))),
+                        "T": l1(m[:, 4], M[:, 4]), "p_w": l1(w[:, 7], W[:, 7]), "tau_w": l1(w[:, 8:10], W[:, 8:10]),
+                        "q_n": l1(w[:, 11], W[:, 11]), "steps": r["steps"], "residual": r["residual"]}
+        ln = np.log(np.array(levels, float))
+        orders = {q: float(-np.polyfit(ln, np.log([errs[v][q] for v in levels]), 1)[0])
+                  for q in ("rho", "U", "T", "p_w", "tau_w", "q_n")}
+        out[tag] = {"L1": {str(v): e for v, e in errs.items()}, "orders": orders}
+    return out
+
+
 def cpu_baseline(case, seed=0):
     from oracle import oracle as oracle_mod
     from paper_2512_20252_amd import cases
@@ -257,6 +317,8 @@ def main():
     ap.add_argument("--cavity", type=int, default=256, help="cells per side of the lid-driven cavity leg (0: skip)")
     ap.add_argument("--cavity-vn", type=int, default=100, help="velocity nodes per axis of the cavity leg")
     ap.add_argument("--cavity-steps", type=int, default=20)
+    ap.add_argument("--cavity-study", action="store_true",
+                    help="add the cavity's velocity-space convergence study (about 4 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy three times (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -332,6 +394,8 @@ def main():
                                     {"f64": parse(args.sphere_tile), "f32": parse(args.sphere_tile32)})
     if args.cavity > 0:
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
+    if args.cavity_study:
+        line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:
         line["serving"] = serving(args.serving, args.serving_cap, 1e-4, 0.5)
     if not args.no_cpu:

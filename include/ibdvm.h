@@ -89,8 +89,8 @@ typedef struct {
 
 /* tensor velocity grid (Section 2.2 quadrature): midpoint nodes at
  * lo + (i + 1/2) h with h = (hi - lo)/N, or trapezoid nodes lo + i h with
- * h = (hi - lo)/(N - 1) and half weights at the ends; the box must be
- * symmetric about 0 */
+ * h = (hi - lo)/(N - 1) and half weights at the ends; 2 to 256 nodes per
+ * axis; the box must be symmetric about 0 */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];

@@ -34,7 +34,7 @@ constexpr int kForceWords = 8;
 
 constexpr int kChunk = 64;       // velocity nodes per wavefront
 constexpr int kFillChunk = 256;  // velocity nodes per ghost-fill workgroup
-constexpr int kMaxVn = 128;
+constexpr int kMaxVn = 256;
 
 struct DPair {
     int gc, dc, ac, axis, sign, ns;

@@ -106,7 +106,7 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
         if (!used) continue;
         if (grid->n[a] < 4) return fail(IBDVM_E_INVALID_ARG, "grid needs at least 4 cells per axis");
         if (!(grid->hi[a] > grid->lo[a])) return fail(IBDVM_E_INVALID_ARG, "grid box is empty");
-        if (vg->n[a] < 2 || vg->n[a] > ibdvm::kMaxVn) return fail(IBDVM_E_INVALID_ARG, "velocity nodes per axis must be in [2, 128]");
+        if (vg->n[a] < 2 || vg->n[a] > ibdvm::kMaxVn) return fail(IBDVM_E_INVALID_ARG, "velocity nodes per axis must be in [2, 256]");
         if (!(vg->hi[a] > 0.0) || vg->lo[a] != -vg->hi[a])
             return fail(IBDVM_E_INVALID_ARG, "velocity box must be symmetric about 0");
     }

@@ -212,13 +212,14 @@ class Solver:
                                  case["Pr"], case["gamma"], case["alpha"], case["Tw"], ctypes.byref(o),
                                  ctypes.byref(h)))
         self._h = h
+        self._lib = lib()  # held so that destruction at interpreter exit needs no module global
         info = (ctypes.c_int64 * 7)()
         check(lib().ibdvm_info(self._h, info))
         self.dim, self.Nc, self.NV, self.NA, self.npairs, self.nfluid, self.nghost = [int(x) for x in info]
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ibdvm_destroy(self._h)
+            self._lib.ibdvm_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -356,13 +357,14 @@ class Graph:
         else:
             check(lib().ibdvm_graph_create(solver.handle, int(nsteps), ctypes.byref(h)))
         self._h = h
+        self._lib = lib()  # held so that destruction at interpreter exit needs no module global
 
     def launch(self):
         check(lib().ibdvm_graph_launch(self._h))
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ibdvm_graph_destroy(self._h)
+            self._lib.ibdvm_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -382,6 +384,7 @@ class Server:
         if code != OK:
             raise IbdvmError(code, "server_create")
         self._h = h
+        self._lib = lib()  # held so that destruction at interpreter exit needs no module global
         self._outs = {}
         if fuse_below is not None:
             self._check(lib().ibdvm_server_set_fusion(self._h, int(fuse_below)))
@@ -425,7 +428,7 @@ class Server:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ibdvm_server_destroy(self._h)
+            self._lib.ibdvm_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

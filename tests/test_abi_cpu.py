@@ -89,6 +89,8 @@ def test_argument_validation():
     _expect(ibdvm.E_INVALID_ARG, mk(vlo=(-5.0, -4.0)))
     _expect(ibdvm.E_INVALID_ARG, mk(n=(3, 32)))
     _expect(ibdvm.E_INVALID_ARG, mk(cfl=1.5))
+    _expect(ibdvm.E_INVALID_ARG, mk(vn=(257, 16)))
+    ibdvm.Solver(dict(base, vn=(256, 4)), host_only=True)
     _expect(ibdvm.E_INVALID_ARG, mk(geometry="sphere"))
     _expect(ibdvm.E_GEOMETRY, mk(size=(0.9, 0.0, 0.0)))
     _expect(ibdvm.E_INVALID_ARG, mk(outer="walls", lid_u=float("nan")))

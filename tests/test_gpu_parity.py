@@ -143,8 +143,8 @@ EDGE = {
                                vlo=(-3.0, -3.0, -3.0), vhi=(3.0, 3.0, 3.0), geometry="sphere",
                                size=(0.4, 0.0, 0.0), Kn=0.1, Ma=0.6),
                     [(1, 16, 256), (2, 8, 5)]),
-    # the largest velocity grid per axis the library takes (128 nodes)
-    "2d_128_axis": (cases.case(dim=2, n=(16, 14), lo=(-0.8, -0.7), hi=(0.8, 0.7), vn=(128, 6), vlo=(-6.0, -5.0),
+    # the largest velocity grid per axis the library takes (256 nodes)
+    "2d_256_axis": (cases.case(dim=2, n=(16, 14), lo=(-0.8, -0.7), hi=(0.8, 0.7), vn=(256, 6), vlo=(-6.0, -5.0),
                                vhi=(6.0, 5.0), geometry="circle", size=(0.22, 0.0, 0.0), Kn=0.2, Ma=0.8),
                     [(1, 8, 64), (2, 4, 32)]),
     # the smallest grids the library takes (4 cells per axis): smaller than
