@@ -43,6 +43,10 @@
 
 #define OR_FLAG_NO_CUTCELL 1u
 #define OR_FLAG_NO_UPWIND 2u
+/* semi-implicit collision (reading R30): explicit transport, then the
+ * Shakhov relaxation taken implicitly with the moments of the transported
+ * state */
+#define OR_FLAG_IMPLICIT 4u
 
 /* velocity-node classes of one pair (Section 3.2.3): fully incident ("gas"),
  * fully reflected ("solid"), cut with node on the incident side (set G) and
@@ -781,7 +785,8 @@ static void all_moments(or_state *s)
 }
 
 /* time step (reading R14): positivity bound of first-order upwinding plus
- * explicit relaxation, with the smallest relaxation time of the state */
+ * explicit relaxation, with the smallest relaxation time of the state; the
+ * implicit relaxation (R30) leaves only the upwinding bound */
 static double time_step(const or_state *s)
 {
     double tmin = INFINITY;
@@ -789,6 +794,7 @@ static double time_step(const or_state *s)
         if (!s->solid[c] && s->tau[c] < tmin) tmin = s->tau[c];
     double adv = 0.0;
     for (int a = 0; a < s->D; ++a) adv += s->maxabs[a] / s->dx[a];
+    if (s->c.flags & OR_FLAG_IMPLICIT) return s->c.cfl / adv;
     return s->c.cfl / (adv + 1.0 / tmin);
 }
 
@@ -1144,7 +1150,10 @@ static void update(or_state *s, double dt)
                         div += (Fp - Fm) / s->dx[a];
                     }
                     double fv = s->f[A][o + k];
-                    s->fn[A][o + k] = fv - dt * div + dt / tau * (g[k] - fv);
+                    if (s->c.flags & OR_FLAG_IMPLICIT)
+                        s->fn[A][o + k] = fv - dt * div; /* transport only (R30) */
+                    else
+                        s->fn[A][o + k] = fv - dt * div + dt / tau * (g[k] - fv);
                 }
             }
         }
@@ -1158,6 +1167,38 @@ static void update(or_state *s, double dt)
     }
 }
 
+/* Semi-implicit collision (reading R30; the paper marches every case with
+ * forward Euler).  After the transport step the collision conserves rho, U
+ * and T, so the relaxation f = f* + (dt/tau)(g^S - f) is taken at the new
+ * time with rho, U, T of the transported state f* and with tau from them.
+ * The heat flux of the new state satisfies q = q* + r((1 - Pr) q - q) with
+ * r = dt/tau (the Shakhov equilibrium carries (1 - Pr) times the heat flux,
+ * Section 2.1), so q = q* / (1 + Pr r), and then f = (f* + r g^S) / (1 + r). */
+static void implicit_relax(or_state *s, double dt)
+{
+    const int NV = s->NV;
+#pragma omp parallel
+    {
+        double *g0 = (double *)malloc(sizeof(double) * NV), *g1 = (double *)malloc(sizeof(double) * NV);
+#pragma omp for schedule(static)
+        for (int c = 0; c < s->Nc; ++c) {
+            if (s->solid[c]) continue;
+            const size_t o = (size_t)c * NV;
+            double mom[8];
+            cell_moments(s, s->f[0] + o, s->NA == 2 ? s->f[1] + o : NULL, mom);
+            const double r = dt / relax_time(s, mom[0], mom[4]);
+            for (int a = 0; a < 3; ++a) mom[5 + a] /= 1.0 + s->c.Pr * r;
+            shakhov(s, mom, g0, g1);
+            for (int A = 0; A < s->NA; ++A) {
+                const double *g = A == 0 ? g0 : g1;
+                for (int k = 0; k < NV; ++k) s->f[A][o + k] = (s->f[A][o + k] + r * g[k]) / (1.0 + r);
+            }
+        }
+        free(g0);
+        free(g1);
+    }
+}
+
 /* advance n forward-Euler steps (Section 4: forward Euler in all cases) */
 void or_step(void *h, int n)
 {
@@ -1168,6 +1209,7 @@ void or_step(void *h, int n)
         ib_fill(s);
         if (s->c.outer == OR_WALLS) wall_fill(s);
         update(s, dt);
+        if (s->c.flags & OR_FLAG_IMPLICIT) implicit_relax(s, dt);
         s->dt = dt;
         s->time += dt;
         s->step++;

@@ -18,7 +18,7 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
 RULE = {"midpoint": 0, "trapezoid": 1}
-FLAGS = {"no_cutcell": 1, "no_upwind": 2}
+FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4}
 
 CL_GAS, CL_SOLID, CL_CUT_G, CL_CUT_S = 0, 1, 2, 3
 

@@ -694,3 +694,95 @@ def test_cavity_mirror_symmetry_and_sense(oracle_mod):
     assert a[-1, :, 1].mean() > 0.05
     assert a[:, -1, 2].mean() < 0.0 < a[:, 0, 2].mean()
     assert abs(a[0, :, 1].mean()) < 0.1 * a[-1, :, 1].mean()
+
+
+# ---------------------------------------------------------------- P16 semi-implicit collision (R30)
+def _pressure_deviator(xi, w, h, U):
+    c = xi[:, :2] - np.asarray(U)[:2]
+    pxx, pyy, pxy = (w * c[:, 0] ** 2) @ h, (w * c[:, 1] ** 2) @ h, (w * c[:, 0] * c[:, 1]) @ h
+    return np.array([pxx - pyy, pxy])
+
+
+def test_implicit_relaxation_closed_forms(oracle_mod):
+    """A uniform periodic box has no transport, so one semi-implicit step is
+    the backward-Euler Shakhov relaxation alone (R30): rho, U, T stay, the
+    heat flux becomes q / (1 + Pr dt/tau) and the pressure deviator
+    sigma / (1 + dt/tau) (the Shakhov equilibrium has no deviatoric stress and
+    (1 - Pr) times the heat flux, Section 2.1), with dt = CFL / sum max|xi|/dx
+    and no relaxation-time bound."""
+    c = cases.case(**_box2(N=56, V=7.0, n=(4, 4), outer="periodic", Kn=0.01, flags=("implicit",)))
+    o = oracle_mod.Oracle(c)
+    f = _nonequilibrium(o, None)
+    o.set_state(tuple(np.tile(fi, (o.Nc, 1)) for fi in f))
+    xi, w = o.velocity()
+    m0 = o.moments()[0]
+    tau = o.tau()[0]
+    dt = o.next_dt()
+    assert dt == pytest.approx(c["cfl"] / (2 * np.max(np.abs(xi[:, 0])) / 0.25), rel=1e-14)
+    r = dt / tau
+    assert 0.3 < r < 3.0
+    s0 = _pressure_deviator(xi, w, f[0], m0[1:3])
+    o.step(1)
+    h1, b1 = o.get_state()
+    m1 = o.moments()
+    assert np.max(np.abs(m1 - m1[0])) == 0.0  # still uniform
+    m1 = m1[0]
+    assert np.allclose(m1[[0, 1, 2, 4]], m0[[0, 1, 2, 4]], rtol=0, atol=1e-12)
+    assert np.allclose(m1[5:7], m0[5:7] / (1.0 + c["Pr"] * r), rtol=1e-9, atol=1e-13)
+    assert np.allclose(_pressure_deviator(xi, w, h1[0], m1[1:3]), s0 / (1.0 + r), rtol=1e-9, atol=1e-13)
+
+
+def test_implicit_periodic_box_conservation(oracle_mod):
+    """Transport telescopes and the implicit relaxation keeps rho, U, T: in a
+    periodic box the totals drift only at round-off and quadrature-defect
+    level."""
+    c = _box2(N=32, V=6.0, n=(12, 10), outer="periodic", Ma=0.0, Kn=0.02, flags=("implicit",))
+    o = oracle_mod.Oracle(cases.case(**c))
+    o.init_freestream(cases.noise(c, seed=1), 1e-1)
+    xi, w = o.velocity()
+
+    def totals():
+        h, b = o.get_state()
+        return np.array([(h @ w).sum(), (h @ (w * xi[:, 0])).sum(), (h @ (w * xi[:, 1])).sum(),
+                         ((h @ (w * (xi[:, 0] ** 2 + xi[:, 1] ** 2))) + b @ w).sum()])
+
+    t0 = totals()
+    o.step(60)
+    t1 = totals()
+    assert abs(t1[0] - t0[0]) < 1e-13 * t0[0]
+    assert np.all(np.abs(t1[1:3] - t0[1:3]) < 1e-12 * t0[0])
+    assert abs(t1[3] - t0[3]) < 1e-12 * t0[3]
+
+
+def test_implicit_stiff_limit(oracle_mod):
+    """With tau far below the transport step (Kn 1e-6, dt/tau ~ 1e5) the
+    semi-implicit step stays bounded and leaves every cell within (dt/tau)^-1
+    of the Shakhov equilibrium of its own moments (R30); dt/tau is about
+    2.6e3 here."""
+    c = _box2(N=32, V=6.0, n=(12, 10), outer="periodic", Ma=0.0, Kn=1e-6, flags=("implicit",))
+    o = oracle_mod.Oracle(cases.case(**c))
+    o.init_freestream(cases.noise(c, seed=2), 1e-1)
+    for _ in range(3):
+        o.step(5)
+        r = o.clock()["dt"] / np.max(o.tau())
+        assert r > 1e3
+        h, b = o.get_state()
+        m = o.moments()
+        for cell in (0, 37, 119):
+            g = o.shakhov(m[cell])
+            assert np.max(np.abs(h[cell] - g[0])) <= 2.0 / r * np.max(h[cell])
+            assert np.max(np.abs(b[cell] - g[1])) <= 2.0 / r * np.max(b[cell])
+
+
+def test_implicit_collisionless_equals_explicit(oracle_mod):
+    """Without collisions (Kn 1e12) the semi-implicit step is the explicit
+    one: both are pure transport with the same dt."""
+    base = _box2(N=24, V=6.0, n=(10, 9), outer="periodic", Ma=0.0, Kn=1e12)
+    states = []
+    for flags in ((), ("implicit",)):
+        o = oracle_mod.Oracle(cases.case(**dict(base, flags=flags)))
+        o.init_freestream(cases.noise(base, seed=3), 1e-1)
+        o.step(8)
+        states.append(o.get_state())
+    for a, z in zip(*states):
+        assert np.max(np.abs(a - z)) <= 1e-13 * np.max(a)
