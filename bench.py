@@ -12,7 +12,8 @@ Prints one JSON line: cell-velocity updates/s of the FP64 step, the
 roofline of the update kernel (algorithmic HBM bytes per launch over its
 HIP-event duration), the FP32-storage form's rate and C_D difference, the
 3D sphere at 96^3 x 24^3 in both forms, the lid-driven cavity at 256^2 x
-100^2 in both forms, the continuous-batching serving leg, and the CPU oracle timed on this host over one step of the same workload.
+100^2 in both forms, the semi-implicit collision against the explicit step on
+the cylinder at Kn 2e-4, the continuous-batching serving leg, and the CPU oracle timed on this host over one step of the same workload.
 """
 import argparse
 import hashlib
@@ -187,6 +188,44 @@ def cavity(n, vn, steps, warmup, tiles):
     return out
 
 
+def implicit_collision(Kn, steps, warmup):
+    """Semi-implicit collision leg: the 256^2 cylinder (48^2 nodes, Ma 0.3)
+    at a small Knudsen number, FP64, with the explicit step and with the
+    semi-implicit collision: time step, wall time per step, simulated time
+    per wall second, update and fill-phase launch times (the fill phase
+    includes the moment finish, which does the implicit relaxation)."""
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    out = {"workload": f"2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
+                       f"Kn {Kn}, Ma 0.3, FP64", "steps": steps, "warmup": warmup}
+    for mode, flags in (("explicit", ()), ("implicit", ("implicit",))):
+        case = cases.case(**dict(cases.cylinder_256(Kn=Kn, Ma=0.3), flags=flags))
+        s = ibdvm.Solver(case)
+        s.init_freestream(cases.noise(case, 0), 1e-3)
+        tile = s.autotune(reps=2)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        s.profile(True)
+        t0 = s.clock()["time"]
+        t = time.perf_counter()
+        s.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        prof = s.profile_read()
+        clk = s.clock()
+        out[mode] = {"dt": clk["dt"], "ms_per_step": wall * 1e3 / steps,
+                     "sim_time_per_s": (clk["time"] - t0) / wall,
+                     "updates_per_s": s.nfluid * s.NV * steps / wall,
+                     "update_avg_launch_ms": prof["update_ms"] / max(prof["update_launches"], 1),
+                     "fill_ms_per_step": prof["fill_ms"] / steps, "tile": list(tile)}
+        del s
+        torch.cuda.empty_cache()
+    out["dt_ratio"] = out["implicit"]["dt"] / out["explicit"]["dt"]
+    out["sim_time_rate_ratio"] = out["implicit"]["sim_time_per_s"] / out["explicit"]["sim_time_per_s"]
+    return out
+
+
 def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     """Velocity-space convergence of the lid-driven cavity at steady state
     (the study of Section 4): the cavity on n^2 cells with velocity meshes
@@ -317,6 +356,8 @@ def main():
     ap.add_argument("--cavity", type=int, default=256, help="cells per side of the lid-driven cavity leg (0: skip)")
     ap.add_argument("--cavity-vn", type=int, default=100, help="velocity nodes per axis of the cavity leg")
     ap.add_argument("--cavity-steps", type=int, default=20)
+    ap.add_argument("--implicit-kn", type=float, default=2e-4,
+                    help="Knudsen number of the semi-implicit collision leg (0: skip)")
     ap.add_argument("--cavity-study", action="store_true",
                     help="add the cavity's velocity-space convergence study (about 4 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -394,6 +435,8 @@ def main():
                                     {"f64": parse(args.sphere_tile), "f32": parse(args.sphere_tile32)})
     if args.cavity > 0:
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
+    if args.implicit_kn > 0:
+        line["implicit_collision"] = implicit_collision(args.implicit_kn, 50, 3)
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:

@@ -75,6 +75,14 @@ enum { IBDVM_F64 = 0, IBDVM_F32_STORE = 1 };
 enum {
     IBDVM_FLAG_NO_CUTCELL = 1u << 0, /* ablation: classify velocity cells by node sign only */
     IBDVM_FLAG_NO_UPWIND = 1u << 1,  /* ablation: uniform weights 1/N_S in the ghost interpolation */
+    /* semi-implicit collision for small Kn (a variant; the paper marches
+     * with forward Euler, Section 4): each step transports explicitly, then
+     * relaxes implicitly, f = (f* + r g^S)/(1 + r) with r = dt/tau, where
+     * rho, U, T and tau come from the transported state f* and the heat flux
+     * of g^S is q* / (1 + Pr r) (the Shakhov equilibrium carries (1 - Pr) q,
+     * Section 2.1); dt = cfl / sum_a max|xi_a|/dx_a, without the
+     * relaxation-time bound */
+    IBDVM_FLAG_IMPLICIT_COLLISION = 1u << 2,
     IBDVM_FLAG_HOST_ONLY = 1u << 8   /* build the geometry tables only; no device work */
 };
 

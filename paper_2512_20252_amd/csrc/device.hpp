@@ -32,6 +32,8 @@ constexpr int kResVars = 5;
 // tau_w[3], q_n
 constexpr int kForceWords = 8;
 
+// Dev::flags bit of the semi-implicit collision (IBDVM_FLAG_IMPLICIT_COLLISION)
+constexpr unsigned kFlagImplicit = 1u << 2;
 constexpr int kChunk = 64;       // velocity nodes per wavefront
 constexpr int kFillChunk = 256;  // velocity nodes per ghost-fill workgroup
 constexpr int kMaxVn = 256;

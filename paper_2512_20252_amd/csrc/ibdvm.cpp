@@ -17,6 +17,8 @@
 #include "geometry.hpp"
 #include "launch.hpp"
 
+static_assert(ibdvm::kFlagImplicit == IBDVM_FLAG_IMPLICIT_COLLISION, "device flag bit of the semi-implicit collision");
+
 namespace {
 
 thread_local std::string g_err;
@@ -267,6 +269,12 @@ ibdvm_status one_step(ibdvm_ctx *c)
     const int slot = (int)(c->step & 1);
     ibdvm_status st;
     if ((st = mark(c, 1))) return st;
+    if (c->pending && (c->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION)) {
+        // the moment finish relaxes the state, so it completes before the
+        // ghost fill reads it
+        HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, false, true, c->stream));
+        c->pending = false;
+    }
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, true, c->pending, c->stream));
     HIP_CHECK(ibdvm::launch_wall_fill(c->dev, c->precision, c->cur, c->stream));
     if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
@@ -306,6 +314,15 @@ void batch_entry(ibdvm::BatchArgs &a, int q, const ibdvm_ctx *c)
 // the fill phases (fill) and the moment finish of pending contexts
 ibdvm_status fused_fill(ibdvm_ctx *const *cs, int n, bool fill, hipStream_t stream)
 {
+    if (fill) {
+        // a semi-implicit solve relaxes in its moment finish: finish first
+        bool split = false;
+        for (int i = 0; i < n; ++i) split = split || (cs[i]->pending && (cs[i]->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION));
+        if (split) {
+            ibdvm_status st = fused_fill(cs, n, false, stream);
+            if (st) return st;
+        }
+    }
     for (int D = 2; D <= 3; ++D)
         for (int prec = 0; prec < 2; ++prec) {
             std::vector<ibdvm_ctx *> grp;

@@ -81,11 +81,14 @@ __device__ __forceinline__ T neighbour(const Dev &d, const T *f, int A, int k, i
     return f[(size_t)n * d.NV + k];
 }
 
-// the cell parameters of one fluid cell from its moments; returns tau
+// the cell parameters of one fluid cell from its moments; returns tau.
+// With the semi-implicit collision the update record's relaxation rate is 0:
+// the update then transports only, and the moment finish relaxes.
 template <typename DR>
 __device__ double write_cell(const DR &d, int c, double rho, const double U[3], double T, const double q[3], int D)
 {
     double tau = d.mu0 * pow(T, d.omega) / (0.5 * rho * T);
+    const double rate = (d.flags & kFlagImplicit) ? 0.0 : 1.0 / tau;
     double *cp = d.cellp + (size_t)c * kCellWords;
     double A = (D == 2) ? rho / (kPi * T) : rho * pow(kPi * T, -1.5);
     double coef = d.shk / (rho * T * T);
@@ -110,7 +113,7 @@ __device__ double write_cell(const DR &d, int c, double rho, const double U[3], 
         k2[4] = coef * q[0];
         k2[5] = coef * q[1];
         k2[6] = 0.5 * T;
-        k2[7] = 1.0 / tau;
+        k2[7] = rate;
     } else {
         // 3D update record: U[3], A, 1/T, s[3], 1/tau (word 9: flag word of the cell above)
         double *k3 = d.cellq + (size_t)c * kQWords;
@@ -122,7 +125,7 @@ __device__ double write_cell(const DR &d, int c, double rho, const double U[3], 
         k3[5] = coef * q[0];
         k3[6] = coef * q[1];
         k3[7] = coef * q[2];
-        k3[8] = 1.0 / tau;
+        k3[8] = rate;
     }
     bool bad = !(rho > 0.0) || !(T > 0.0) || !isfinite(rho) || !isfinite(T) || !isfinite(tau);
     if (bad) atomicOr(&d.ctrl->health, 1u);
@@ -132,6 +135,9 @@ __device__ double write_cell(const DR &d, int c, double rho, const double U[3], 
 template <typename DR>
 __device__ __forceinline__ void tau_min_commit(const DR &d, int slot, double tau)
 {
+    // the semi-implicit collision takes no relaxation-time bound on dt: the
+    // slot keeps +inf (uniform over the workgroup)
+    if (d.flags & kFlagImplicit) return;
     __shared__ double red[4];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -347,8 +353,75 @@ __device__ void fill_ghost(const DR &d, int p, int chunk)
 }
 
 // ---------------------------------------------------------------- moments
-template <int D, typename DR>
-__device__ void fin_cells(const DR &d, int slot, int blk)
+// f = (f* + r g^S)/(1 + r) over the nodes of fluid cell c, one wavefront;
+// g^S from rho, U, T and the new heat flux q (the equilibrium of the update).
+// Returns the moments of the relaxed state in rho, U, T, q (every lane):
+// rho, U and T from its raw sums, then q about that U in a second pass.
+template <int D, typename T, typename DR>
+__device__ void relax_cell(const DR &d, int cur, int c, double &rho, double U[3], double &Tc, double q[3], double r)
+{
+    const int lane = threadIdx.x & 63;
+    const double iT = 1.0 / Tc;
+    const double A = (D == 2) ? rho / (kPi * Tc) : rho * pow(kPi * Tc, -1.5);
+    const double coef = d.shk / (rho * Tc * Tc), c0 = 1.0 / (1.0 + r), halfT = 0.5 * Tc;
+    double s[3];
+    for (int a = 0; a < 3; ++a) s[a] = coef * q[a];
+    T *f0 = (T *)d.f[cur][0] + (size_t)c * d.NV;
+    T *f1 = D == 2 ? (T *)d.f[cur][1] + (size_t)c * d.NV : nullptr;
+    double m0 = 0.0, m1[3] = {0, 0, 0}, E2 = 0.0;
+    for (int k = lane; k < d.NV; k += 64) {
+        double c2 = 0.0, cs = 0.0, x2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            const double x = d.xi[a][k], ca = x - U[a];
+            c2 += ca * ca;
+            cs += ca * s[a];
+            x2 += x * x;
+        }
+        const double a_ = c2 * iT, Ae = A * exp(-a_);
+        double e2;
+        if (D == 2) {
+            const double g0 = Ae * (1.0 + cs * (2.0 * a_ - 4.0));
+            const double g1 = halfT * Ae * (1.0 + cs * (2.0 * a_ - 2.0));
+            const T n0 = (T)(((double)f0[k] + r * g0) * c0), n1 = (T)(((double)f1[k] + r * g1) * c0);
+            f0[k] = n0;
+            f1[k] = n1;
+            m0 += d.w[k] * (double)n0;
+            for (int a = 0; a < D; ++a) m1[a] += d.w[k] * d.xi[a][k] * (double)n0;
+            e2 = x2 * (double)n0 + (double)n1;
+        } else {
+            const double g = Ae * (1.0 + cs * (2.0 * a_ - 5.0));
+            const T n0 = (T)(((double)f0[k] + r * g) * c0);
+            f0[k] = n0;
+            m0 += d.w[k] * (double)n0;
+            for (int a = 0; a < D; ++a) m1[a] += d.w[k] * d.xi[a][k] * (double)n0;
+            e2 = x2 * (double)n0;
+        }
+        E2 += d.w[k] * e2;
+    }
+    rho = wave_sum(m0);
+    E2 = wave_sum(E2);
+    double U2 = 0.0;
+    for (int a = 0; a < 3; ++a) U[a] = 0.0;
+    for (int a = 0; a < D; ++a) {
+        U[a] = wave_sum(m1[a]) / rho;
+        U2 += U[a] * U[a];
+    }
+    Tc = 4.0 * (0.5 * E2 - 0.5 * rho * U2) / (3.0 * rho);
+    double qq[3] = {0, 0, 0};
+    for (int k = lane; k < d.NV; k += 64) {
+        double cc[3] = {0, 0, 0}, c2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            cc[a] = d.xi[a][k] - U[a];
+            c2 += cc[a] * cc[a];
+        }
+        const double E = c2 * (double)f0[k] + (D == 2 ? (double)f1[k] : 0.0);
+        for (int a = 0; a < D; ++a) qq[a] += d.w[k] * cc[a] * E;
+    }
+    for (int a = 0; a < 3; ++a) q[a] = a < D ? 0.5 * wave_sum(qq[a]) : 0.0;
+}
+
+template <int D, typename TS, typename DR>
+__device__ void fin_cells(const DR &d, int cur, int slot, int blk)
 {
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -409,6 +482,15 @@ __device__ void fin_cells(const DR &d, int slot, int blk)
             for (int b = 0; b < D; ++b) Md += M[a][b] * del[b];
             q[a] = 0.5 * (m3[a] - 2.0 * Md - del[a] * m2 + 2.0 * dd * m1[a]);
         }
+        // semi-implicit collision: the new heat flux in closed form, then
+        // the backward-Euler relaxation of the cell's transported state,
+        // which returns the relaxed state's moments
+        const bool imp = d.flags & kFlagImplicit;
+        if (imp) {
+            const double r = d.ctrl->dt * (0.5 * m0 * T) / (d.mu0 * pow(T, d.omega));
+            for (int a = 0; a < D; ++a) q[a] /= 1.0 + d.Pr * r;
+            relax_cell<D, TS>(d, cur, c, m0, U, T, q, r);
+        }
         const double Wo[kResVars] = {rho_old, rho_old * Uref[0], rho_old * Uref[1], rho_old * Uref[2],
                                      rho_old * (0.5 * (Uref[0] * Uref[0] + Uref[1] * Uref[1] + Uref[2] * Uref[2]) +
                                                 0.75 * T_old)};
@@ -441,7 +523,7 @@ __global__ __launch_bounds__(256) void k_fill_fin(Dev d, int cur, int slot, int 
         fill_incident<D, T>(d, cur, blockIdx.x / nfc, blockIdx.x % nfc);
         return;
     }
-    if (dofin) fin_cells<D>(d, slot, blockIdx.x - nfill);
+    if (dofin) fin_cells<D, T>(d, cur, slot, blockIdx.x - nfill);
 }
 
 template <int D>
@@ -484,7 +566,7 @@ __global__ __launch_bounds__(256) void k_fill_fin_batch(BatchArgs a)
         fill_incident<D, T>(d, a.cur[s], b / nfc, b % nfc);
         return;
     }
-    fin_cells<D>(d, a.slot[s], b - a.nfill[s]);
+    fin_cells<D, T>(d, a.cur[s], a.slot[s], b - a.nfill[s]);
 }
 
 template <int D>

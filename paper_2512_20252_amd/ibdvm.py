@@ -19,7 +19,7 @@ GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
 RULE = {"midpoint": 0, "trapezoid": 1}
 PRECISION = {"f64": 0, "f32": 1}
-FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "host_only": 1 << 8}
+FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "implicit": 1 << 2, "host_only": 1 << 8}
 
 c_int32, c_double, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 
