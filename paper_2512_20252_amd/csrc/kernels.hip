@@ -353,13 +353,52 @@ __device__ void fill_ghost(const DR &d, int p, int chunk)
 }
 
 // ---------------------------------------------------------------- moments
+// rho, U, T, q of a cell from its moment sums about Uref: S = m0, m1[D],
+// m2, m3[D], M (upper triangle), with m2 and m3 over c^2 h + b in 2D (the
+// record the update writes per node chunk)
+template <int D>
+__device__ __forceinline__ void moments_from_sums(const double *S, const double Uref[3], double &rho, double U[3],
+                                                  double &T, double q[3])
+{
+    double m1[3] = {0, 0, 0}, m3[3] = {0, 0, 0}, M[3][3] = {};
+    const double m0 = S[0];
+    for (int a = 0; a < D; ++a) {
+        m1[a] = S[1 + a];
+        m3[a] = S[2 + D + a];
+    }
+    const double m2 = S[1 + D];
+    int o = 2 + 2 * D;
+    for (int a = 0; a < D; ++a)
+        for (int b = a; b < D; ++b) {
+            M[a][b] = M[b][a] = S[o];
+            ++o;
+        }
+    double del[3] = {0, 0, 0}, mm = 0.0, dd = 0.0;
+    for (int a = 0; a < 3; ++a) U[a] = Uref[a];
+    for (int a = 0; a < D; ++a) {
+        del[a] = m1[a] / m0;
+        U[a] = Uref[a] + del[a];
+        mm += m1[a] * m1[a];
+        dd += del[a] * del[a];
+    }
+    rho = m0;
+    T = (2.0 / 3.0) * (m2 - mm / m0) / m0;
+    for (int a = 0; a < 3; ++a) q[a] = 0.0;
+    for (int a = 0; a < D; ++a) {
+        double Md = 0.0;
+        for (int b = 0; b < D; ++b) Md += M[a][b] * del[b];
+        q[a] = 0.5 * (m3[a] - 2.0 * Md - del[a] * m2 + 2.0 * dd * m1[a]);
+    }
+}
+
 // f = (f* + r g^S)/(1 + r) over the nodes of fluid cell c, one wavefront;
 // g^S from rho, U, T and the new heat flux q (the equilibrium of the update).
-// Returns the moments of the relaxed state in rho, U, T, q (every lane):
-// rho, U and T from its raw sums, then q about that U in a second pass.
+// Leaves the relaxed state's moment sums about U in S (every lane).
 template <int D, typename T, typename DR>
-__device__ void relax_cell(const DR &d, int cur, int c, double &rho, double U[3], double &Tc, double q[3], double r)
+__device__ void relax_cell(const DR &d, int cur, int c, double rho, const double U[3], double Tc, const double q[3],
+                           double r, double *S)
 {
+    constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63;
     const double iT = 1.0 / Tc;
     const double A = (D == 2) ? rho / (kPi * Tc) : rho * pow(kPi * Tc, -1.5);
@@ -368,56 +407,44 @@ __device__ void relax_cell(const DR &d, int cur, int c, double &rho, double U[3]
     for (int a = 0; a < 3; ++a) s[a] = coef * q[a];
     T *f0 = (T *)d.f[cur][0] + (size_t)c * d.NV;
     T *f1 = D == 2 ? (T *)d.f[cur][1] + (size_t)c * d.NV : nullptr;
-    double m0 = 0.0, m1[3] = {0, 0, 0}, E2 = 0.0;
+    double acc[PW];
+#pragma unroll
+    for (int j = 0; j < PW; ++j) acc[j] = 0.0;
     for (int k = lane; k < d.NV; k += 64) {
-        double c2 = 0.0, cs = 0.0, x2 = 0.0;
-        for (int a = 0; a < D; ++a) {
-            const double x = d.xi[a][k], ca = x - U[a];
-            c2 += ca * ca;
-            cs += ca * s[a];
-            x2 += x * x;
-        }
-        const double a_ = c2 * iT, Ae = A * exp(-a_);
-        double e2;
-        if (D == 2) {
-            const double g0 = Ae * (1.0 + cs * (2.0 * a_ - 4.0));
-            const double g1 = halfT * Ae * (1.0 + cs * (2.0 * a_ - 2.0));
-            const T n0 = (T)(((double)f0[k] + r * g0) * c0), n1 = (T)(((double)f1[k] + r * g1) * c0);
-            f0[k] = n0;
-            f1[k] = n1;
-            m0 += d.w[k] * (double)n0;
-            for (int a = 0; a < D; ++a) m1[a] += d.w[k] * d.xi[a][k] * (double)n0;
-            e2 = x2 * (double)n0 + (double)n1;
-        } else {
-            const double g = Ae * (1.0 + cs * (2.0 * a_ - 5.0));
-            const T n0 = (T)(((double)f0[k] + r * g) * c0);
-            f0[k] = n0;
-            m0 += d.w[k] * (double)n0;
-            for (int a = 0; a < D; ++a) m1[a] += d.w[k] * d.xi[a][k] * (double)n0;
-            e2 = x2 * (double)n0;
-        }
-        E2 += d.w[k] * e2;
-    }
-    rho = wave_sum(m0);
-    E2 = wave_sum(E2);
-    double U2 = 0.0;
-    for (int a = 0; a < 3; ++a) U[a] = 0.0;
-    for (int a = 0; a < D; ++a) {
-        U[a] = wave_sum(m1[a]) / rho;
-        U2 += U[a] * U[a];
-    }
-    Tc = 4.0 * (0.5 * E2 - 0.5 * rho * U2) / (3.0 * rho);
-    double qq[3] = {0, 0, 0};
-    for (int k = lane; k < d.NV; k += 64) {
-        double cc[3] = {0, 0, 0}, c2 = 0.0;
+        double cc[3] = {0, 0, 0}, c2 = 0.0, cs = 0.0;
         for (int a = 0; a < D; ++a) {
             cc[a] = d.xi[a][k] - U[a];
             c2 += cc[a] * cc[a];
+            cs += cc[a] * s[a];
         }
-        const double E = c2 * (double)f0[k] + (D == 2 ? (double)f1[k] : 0.0);
-        for (int a = 0; a < D; ++a) qq[a] += d.w[k] * cc[a] * E;
+        const double a_ = c2 * iT, Ae = A * exp(-a_), w = d.w[k];
+        double n0, e;
+        if (D == 2) {
+            const double g0 = Ae * (1.0 + cs * (2.0 * a_ - 4.0));
+            const double g1 = halfT * Ae * (1.0 + cs * (2.0 * a_ - 2.0));
+            const T t0 = (T)(((double)f0[k] + r * g0) * c0), t1 = (T)(((double)f1[k] + r * g1) * c0);
+            f0[k] = t0;
+            f1[k] = t1;
+            n0 = (double)t0;
+            e = c2 * n0 + (double)t1;
+        } else {
+            const double g = Ae * (1.0 + cs * (2.0 * a_ - 5.0));
+            const T t0 = (T)(((double)f0[k] + r * g) * c0);
+            f0[k] = t0;
+            n0 = (double)t0;
+            e = c2 * n0;
+        }
+        acc[0] += w * n0;
+        acc[1 + D] += w * e;
+        int o = 2 + 2 * D;
+        for (int a = 0; a < D; ++a) {
+            acc[1 + a] += w * cc[a] * n0;
+            acc[2 + D + a] += w * cc[a] * e;
+            for (int b = a; b < D; ++b) acc[o++] += w * cc[a] * cc[b] * n0;
+        }
     }
-    for (int a = 0; a < 3; ++a) q[a] = a < D ? 0.5 * wave_sum(qq[a]) : 0.0;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) S[j] = wave_sum(acc[j]);
 }
 
 template <int D, typename TS, typename DR>
@@ -454,42 +481,19 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
 #pragma unroll
         for (int j = 0; j < PW; ++j) S[j] = __shfl(acc, j, 64);
         const double *cp = d.cellp + (size_t)c * kCellWords;
-        double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
+        const double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
         const double rho_old = cp[CW_RHO], T_old = cp[CW_T];
-        double m0 = S[0], m1[3] = {0, 0, 0}, m3[3] = {0, 0, 0}, M[3][3] = {};
-        for (int a = 0; a < D; ++a) {
-            m1[a] = S[1 + a];
-            m3[a] = S[2 + D + a];
-        }
-        double m2 = S[1 + D];
-        int o = 2 + 2 * D;
-        for (int a = 0; a < D; ++a)
-            for (int b = a; b < D; ++b) {
-                M[a][b] = M[b][a] = S[o];
-                ++o;
-            }
-        double del[3] = {0, 0, 0}, U[3] = {0, 0, 0}, mm = 0.0, dd = 0.0;
-        for (int a = 0; a < D; ++a) {
-            del[a] = m1[a] / m0;
-            U[a] = Uref[a] + del[a];
-            mm += m1[a] * m1[a];
-            dd += del[a] * del[a];
-        }
-        double T = (2.0 / 3.0) * (m2 - mm / m0) / m0;
-        double q[3] = {0, 0, 0};
-        for (int a = 0; a < D; ++a) {
-            double Md = 0.0;
-            for (int b = 0; b < D; ++b) Md += M[a][b] * del[b];
-            q[a] = 0.5 * (m3[a] - 2.0 * Md - del[a] * m2 + 2.0 * dd * m1[a]);
-        }
+        double m0, U[3], T, q[3];
+        moments_from_sums<D>(S, Uref, m0, U, T, q);
         // semi-implicit collision: the new heat flux in closed form, then
-        // the backward-Euler relaxation of the cell's transported state,
-        // which returns the relaxed state's moments
-        const bool imp = d.flags & kFlagImplicit;
-        if (imp) {
+        // the backward-Euler relaxation of the cell's transported state and
+        // the relaxed state's moments
+        if (d.flags & kFlagImplicit) {
             const double r = d.ctrl->dt * (0.5 * m0 * T) / (d.mu0 * pow(T, d.omega));
             for (int a = 0; a < D; ++a) q[a] /= 1.0 + d.Pr * r;
-            relax_cell<D, TS>(d, cur, c, m0, U, T, q, r);
+            const double Us[3] = {U[0], U[1], U[2]};
+            relax_cell<D, TS>(d, cur, c, m0, Us, T, q, r, S);
+            moments_from_sums<D>(S, Us, m0, U, T, q);
         }
         const double Wo[kResVars] = {rho_old, rho_old * Uref[0], rho_old * Uref[1], rho_old * Uref[2],
                                      rho_old * (0.5 * (Uref[0] * Uref[0] + Uref[1] * Uref[1] + Uref[2] * Uref[2]) +
