@@ -40,6 +40,9 @@
 
 #define OR_RULE_MIDPOINT 0
 #define OR_RULE_TRAPEZOID 1
+/* stretched tensor grid (reading R31): the midpoint grid of u in [-1, 1]
+ * mapped by x(u) = V sinh(beta u) / sinh(beta), finer near xi = 0 */
+#define OR_RULE_STRETCHED 2
 
 #define OR_FLAG_NO_CUTCELL 1u
 #define OR_FLAG_NO_UPWIND 2u
@@ -71,6 +74,7 @@ typedef struct {
     double Kn, Ma, Pr, gam, alpha, Tw, cfl, omega, avhs;
     int flags;
     double lid_u; /* OR_WALLS: velocity of the wall at y = hi, along x */
+    double vstretch; /* OR_RULE_STRETCHED: beta */
 } or_case;
 
 typedef struct {
@@ -89,6 +93,7 @@ typedef struct {
     int D, Nc, NV, NA;
     double dx[3];
     double *xi1[3], *w1[3];
+    double *ed0[3], *ed1[3]; /* dual cell [ed0, ed1] of each node per axis */
     double dxi[3];
     double *xi;   /* [NV*3] */
     double *w;    /* [NV] */
@@ -255,16 +260,41 @@ static void normal(const or_state *s, const double x[3], double nrm[3])
 /* velocity space (Section 2.2 quadrature; midpoint rule of 3.2.3)     */
 /* ------------------------------------------------------------------ */
 
-static void velocity_axis(int N, double lo, double hi, int rule, double *x, double *w, double *d)
+/* stretched map of reading R31 at u = m / N (m an integer in [-N, N], so
+ * that -m gives exactly the negated value) */
+static double stretch_map(double V, double beta, int m, int N)
 {
+    return V * sinh(beta * ((double)m / (double)N)) / sinh(beta);
+}
+
+/* nodes, weights and dual cells [e0, e1] of one axis */
+static void velocity_axis(int N, double lo, double hi, int rule, double beta, double *x, double *w, double *e0,
+                          double *e1, double *d)
+{
+    if (rule == OR_RULE_STRETCHED) {
+        /* node i at u = (2i + 1 - N)/N, its dual cell between the images of
+         * u = (2i - N)/N and (2i + 2 - N)/N; the weight is the cell width */
+        const double V = hi;
+        for (int i = 0; i < N; ++i) {
+            x[i] = stretch_map(V, beta, 2 * i + 1 - N, N);
+            e0[i] = stretch_map(V, beta, 2 * i - N, N);
+            e1[i] = stretch_map(V, beta, 2 * i + 2 - N, N);
+            w[i] = e1[i] - e0[i];
+        }
+        *d = 0.0;
+        return;
+    }
     /* nodes c + (i - (N-1)/2) h about the box centre c: the same uniform
      * nodes as lo + i h (trapezoid) or lo + (i + 1/2) h (midpoint), written
-     * so that a symmetric box gives exactly antisymmetric nodes */
+     * so that a symmetric box gives exactly antisymmetric nodes; dual cells
+     * x +- h/2 clipped to the box */
     double h = (rule == OR_RULE_TRAPEZOID) ? (hi - lo) / (double)(N - 1) : (hi - lo) / (double)N;
     double c = 0.5 * (lo + hi);
     for (int i = 0; i < N; ++i) {
         x[i] = c + ((double)i - 0.5 * (double)(N - 1)) * h;
         w[i] = (rule == OR_RULE_TRAPEZOID && (i == 0 || i == N - 1)) ? 0.5 * h : h;
+        e0[i] = x[i] - 0.5 * h < lo ? lo : x[i] - 0.5 * h;
+        e1[i] = x[i] + 0.5 * h > hi ? hi : x[i] + 0.5 * h;
     }
     *d = h;
 }
@@ -272,12 +302,8 @@ static void velocity_axis(int N, double lo, double hi, int rule, double *x, doub
 /* dual cell of node i on one axis, clipped to the velocity box */
 static void dual_edges(const or_state *s, int a, int i, double *e0, double *e1)
 {
-    double x = s->xi1[a][i], h = s->dxi[a];
-    double lo = x - 0.5 * h, hi = x + 0.5 * h;
-    if (lo < s->c.vlo[a]) lo = s->c.vlo[a];
-    if (hi > s->c.vhi[a]) hi = s->c.vhi[a];
-    *e0 = lo;
-    *e1 = hi;
+    *e0 = s->ed0[a][i];
+    *e1 = s->ed1[a][i];
 }
 
 /* ------------------------------------------------------------------ */
@@ -549,11 +575,17 @@ void *or_create(const or_case *cs, int *err)
         s->c.n[2] = 1;
         s->c.vn[2] = 1;
     }
+    if (cs->vrule == OR_RULE_STRETCHED)
+        for (int a = 0; a < D; ++a)
+            if (!(cs->vstretch > 0.0) || cs->vlo[a] != -cs->vhi[a]) *err = 1;
     /* velocity grid */
     for (int a = 0; a < D; ++a) {
         s->xi1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
         s->w1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
-        velocity_axis(cs->vn[a], cs->vlo[a], cs->vhi[a], cs->vrule, s->xi1[a], s->w1[a], &s->dxi[a]);
+        s->ed0[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
+        s->ed1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
+        velocity_axis(cs->vn[a], cs->vlo[a], cs->vhi[a], cs->vrule, cs->vstretch, s->xi1[a], s->w1[a], s->ed0[a],
+                      s->ed1[a], &s->dxi[a]);
         s->maxabs[a] = 0.0;
         for (int i = 0; i < cs->vn[a]; ++i)
             if (fabs(s->xi1[a][i]) > s->maxabs[a]) s->maxabs[a] = fabs(s->xi1[a][i]);
@@ -699,6 +731,8 @@ void or_destroy(void *h)
     for (int a = 0; a < 3; ++a) {
         free(s->xi1[a]);
         free(s->w1[a]);
+        free(s->ed0[a]);
+        free(s->ed1[a]);
     }
     free(s->xi);
     free(s->w);

@@ -17,7 +17,7 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
-RULE = {"midpoint": 0, "trapezoid": 1}
+RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2}
 FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4}
 
 CL_GAS, CL_SOLID, CL_CUT_G, CL_CUT_S = 0, 1, 2, 3
@@ -40,7 +40,8 @@ class _Case(ctypes.Structure):
                 ("aoa", ctypes.c_double), ("Kn", ctypes.c_double), ("Ma", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("gam", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("Tw", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
-                ("avhs", ctypes.c_double), ("flags", ctypes.c_int), ("lid_u", ctypes.c_double)]
+                ("avhs", ctypes.c_double), ("flags", ctypes.c_int), ("lid_u", ctypes.c_double),
+                ("vstretch", ctypes.c_double)]
 
 
 _lib = None
@@ -123,6 +124,7 @@ def _case_struct(case):
         fl |= FLAGS[f]
     c.flags = fl
     c.lid_u = case.get("lid_u", 0.0)
+    c.vstretch = case.get("vstretch", 0.0)
     return c
 
 

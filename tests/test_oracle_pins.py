@@ -198,16 +198,19 @@ def test_wall_specular_limit(oracle_mod):
 
 
 # ---------------------------------------------------------------- P4 cut measures
-@pytest.mark.parametrize("dim", [2, 3])
-def test_cut_measures_half_box(oracle_mod, dim):
+@pytest.mark.parametrize("dim,rule", [(2, "midpoint"), (3, "midpoint"), (2, "stretched"), (3, "stretched")])
+def test_cut_measures_half_box(oracle_mod, dim, rule):
     """A plane through the origin halves a centrally symmetric velocity box:
     the incident measures (gas cells plus omega^g of cut cells) sum to half the
-    box, and 0 <= omega^g <= omega (Section 3.2.3)."""
+    box, and 0 <= omega^g <= omega (Section 3.2.3).  On the stretched grid
+    (R31) this holds only if the dual cells tile the box and each weight is
+    its cell's measure."""
+    st = dict(rule=rule, vstretch=1.7) if rule == "stretched" else {}
     if dim == 2:
-        c = _box2(N=17, V=5.0)
+        c = _box2(N=17, V=5.0, **st)
     else:
         c = dict(dim=3, n=(4, 4, 4), lo=(0, 0, 0), hi=(1, 1, 1), vn=(9, 9, 9), vlo=(-3, -3, -3),
-                 vhi=(3, 3, 3), Kn=0.1, Ma=0.0)
+                 vhi=(3, 3, 3), Kn=0.1, Ma=0.0, **st)
     o = _orc(oracle_mod, **c)
     _, w = o.velocity()
     rng = np.random.default_rng(3)
@@ -786,3 +789,36 @@ def test_implicit_collisionless_equals_explicit(oracle_mod):
         states.append(o.get_state())
     for a, z in zip(*states):
         assert np.max(np.abs(a - z)) <= 1e-13 * np.max(a)
+
+
+# ---------------------------------------------------------------- P17 stretched velocity grid (R31)
+def test_stretched_grid_nodes_and_weights(oracle_mod):
+    """Stretched tensor grid (R31): nodes strictly increasing and exactly
+    antisymmetric, weights integrating 1 over the box, and the spacing at the
+    centre finer than at the edges by the ratio of the map's slopes at the
+    two nodes, cosh(beta (N - 1)/N) / cosh(beta / N) (to O(1/N^2))."""
+    beta, N, V = 1.5, 64, 6.0
+    o = _orc(oracle_mod, **_box2(N=N, V=V, rule="stretched", vstretch=beta))
+    xi, w = o.velocity()
+    x = xi[:N, 0]
+    assert np.all(np.diff(x) > 0)
+    assert np.array_equal(x, -x[::-1])
+    assert abs(w.sum() - (2 * V) ** 2) < 1e-12 * (2 * V) ** 2
+    wx = w[:N] / w[:N].sum() * 2 * V  # the per-axis weights (w is their tensor product)
+    ratio = wx[0] / wx[N // 2]
+    expect = np.cosh(beta * (N - 1) / N) / np.cosh(beta / N)
+    assert abs(ratio - expect) < 1e-3 * expect
+    assert abs(x[-1] - V * np.sinh(beta * (N - 1) / N) / np.sinh(beta)) < 1e-13 * V
+
+
+def test_stretched_grid_second_order(oracle_mod):
+    """The stretched rule is a second-order quadrature: the moments of a
+    drifting Maxwellian converge like N^-2 (error ratio about 4 per doubling)
+    to (rho, U, T) and zero heat flux."""
+    errs = []
+    for N in (12, 24, 48):
+        o = _orc(oracle_mod, **_box2(N=N, V=7.0, rule="stretched", vstretch=1.2))
+        m = o.cell_moments(*o.maxwellian(1.2, (0.4, -0.25), 1.1))
+        errs.append(max(abs(m[0] - 1.2), abs(m[1] - 0.4), abs(m[2] + 0.25), abs(m[4] - 1.1)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
