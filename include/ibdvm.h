@@ -63,7 +63,7 @@ typedef enum {
  * the wall model of Section 2.3 applied at the domain faces, with the wall
  * density from zero normal mass flux through each boundary face */
 enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1, IBDVM_OUTER_WALLS = 2 };
-enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1 };
+enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1, IBDVM_RULE_STRETCHED = 2 };
 enum {
     IBDVM_GEOM_NONE = 0,
     IBDVM_GEOM_CIRCLE = 1,  /* 2D, size[0] = radius */
@@ -97,12 +97,17 @@ typedef struct {
 
 /* tensor velocity grid (Section 2.2 quadrature): midpoint nodes at
  * lo + (i + 1/2) h with h = (hi - lo)/N, or trapezoid nodes lo + i h with
- * h = (hi - lo)/(N - 1) and half weights at the ends; 2 to 256 nodes per
- * axis; the box must be symmetric about 0 */
+ * h = (hi - lo)/(N - 1) and half weights at the ends, or stretched nodes
+ * (a tensor form of the locally refined velocity mesh of Section 4): the
+ * midpoint grid of u in [-1, 1] mapped by x(u) = hi sinh(stretch u) /
+ * sinh(stretch), finer near 0, each node's dual cell the image of its
+ * u-cell and its weight that cell's width; 2 to 256 nodes per axis; the box
+ * must be symmetric about 0 */
 typedef struct {
     int32_t n[3];
     double lo[3], hi[3];
     int32_t rule;
+    double stretch; /* IBDVM_RULE_STRETCHED: beta in (0, 20]; else ignored */
 } ibdvm_vgrid;
 
 typedef struct {

@@ -227,18 +227,38 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
         g.dx[a] = (p.hi[a] - p.lo[a]) / (double)p.n[a];
     }
     // velocity nodes about the box centre (exactly antisymmetric for a
-    // symmetric box) with midpoint or trapezoid weights
+    // symmetric box) with midpoint or trapezoid weights and dual cells
+    // x +- h/2 clipped to the box; or the stretched grid: the image under
+    // x(u) = V sinh(beta u)/sinh(beta) of the midpoint grid of u in [-1, 1]
+    // and of its cells, u = m/N with an integer m so that nodes and cell
+    // faces are exactly antisymmetric
     for (int a = 0; a < D; ++a) {
         int N = p.vn[a];
+        g.xa[a].resize(N);
+        g.wa[a].resize(N);
+        g.ea0[a].resize(N);
+        g.ea1[a].resize(N);
+        if (p.rule == 2) {
+            const double V = p.vhi[a], beta = p.vstretch;
+            auto map = [&](int m) { return V * std::sinh(beta * ((double)m / (double)N)) / std::sinh(beta); };
+            g.dxi[a] = 0.0;
+            for (int i = 0; i < N; ++i) {
+                g.xa[a][i] = map(2 * i + 1 - N);
+                g.ea0[a][i] = map(2 * i - N);
+                g.ea1[a][i] = map(2 * i + 2 - N);
+                g.wa[a][i] = g.ea1[a][i] - g.ea0[a][i];
+            }
+            continue;
+        }
         bool trap = p.rule == 1;
         double h = trap ? (p.vhi[a] - p.vlo[a]) / (double)(N - 1) : (p.vhi[a] - p.vlo[a]) / (double)N;
         double c = 0.5 * (p.vlo[a] + p.vhi[a]);
         g.dxi[a] = h;
-        g.xa[a].resize(N);
-        g.wa[a].resize(N);
         for (int i = 0; i < N; ++i) {
             g.xa[a][i] = c + ((double)i - 0.5 * (double)(N - 1)) * h;
             g.wa[a][i] = (trap && (i == 0 || i == N - 1)) ? 0.5 * h : h;
+            g.ea0[a][i] = std::max(p.vlo[a], g.xa[a][i] - 0.5 * h);
+            g.ea1[a][i] = std::min(p.vhi[a], g.xa[a][i] + 0.5 * h);
         }
     }
     g.xi.assign((size_t)3 * g.NV, 0.0);
@@ -392,9 +412,8 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
             }
             double e0[3] = {0, 0, 0}, e1[3] = {0, 0, 0};
             for (int a = 0; a < D; ++a) {
-                double x = g.xa[a][id[a]], h = g.dxi[a];
-                e0[a] = std::max(p.vlo[a], x - 0.5 * h);
-                e1[a] = std::min(p.vhi[a], x + 0.5 * h);
+                e0[a] = g.ea0[a][id[a]];
+                e1[a] = g.ea1[a][id[a]];
             }
             double dmin = INFINITY, dmax = -INFINITY, vmax = 0.0;
             for (int corner = 0; corner < (1 << D); ++corner) {

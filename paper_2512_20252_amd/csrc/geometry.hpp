@@ -24,6 +24,7 @@ struct Problem {
     int vn[3] = {1, 1, 1};
     double vlo[3] = {0, 0, 0}, vhi[3] = {0, 0, 0};
     int rule = 0;
+    double vstretch = 0;
     int gkind = 0;
     double gcen[3] = {0, 0, 0}, gsize[3] = {0, 0, 0}, aoa = 0;
     uint32_t flags = 0;
@@ -41,6 +42,7 @@ struct Geometry {
     int D = 2, Nc = 0, NV = 0, nfluid = 0, nghost = 0;
     double dx[3] = {1, 1, 1};
     std::vector<double> xa[3], wa[3];  // per-axis velocity nodes and weights
+    std::vector<double> ea0[3], ea1[3];  // per-axis dual cell [ea0, ea1] of each node
     double dxi[3] = {1, 1, 1};
     std::vector<double> xi;  // [NV*3]
     std::vector<double> w;   // [NV]

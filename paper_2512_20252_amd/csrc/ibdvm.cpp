@@ -121,8 +121,12 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
         return fail(IBDVM_E_INVALID_ARG, "lid speed must be finite");
     p.outer = grid->outer_bc;
     p.lid_u = grid->outer_bc == IBDVM_OUTER_WALLS ? grid->lid_u : 0.0;
-    if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID) return fail(IBDVM_E_INVALID_ARG, "unknown quadrature rule");
+    if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID && vg->rule != IBDVM_RULE_STRETCHED)
+        return fail(IBDVM_E_INVALID_ARG, "unknown quadrature rule");
+    if (vg->rule == IBDVM_RULE_STRETCHED && !(vg->stretch > 0.0 && vg->stretch <= 20.0))
+        return fail(IBDVM_E_INVALID_ARG, "stretch must be in (0, 20]");
     p.rule = vg->rule;
+    p.vstretch = vg->rule == IBDVM_RULE_STRETCHED ? vg->stretch : 0.0;
     int k = geom->kind;
     bool ok2 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_CIRCLE || k == IBDVM_GEOM_ELLIPSE || k == IBDVM_GEOM_AIRFOIL;
     bool ok3 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_SPHERE;

@@ -178,8 +178,17 @@ __device__ double vel_interp(const DR &d, const double *g, const double v[3], in
         const double *x = d.xa + a * kMaxVn;
         int N = d.vn[a];
         if (v[a] < x[0] || v[a] > x[N - 1]) return 0.0;
-        int i = (int)floor((v[a] - x[0]) / (x[1] - x[0]));
-        i = i < 0 ? 0 : (i > N - 2 ? N - 2 : i);
+        // interval [x_i, x_i+1] holding v: i = the number of interior nodes
+        // x_1 .. x_N-2 below v (binary search; the nodes need not be uniform)
+        int lo = 1, hi = N - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (x[mid] < v[a])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int i = lo - 1;
         i0[a] = i;
         t[a] = (v[a] - x[i]) / (x[i + 1] - x[i]);
     }

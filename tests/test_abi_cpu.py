@@ -43,6 +43,9 @@ GEOMS = {
                                   Kn=0.08, Ma=0.9),
     "ragged": lambda: cases.case(dim=2, n=(24, 20), lo=(-1.2, -1.0), hi=(1.2, 1.0), vn=(13, 11), vlo=(-4.5, -4.0),
                                  vhi=(4.5, 4.0), geometry="circle", size=(0.41, 0.0, 0.0), Kn=0.2, Ma=0.7),
+    # stretched velocity grids (non-uniform dual cells in the cut-cell sets)
+    "stretched_2d": lambda: dict(cases.cylinder_small(), rule="stretched", vstretch=1.5, vn=(17, 14)),
+    "stretched_3d": lambda: dict(cases.sphere(n=28, vn=9), rule="stretched", vstretch=1.1),
 }
 
 
@@ -90,6 +93,8 @@ def test_argument_validation():
     _expect(ibdvm.E_INVALID_ARG, mk(n=(3, 32)))
     _expect(ibdvm.E_INVALID_ARG, mk(cfl=1.5))
     _expect(ibdvm.E_INVALID_ARG, mk(vn=(257, 16)))
+    _expect(ibdvm.E_INVALID_ARG, mk(rule="stretched", vstretch=0.0))
+    _expect(ibdvm.E_INVALID_ARG, mk(rule="stretched", vstretch=25.0))
     ibdvm.Solver(dict(base, vn=(256, 4)), host_only=True)
     _expect(ibdvm.E_INVALID_ARG, mk(geometry="sphere"))
     _expect(ibdvm.E_GEOMETRY, mk(size=(0.9, 0.0, 0.0)))
