@@ -226,6 +226,65 @@ def implicit_collision(Kn, steps, warmup):
     return out
 
 
+def _steady(case, t_end, tag, block=1000):
+    """Run a solve from its freestream (rest for Ma 0) to time t_end in
+    replays of a captured graph of `block` steps; moments, wall points,
+    step count, last residual and wall time."""
+    import torch
+    from paper_2512_20252_amd import ibdvm
+
+    s = ibdvm.Solver(case, stream=torch.cuda.Stream())
+    s.init_freestream()
+    g = ibdvm.Graph(s, block)
+    t0, k = time.perf_counter(), 0
+    while s.clock()["time"] < t_end:
+        g.launch()
+        k += 1
+        if k % 20 == 0:
+            print(f"{tag}: t = {s.clock()['time']:.1f}", file=sys.stderr, flush=True)
+    s.step(2)
+    r = {"m": s.moments(), "wall": s.surface_forces(), "steps": s.clock()["step"],
+         "residual": s.residual()[1], "seconds": time.perf_counter() - t0}
+    print(f"{tag}: {r['steps']} steps in {r['seconds']:.1f} s", file=sys.stderr, flush=True)
+    g.close()
+    s.close()
+    torch.cuda.empty_cache()
+    return r
+
+
+def _l1(a, b):
+    import numpy as np
+    return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
+
+
+def vmesh_study(levels, nref, t_end, beta):
+    """Velocity-mesh efficiency: the 32^2 cylinder (Ma 0.5, Kn 0.1) at steady
+    state (t = t_end) on uniform midpoint and stretched (R31, beta) velocity
+    grids of levels^2 nodes on [-5,5]^2, against a uniform nref^2 reference:
+    relative errors of C_D and L1 errors of p_w, tau_w and q_n over the wall
+    points.  Same N means the same cost per step."""
+    import numpy as np
+    from paper_2512_20252_amd import cases
+
+    base = dict(cases.cylinder_small(), rule="midpoint")
+    ref = _steady(cases.case(**dict(base, vn=(nref, nref))), t_end, f"vmesh reference {nref}^2")
+    cd_ref, W = ref["wall"][1], ref["wall"][3]
+    out = {"workload": f"2D cylinder 32^2 cells (R=0.3, Ma 0.5, Kn 0.1), velocity grids "
+                       f"{'/'.join(str(v) for v in levels)} squared on [-5,5]^2, uniform midpoint and stretched "
+                       f"(beta {beta}), against uniform {nref}^2, steady state (t = {t_end})",
+           "reference": {"CD": cd_ref, "steps": ref["steps"], "residual": ref["residual"]}}
+    for tag, extra in (("uniform", {}), ("stretched", {"rule": "stretched", "vstretch": beta})):
+        errs = {}
+        for vn in levels:
+            r = _steady(cases.case(**dict(base, vn=(vn, vn), **extra)), t_end, f"vmesh {tag} {vn}^2")
+            w = r["wall"][3]
+            errs[str(vn)] = {"CD": abs(r["wall"][1] - cd_ref) / abs(cd_ref), "p_w": _l1(w[:, 7], W[:, 7]),
+                             "tau_w": _l1(w[:, 8:10], W[:, 8:10]), "q_n": _l1(w[:, 11], W[:, 11]),
+                             "steps": r["steps"]}
+        out[tag] = errs
+    return out
+
+
 def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     """Velocity-space convergence of the lid-driven cavity at steady state
     (the study of Section 4): the cavity on n^2 cells with velocity meshes
@@ -236,33 +295,15 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     over the wall points; observed orders are least-squares slopes of
     log error against log N."""
     import numpy as np
-    import torch
-    from paper_2512_20252_amd import cases, ibdvm
+    from paper_2512_20252_amd import cases
 
     def steady(vn, flags):
-        c = cases.case(**dict(cases.cavity(n=n, vn=vn), flags=flags))
-        s = ibdvm.Solver(c, stream=torch.cuda.Stream())
-        s.init_freestream()
-        g = ibdvm.Graph(s, block)
-        t0, k = time.perf_counter(), 0
-        while s.clock()["time"] < t_end:
-            g.launch()
-            k += 1
-            if k % 20 == 0:
-                print(f"cavity study: {vn}^2 nodes, t = {s.clock()['time']:.1f}", file=sys.stderr, flush=True)
-        s.step(2)
-        r = {"m": s.moments(), "wall": s.surface_forces()[3], "steps": s.clock()["step"],
-             "residual": s.residual()[1], "seconds": time.perf_counter() - t0}
-        print(f"cavity study: {vn}^2 nodes {flags or ''} {r['steps']} steps in {r['seconds']:.1f} s",
-              file=sys.stderr, flush=True)
-        g.close()
-        s.close()
-        torch.cuda.empty_cache()
+        r = _steady(cases.case(**dict(cases.cavity(n=n, vn=vn), flags=flags)), t_end,
+                    f"cavity study {vn}^2 {'/'.join(flags)}", block)
+        r["wall"] = r["wall"][3]
         return r
 
-    def l1(a, b):
-        return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
-
+    l1 = _l1
     ref = steady(nref, ())
     ok = np.isfinite(ref["m"][:, 0])
     M, W = ref["m"][ok], ref["wall"]
@@ -358,6 +399,8 @@ def main():
     ap.add_argument("--cavity-steps", type=int, default=20)
     ap.add_argument("--implicit-kn", type=float, default=2e-4,
                     help="Knudsen number of the semi-implicit collision leg (0: skip)")
+    ap.add_argument("--vmesh-study", action="store_true",
+                    help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
     ap.add_argument("--cavity-study", action="store_true",
                     help="add the cavity's velocity-space convergence study (about 4 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -437,6 +480,8 @@ def main():
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
     if args.implicit_kn > 0:
         line["implicit_collision"] = implicit_collision(args.implicit_kn, 50, 3)
+    if args.vmesh_study:
+        line["vmesh_study"] = vmesh_study([8, 12, 16, 24, 32], 128, 30.0, 1.5)
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:
