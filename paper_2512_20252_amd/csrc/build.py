@@ -32,10 +32,23 @@ def _run(cmd, verbose):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
     k_obj = os.path.join(BUILD, "kernels.o")
-    _run([HIPCC] + HIP_FLAGS + INCLUDES + ["-c", os.path.join(HERE, "kernels.hip"), "-o", k_obj], verbose)
-    objs.append(k_obj)
+    # the FP64 2D update in its own unit, scheduled for instruction-level
+    # parallelism (about 6 % faster there, slower for the other kernels)
+    k64_obj = os.path.join(BUILD, "kernels_update2d_f64.o")
+    jobs = [[HIPCC] + HIP_FLAGS + INCLUDES + ["-c", os.path.join(HERE, "kernels.hip"), "-o", k_obj],
+            [HIPCC] + HIP_FLAGS + INCLUDES + ["-DIBDVM_FP64_UPDATE2D_UNIT", "-mllvm", "-amdgpu-sched-strategy=max-ilp",
+                                              "-c", os.path.join(HERE, "kernels.hip"), "-o", k64_obj]]
+    procs = []
+    for cmd in jobs:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+    codes = [p.wait() for p in procs]
+    for cmd, code in zip(jobs, codes):
+        if code:
+            raise subprocess.CalledProcessError(code, cmd)
+    objs = [k_obj, k64_obj]
     for src in ("geometry.cpp", "ibdvm.cpp", "server.cpp"):
         o = os.path.join(BUILD, src.replace(".cpp", ".o"))
         _run(["g++"] + HOST_FLAGS + INCLUDES + ["-c", os.path.join(HERE, src), "-o", o], verbose)

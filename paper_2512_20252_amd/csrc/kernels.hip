@@ -1934,6 +1934,8 @@ __global__ void k_moments_out(Dev d, double *out)
 
 }  // namespace
 
+#ifndef IBDVM_FP64_UPDATE2D_UNIT
+
 // ---------------------------------------------------------------- launchers
 #define DISPATCH(D_, S_, ...)                                      \
     do {                                                           \
@@ -1972,19 +1974,16 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     long long nblk = (long long)ntx * nys * ncv;
     nblk = (nblk + 7) / 8 * 8;
     dim3 grid((unsigned)nblk), block(64 * t.TX);
-#define U2D(TT, VV, XX)                                                                                              \
-    if (t.V == VV && t.TX == XX) {                                                                                \
-        if (d.outer == 2)                                                                                         \
-            hipLaunchKernelGGL((k_update2d<TT, VV, XX, true>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv);  \
-        else                                                                                                      \
-            hipLaunchKernelGGL((k_update2d<TT, VV, XX, false>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv); \
-        return hipGetLastError();                                                                                 \
+    if (storage == 0) return launch_update2d_f64(d, t.V, t.TX, cur, slot, t.LY, ntx, nys, ncv, grid, block, s);
+#define U2D(VV, XX)                                                                                                   \
+    if (t.V == VV && t.TX == XX) {                                                                                 \
+        if (d.outer == 2)                                                                                          \
+            hipLaunchKernelGGL((k_update2d<float, VV, XX, true>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_update2d<float, VV, XX, false>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv); \
+        return hipGetLastError();                                                                                  \
     }
-    if (storage == 0) {
-        U2D(double, 1, 4) U2D(double, 1, 8) U2D(double, 2, 4) U2D(double, 2, 8)
-    } else {
-        U2D(float, 1, 4) U2D(float, 1, 8) U2D(float, 2, 4) U2D(float, 2, 8)
-    }
+    U2D(1, 4) U2D(1, 8) U2D(2, 4) U2D(2, 8)
 #undef U2D
     return hipErrorInvalidValue;
 }
@@ -1996,19 +1995,16 @@ hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const B
     nblk = (nblk + 7) / 8 * 8;
     if (nblk >= (1ll << 31)) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblk), block(64 * TX);
-#define U2B(TT, VV, XX)                                                                       \
+    if (storage == 0) return launch_update2d_batch_f64(V, TX, walls, a, grid, block, s);
+#define U2B(VV, XX)                                                                           \
     if (V == VV && TX == XX) {                                                             \
         if (walls)                                                                         \
-            hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX, true>), grid, block, 0, s, a);  \
+            hipLaunchKernelGGL((k_update2d_batch<float, VV, XX, true>), grid, block, 0, s, a);  \
         else                                                                               \
-            hipLaunchKernelGGL((k_update2d_batch<TT, VV, XX, false>), grid, block, 0, s, a); \
+            hipLaunchKernelGGL((k_update2d_batch<float, VV, XX, false>), grid, block, 0, s, a); \
         return hipGetLastError();                                                          \
     }
-    if (storage == 0) {
-        U2B(double, 1, 4) U2B(double, 1, 8) U2B(double, 2, 4) U2B(double, 2, 8)
-    } else {
-        U2B(float, 1, 4) U2B(float, 1, 8) U2B(float, 2, 4) U2B(float, 2, 8)
-    }
+    U2B(1, 4) U2B(1, 8) U2B(2, 4) U2B(2, 8)
 #undef U2B
     return hipErrorInvalidValue;
 }
@@ -2158,5 +2154,44 @@ hipError_t launch_moments_out(const Dev &d, double *out, hipStream_t s)
     hipLaunchKernelGGL(k_moments_out, dim3(blocks_for(d.Nc, 256)), dim3(256), 0, s, d, out);
     return hipGetLastError();
 }
+
+#else
+
+// The FP64 2D update is compiled in a translation unit of its own
+// (IBDVM_FP64_UPDATE2D_UNIT) with the instruction scheduler set to maximise
+// instruction-level parallelism, which it gains from and the other kernels
+// lose from; that unit defines only these two launchers.
+hipError_t launch_update2d_f64(const Dev &d, int V, int TX, int cur, int slot, int LY, int ntx, int nys, int ncv,
+                               dim3 grid, dim3 block, hipStream_t s)
+{
+#define U2D(VV, XX)                                                                                                    \
+    if (V == VV && TX == XX) {                                                                                      \
+        if (d.outer == 2)                                                                                           \
+            hipLaunchKernelGGL((k_update2d<double, VV, XX, true>), grid, block, 0, s, d, cur, slot, LY, ntx, nys, ncv);  \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_update2d<double, VV, XX, false>), grid, block, 0, s, d, cur, slot, LY, ntx, nys, ncv); \
+        return hipGetLastError();                                                                                   \
+    }
+    U2D(1, 4) U2D(1, 8) U2D(2, 4) U2D(2, 8)
+#undef U2D
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_update2d_batch_f64(int V, int TX, bool walls, const BatchArgs &a, dim3 grid, dim3 block, hipStream_t s)
+{
+#define U2B(VV, XX)                                                                            \
+    if (V == VV && TX == XX) {                                                              \
+        if (walls)                                                                          \
+            hipLaunchKernelGGL((k_update2d_batch<double, VV, XX, true>), grid, block, 0, s, a);  \
+        else                                                                                \
+            hipLaunchKernelGGL((k_update2d_batch<double, VV, XX, false>), grid, block, 0, s, a); \
+        return hipGetLastError();                                                           \
+    }
+    U2B(1, 4) U2B(1, 8) U2B(2, 4) U2B(2, 8)
+#undef U2B
+    return hipErrorInvalidValue;
+}
+
+#endif
 
 }  // namespace ibdvm

@@ -21,6 +21,10 @@ hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const T
 hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const BatchArgs &a, hipStream_t s);
 hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
                              hipStream_t s);
+// the FP64 forms of the two above, defined in their own translation unit
+hipError_t launch_update2d_f64(const Dev &d, int V, int TX, int cur, int slot, int LY, int ntx, int nys, int ncv,
+                               dim3 grid, dim3 block, hipStream_t s);
+hipError_t launch_update2d_batch_f64(int V, int TX, bool walls, const BatchArgs &a, dim3 grid, dim3 block, hipStream_t s);
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s);
 // ghost rows of the diffuse outer walls from buffer cur (no-op unless the
 // outer boundary is walls)
