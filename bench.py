@@ -355,13 +355,17 @@ def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
     free, _ = torch.cuda.mem_get_info()
     ws = int(max(max(fps) + (1 << 20), min(sum(fps) + (1 << 20), 0.8 * free)))
     srv = ibdvm.Server(ws, max_active=max_active, steps_per_replay=100)
-    t0, sub, done, samples = srv.clock(), 0, [], []
+    t0, sub, done, samples, index = srv.clock(), 0, [], [], {}
     while len(done) < nreq:
         now = srv.clock() - t0
         while sub < nreq and arrivals[sub] <= now:
-            srv.submit(reqs[sub], "f32", seed=sub, amp=1e-3, tol=tol, max_steps=cap)
+            index[srv.submit(reqs[sub], "f32", seed=sub, amp=1e-3, tol=tol, max_steps=cap)] = sub
             sub += 1
-        done += srv.poll(block=False)
+        new = srv.poll(block=False)
+        for r in new:
+            print(f"serving: request {r['id']} finished after {r['steps']} steps "
+                  f"({len(done) + 1}/{nreq})", file=sys.stderr, flush=True)
+            done.append(r)
         samples.append(srv.info()["active"])
         time.sleep(0.002)
     srv.close()
@@ -375,7 +379,10 @@ def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
             "p50_time_to_converged_s": pct(lat[conv], 50), "p99_time_to_converged_s": pct(lat[conv], 99),
             "p50_time_to_done_s": pct(lat, 50), "p99_time_to_done_s": pct(lat, 99),
             "mean_active": float(np.mean(samples)), "aggregate_updates_per_s": ups,
-            "steps": [int(r["steps"]) for r in done]}
+            "steps": [int(r["steps"]) for r in done],
+            "failures": [{"request": index[r["id"]], "status": int(r["status"]), "steps": int(r["steps"]),
+                          **{k: reqs[index[r["id"]]][k] for k in ("n", "vn", "geometry", "size", "Kn", "Ma", "alpha")}}
+                         for r in done if r["status"] != 0]}
 
 
 def main():
