@@ -397,6 +397,7 @@ def main():
     ap.add_argument("--tile32", type=str, default="", help="V,TX,LY of the FP32-storage 2D update (default: autotune)")
     ap.add_argument("--serving", type=int, default=12, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serving-cap", type=int, default=2000, help="step cap per serving request")
+    ap.add_argument("--serving-gap", type=float, default=0.5, help="mean arrival gap of the serving stream, seconds")
     ap.add_argument("--sphere", type=int, default=96, help="cells per side of the 3D sphere leg (0: skip)")
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
@@ -492,7 +493,7 @@ def main():
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:
-        line["serving"] = serving(args.serving, args.serving_cap, 1e-4, 0.5)
+        line["serving"] = serving(args.serving, args.serving_cap, 1e-4, args.serving_gap)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)
