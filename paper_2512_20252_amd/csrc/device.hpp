@@ -92,6 +92,9 @@ struct Dev {
     // [2ny, 2ny + nx) y = lo (row 2ny + i: cell (i, 0)), then y = hi
     void *wallT[2];
     double lid_u;  // speed of the wall y = hi along +x
+    // incoming normal flux sum_{xi_n < 0} w |xi_n| e^{-|xi - U_w|^2 / T_w} of
+    // each outer wall (x = lo, x = hi, y = lo, y = hi)
+    double wall_in[4];
     Ctrl *ctrl;
 };
 

@@ -601,6 +601,20 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.npairs = (int)np;
     d.outer = c->prob.outer;
     d.lid_u = c->prob.lid_u;
+    if (c->prob.outer == IBDVM_OUTER_WALLS)
+        for (int a = 0; a < 2; ++a)
+            for (int sd = 0; sd < 2; ++sd) {
+                const double Ux = (a == 1 && sd == 1) ? c->prob.lid_u : 0.0, side = sd ? 1.0 : -1.0;
+                double in = 0.0;
+                for (int k = 0; k < NV; ++k) {
+                    const double xn = side * g.xi[3 * k + a];
+                    if (xn < 0.0) {
+                        const double cx = g.xi[3 * k] - Ux, cy = g.xi[3 * k + 1];
+                        in -= g.w[k] * xn * std::exp(-(cx * cx + cy * cy) / T_w);
+                    }
+                }
+                d.wall_in[2 * a + sd] = in;
+            }
     d.flags = c->prob.flags;
     for (int a = 0; a < 3; ++a) {
         d.n[a] = c->prob.n[a];

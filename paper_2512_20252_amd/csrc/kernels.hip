@@ -1312,8 +1312,10 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
 // leaving the wall carry the wall Maxwellian at (U_wall, T_w) scaled by the
 // density that zeroes the normal mass flux through the face against the
 // cell's own h on the velocities toward the wall; those and the tangential
-// velocities keep the cell's value.  The sums run in FP64, the rows are
-// written in the storage type.
+// velocities keep the cell's value.  The incoming flux of the unit wall
+// Maxwellian depends on the wall side only and comes from the host (wall_in);
+// the outgoing flux of the cell is summed here in FP64; the rows are written
+// in the storage type.
 template <typename T>
 __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
 {
@@ -1340,19 +1342,15 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
         const double cx = d.xi[0][k] - Ux, cy = d.xi[1][k];
         return exp(-(cx * cx + cy * cy) * iTw);
     };
-    double out = 0.0, in = 0.0;
+    double out = 0.0;
     for (int k = threadIdx.x; k < NV; k += 256) {
         const double xn = sd * d.xi[a][k];
-        if (xn > 0.0)
-            out += d.w[k] * xn * (double)h[k];
-        else if (xn < 0.0)
-            in -= d.w[k] * xn * ew(k);
+        if (xn > 0.0) out += d.w[k] * xn * (double)h[k];
     }
     out = block_sum(out);
-    in = block_sum(in);
-    // in sums e^{-c^2/T_w} without the prefactor A_w, so out / in is
-    // rho_w A_w: the factor of e^{-c^2/T_w} in the ghost
-    const double rA = out / in;
+    // wall_in sums e^{-c^2/T_w} without the prefactor A_w, so out / wall_in
+    // is rho_w A_w: the factor of e^{-c^2/T_w} in the ghost
+    const double rA = out / d.wall_in[2 * a + (sd > 0 ? 1 : 0)];
     T *g0 = (T *)d.wallT[0] + (size_t)r * NV;
     T *g1 = (T *)d.wallT[1] + (size_t)r * NV;
     for (int k = threadIdx.x; k < NV; k += 256) {
