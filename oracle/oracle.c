@@ -1284,14 +1284,17 @@ void or_clock(void *h, double *out3)
 }
 
 /* body force from the momentum flux through the immersed-boundary faces
- * (reading R16) and drag/lift coefficients; wall records per pair (13
- * doubles): x_w[3], n_w[3], rho_w, p_w, tau_w[3], q_n, C_p.  With the wall
+ * (reading R16) and drag/lift coefficients; wall records per pair (17
+ * doubles): x_w[3], n_w[3], rho_w, p_w, tau_w[3], q_n, C_p, T_s, u_s[3].  With the wall
  * distribution f*_w (at rest) and n into the gas: p_w = sum w (xi.n)^2 f*_w,
  * the shear tau_w = sum w (xi.n) (xi - (xi.n) n) f*_w (the tangential part of
  * the momentum flux through the wall), the normal heat flux q_n = 1/2 sum w
  * (xi.n) (|xi|^2 h + b) (2D reduced; 3D: |xi|^2 f), and the pressure
  * coefficient of Section 4, C_p = 2 (p_w - p_0) / (rho_0 U_0^2) with the
- * freestream p_0 = rho_0 T_0 / 2 = 1/2 and U_0 the freestream speed */
+ * freestream p_0 = rho_0 T_0 / 2 = 1/2 and U_0 the freestream speed; T_s and
+ * u_s are the temperature and velocity of the gas at the wall point, the
+ * moments (Section 2.1 definitions) of f*_w, which Section 4 plots along
+ * the body surface */
 void or_forces(void *h, double *F3, double *cdcl, double *wall)
 {
     or_state *s = (or_state *)h;
@@ -1327,16 +1330,20 @@ void or_forces(void *h, double *F3, double *cdcl, double *wall)
                 const double e = x2 * fw + (s->NA == 2 ? s->fw[1][(size_t)ip * NV + k] : 0.0);
                 qn += 0.5 * s->w[k] * dn * e;
             }
-            double *wr = &wall[13 * ip];
+            double mw[8];
+            cell_moments(s, s->fw[0] + (size_t)ip * NV, s->NA == 2 ? s->fw[1] + (size_t)ip * NV : NULL, mw);
+            double *wr = &wall[17 * ip];
             for (int b = 0; b < 3; ++b) {
                 wr[b] = p->xw[b];
                 wr[3 + b] = p->nw[b];
                 wr[8 + b] = tau[b];
+                wr[14 + b] = mw[1 + b];
             }
             wr[6] = s->rhow[ip];
             wr[7] = pw;
             wr[11] = qn;
             wr[12] = s->Uinf > 0 ? 2.0 * (pw - 0.5) / (s->Uinf * s->Uinf) : NAN;
+            wr[13] = mw[4];
         }
     }
     for (int b = 0; b < 3; ++b) F3[b] = F[b];

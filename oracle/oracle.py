@@ -195,7 +195,7 @@ class Oracle:
     def forces(self):
         F = np.empty(3)
         cdcl = np.empty(2)
-        wall = np.empty((max(self.npairs, 1), 13))
+        wall = np.empty((max(self.npairs, 1), 17))
         lib().or_forces(self._h, _dp(F), _dp(cdcl), _dp(wall))
         return F, cdcl[0], cdcl[1], wall[: self.npairs]
 

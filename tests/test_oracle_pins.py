@@ -421,6 +421,29 @@ def test_rest_state_wall_diagnostics(oracle_mod):
     assert np.max(np.abs(wall[:, 11])) < 1e-13
     assert np.max(np.abs(wall[:, 7] - 0.5)) < 1e-10
     assert np.all(np.isnan(wall[:, 12]))
+    # the gas at the wall is the rest state itself: T_s = T_w, no slip
+    assert np.max(np.abs(wall[:, 13] - 1.0)) < 1e-10
+    assert np.max(np.abs(wall[:, 14:17])) < 1e-13
+
+
+def test_wall_temperature_jump_closed_form(oracle_mod):
+    """Gas at rest at T_g against a diffuse wall at T_w (Section 2.3): the
+    zero-flux wall density is rho_g sqrt(T_g / T_w) and each half-range
+    carries half its Maxwellian's energy, so the gas at the wall has
+    T_s = sqrt(T_g T_w) and no velocity, whatever the normal.  On the
+    cylinder's tilted normals the cut-cell quadrature reaches it at second
+    order in the velocity spacing."""
+    errs = []
+    for N in (24, 48):
+        c = cases.case(dim=2, n=(24, 24), lo=(-1.0, -1.0), hi=(1.0, 1.0), vn=(N, N), vlo=(-6.0, -6.0),
+                       vhi=(6.0, 6.0), geometry="circle", size=(0.3, 0.0, 0.0), Kn=0.1, Ma=0.0, Tw=2.0)
+        o = oracle_mod.Oracle(c)
+        o.init_freestream()
+        _, _, _, wall = o.forces()
+        errs.append(np.max(np.abs(wall[:, 13] - sqrt(2.0))))
+        assert np.max(np.abs(wall[:, 14:17])) < 2e-3
+    assert errs[1] < 1e-3
+    assert errs[0] / errs[1] > 3.4
 
 
 def test_residual_hand_example(oracle_mod):
