@@ -291,9 +291,9 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     levels^2, with and without the cut-cell correction, each run from rest
     to time t_end (past the point where the residual stops falling), against
     a reference on nref^2 nodes with the correction.  L1 errors relative to
-    the reference: rho, |U| and T over the fluid cells, p_w, tau_w and q_n
-    over the wall points; observed orders are least-squares slopes of
-    log error against log N."""
+    the reference: rho, |U| and T over the fluid cells, p_w, tau_w, q_n and
+    the gas temperature T_s and slip velocity u_s at the wall points;
+    observed orders are least-squares slopes of log error against log N."""
     import numpy as np
     from paper_2512_20252_amd import cases
 
@@ -319,10 +319,11 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
                         "U": float(np.sum(np.linalg.norm(m[:, 1:3] - M[:, 1:3], axis=1)) /
                                    np.sum(np.linalg.norm(M[:, 1:3], axis=1))),
                         "T": l1(m[:, 4], M[:, 4]), "p_w": l1(w[:, 7], W[:, 7]), "tau_w": l1(w[:, 8:10], W[:, 8:10]),
-                        "q_n": l1(w[:, 11], W[:, 11]), "steps": r["steps"], "residual": r["residual"]}
+                        "q_n": l1(w[:, 11], W[:, 11]), "T_s": l1(w[:, 13], W[:, 13]),
+                        "u_s": l1(w[:, 14:16], W[:, 14:16]), "steps": r["steps"], "residual": r["residual"]}
         ln = np.log(np.array(levels, float))
         orders = {q: float(-np.polyfit(ln, np.log([errs[v][q] for v in levels]), 1)[0])
-                  for q in ("rho", "U", "T", "p_w", "tau_w", "q_n")}
+                  for q in ("rho", "U", "T", "p_w", "tau_w", "q_n", "T_s", "u_s")}
         out[tag] = {"L1": {str(v): e for v, e in errs.items()}, "orders": orders}
     return out
 

@@ -135,7 +135,9 @@ typedef struct {
  * tangential part of the momentum flux), normal heat flux q_n = 1/2 sum w
  * xi_n (|xi|^2 h + b) (2D; 3D: |xi|^2 f), and the pressure coefficient of
  * Section 4, C_p = 2 (p_w - p_0) / (rho_0 U_0^2) with the freestream p_0 =
- * rho_0 T_0 / 2 = 1/2 (NaN when U_0 = 0) */
+ * rho_0 T_0 / 2 = 1/2 (NaN when U_0 = 0); the temperature T_s and velocity
+ * u_s of the gas at the wall point, the moments of f*_w (Section 2.1
+ * definitions: the surface temperature and slip velocity Section 4 plots) */
 typedef struct {
     double xw[3];
     double nw[3];
@@ -144,6 +146,8 @@ typedef struct {
     double tau_w[3];
     double q_n;
     double C_p;
+    double T_s;
+    double u_s[3];
 } ibdvm_wall_point;
 
 /* Bytes of device workspace a problem needs (state double buffer, per-cell

@@ -29,8 +29,9 @@ constexpr int kQWords = 10;
 // moment-finish workgroup the sums of squared changes, then of magnitudes
 constexpr int kResVars = 5;
 // per pair: momentum flux through the face F[3], then at the wall point p_w,
-// tau_w[3], q_n
-constexpr int kForceWords = 8;
+// tau_w[3], q_n, and the raw moments of the wall distribution: sum w f,
+// sum w xi f [3], sum w (|xi|^2 h + b) (3D: |xi|^2 f)
+constexpr int kForceWords = 13;
 
 // Dev::flags bit of the semi-implicit collision (IBDVM_FLAG_IMPLICIT_COLLISION)
 constexpr unsigned kFlagImplicit = 1u << 2;

@@ -1075,6 +1075,15 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
             pts[m].q_n = pf[KW * p + 7];
             // Section 4: C_p = 2 (p_w - p_0) / (rho_0 U_0^2), freestream p_0 = rho_0 T_0 / 2 = 1/2
             pts[m].C_p = c->Uinf > 0 ? 2.0 * (pts[m].p_w - 0.5) / (c->Uinf * c->Uinf) : NAN;
+            // gas at the wall point: rho, U from the raw moments, then
+            // T = 4 (rho E - rho |U|^2 / 2) / (3 rho) with rho E = sum w e / 2
+            const double *r = &pf[KW * p + 8];
+            double u2 = 0.0;
+            for (int b = 0; b < 3; ++b) {
+                pts[m].u_s[b] = b < c->prob.dim ? r[1 + b] / r[0] : 0.0;
+                u2 += pts[m].u_s[b] * pts[m].u_s[b];
+            }
+            pts[m].T_s = 4.0 * (0.5 * r[4] - 0.5 * r[0] * u2) / (3.0 * r[0]);
         }
     if (n_pts) *n_pts = pts ? m : (int32_t)np;
     return IBDVM_OK;

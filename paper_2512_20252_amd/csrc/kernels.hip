@@ -1823,8 +1823,9 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
     ijk[0] = dc % d.n[0];
     ijk[1] = (dc / d.n[0]) % d.n[1];
     ijk[2] = D == 3 ? dc / (d.n[0] * d.n[1]) : 0;
-    // F[3] (momentum flux through the face), p_w, tau_w[3], q_n
-    double acc[kForceWords] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // F[3] (momentum flux through the face), p_w, tau_w[3], q_n, then the
+    // raw moments of the wall distribution (density, momentum, energy)
+    double acc[kForceWords] = {};
     for (int k = threadIdx.x; k < NV; k += 256) {
         double xa = d.xi[a][k], st;
         if (side * xa > 0.0) {
@@ -1847,7 +1848,11 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
         const double wdf = d.w[k] * dn * fw;
         acc[3] += wdf * dn;
         for (int b = 0; b < D; ++b) acc[4 + b] += wdf * (d.xi[b][k] - dn * P.nw[b]);
-        acc[7] += 0.5 * d.w[k] * dn * (x2 * fw + (d.NA == 2 ? d.fwall[1][(size_t)p * NV + k] : 0.0));
+        const double e = x2 * fw + (d.NA == 2 ? d.fwall[1][(size_t)p * NV + k] : 0.0);
+        acc[7] += 0.5 * d.w[k] * dn * e;
+        acc[8] += d.w[k] * fw;
+        for (int b = 0; b < D; ++b) acc[9 + b] += d.w[k] * d.xi[b][k] * fw;
+        acc[12] += d.w[k] * e;
     }
     for (int b = 0; b < kForceWords; ++b) {
         double s = block_sum(acc[b]);

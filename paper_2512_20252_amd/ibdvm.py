@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
 
 class WallPoint(ctypes.Structure):
     _fields_ = [("xw", c_double * 3), ("nw", c_double * 3), ("rho_w", c_double), ("p_w", c_double),
-                ("tau_w", c_double * 3), ("q_n", c_double), ("C_p", c_double)]
+                ("tau_w", c_double * 3), ("q_n", c_double), ("C_p", c_double), ("T_s", c_double),
+                ("u_s", c_double * 3)]
 
 
 class Result(ctypes.Structure):
@@ -282,8 +283,8 @@ class Solver:
         n = c_int32(0)
         check(lib().ibdvm_surface_forces(self._h, _dp(F), ctypes.byref(cd), ctypes.byref(cl), pts, cap,
                                          ctypes.byref(n)))
-        wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] + list(p.tau_w) + [p.q_n, p.C_p]
-                         for p in pts[: n.value]]).reshape(-1, 13)
+        wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] + list(p.tau_w) + [p.q_n, p.C_p, p.T_s]
+                         + list(p.u_s) for p in pts[: n.value]]).reshape(-1, 17)
         return F, cd.value, cl.value, wall
 
     def residual(self):

@@ -113,6 +113,9 @@ def test_cylinder_small_full_run(oracle_mod, torch_cuda):
     assert np.max(np.abs(wg[:, 8:12] - wo[:, 8:12])) <= TOL64 * pscale
     u0 = c["Ma"] * np.sqrt(c["gamma"] / 2)
     assert np.max(np.abs(wg[:, 12] - wo[:, 12])) <= TOL64 * 2 * pscale / u0 ** 2
+    # temperature and velocity of the gas at the wall points
+    assert _rel(wg[:, 13], wo[:, 13]) <= TOL64
+    assert np.max(np.abs(wg[:, 14:17] - wo[:, 14:17])) <= TOL64 * max(np.max(np.abs(wo[:, 14:17])), 1.0)
 
 
 @pytest.mark.parametrize("flag", ["no_upwind", "no_cutcell"])
