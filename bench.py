@@ -328,6 +328,51 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     return out
 
 
+def precision_sweep(cases_kn_ma, rtol, cap, block=100):
+    """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep:
+    each case from the same seeded state, in replays of a captured graph of
+    `block` steps; the FP64 form runs until C_D changes by less than rtol
+    relative over a replay (or `cap` steps), the FP32 form then runs the same
+    number of steps, so the two C_D differ by precision only; the updates/s
+    of each form over its run."""
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    out = {"workload": "2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
+                       f"C_D change below {rtol:g} relative per {block} steps or {cap} steps", "cases": []}
+    for Kn, Ma in cases_kn_ma:
+        row = {"Kn": Kn, "Ma": Ma}
+        for prec in ("f64", "f32"):
+            case = cases.cylinder_256(Kn=Kn, Ma=Ma)
+            s = ibdvm.Solver(case, precision=prec, stream=torch.cuda.Stream())
+            s.init_freestream(cases.noise(case, 0), 1e-3)
+            s.set_tile(2, 4, 32)
+            g = ibdvm.Graph(s, block)
+            cd_prev, steps, t = None, 0, time.perf_counter()
+            limit = cap if prec == "f64" else row["f64"]["steps"]
+            while steps < limit:
+                g.launch()
+                steps += block
+                cd = s.surface_forces()[1]
+                if prec == "f64" and cd_prev is not None and abs(cd - cd_prev) < rtol * abs(cd):
+                    break
+                cd_prev = cd
+            wall = time.perf_counter() - t
+            row[prec] = {"CD": cd, "steps": steps, "converged": abs(cd - cd_prev) < rtol * abs(cd),
+                         "last_rel_change": abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None,
+                         "updates_per_s": s.nfluid * s.NV * steps / wall}
+            print(f"precision sweep: Kn {Kn} Ma {Ma} {prec}: C_D {cd:.8f} after {steps} steps", file=sys.stderr,
+                  flush=True)
+            g.close()
+            s.close()
+            torch.cuda.empty_cache()
+        row["dCD"] = abs(row["f32"]["CD"] - row["f64"]["CD"])
+        row["dCD_rel"] = row["dCD"] / abs(row["f64"]["CD"])
+        row["ratio_f32_vs_f64"] = row["f32"]["updates_per_s"] / row["f64"]["updates_per_s"]
+        out["cases"].append(row)
+    return out
+
+
 def cpu_baseline(case, seed=0):
     from oracle import oracle as oracle_mod
     from paper_2512_20252_amd import cases
@@ -408,6 +453,8 @@ def main():
     ap.add_argument("--cavity-steps", type=int, default=20)
     ap.add_argument("--implicit-kn", type=float, default=2e-4,
                     help="Knudsen number of the semi-implicit collision leg (0: skip)")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="add FP32 storage against FP64 over the cylinder's Kn x Ma sweep, run toward convergence")
     ap.add_argument("--vmesh-study", action="store_true",
                     help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
     ap.add_argument("--cavity-study", action="store_true",
@@ -489,6 +536,8 @@ def main():
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
     if args.implicit_kn > 0:
         line["implicit_collision"] = implicit_collision(args.implicit_kn, 50, 3)
+    if args.precision_sweep:
+        line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP, 1e-5, 20000)
     if args.vmesh_study:
         line["vmesh_study"] = vmesh_study([8, 12, 16, 24, 32], 128, 30.0, 1.5)
     if args.cavity_study:
