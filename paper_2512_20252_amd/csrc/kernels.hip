@@ -49,6 +49,20 @@ __device__ __forceinline__ T vanleer(T s1, T s2)
     return T(0);
 }
 
+// FP32 storage holds f minus the freestream Maxwellian, so that its
+// rounding is relative to the deviation from the freestream (the rounding of
+// a steady state acts like a constant source, and the deviation is small
+// over most of the domain); FP64 storage holds f.  fref is the offset of a
+// stored value of node k of array A.
+template <typename T, typename DR>
+__device__ __forceinline__ double fref(const DR &d, int A, int k)
+{
+    if constexpr (sizeof(T) == 4)
+        return d.fs[A][k];
+    else
+        return 0.0;
+}
+
 enum { NB_FLUID = 0, NB_BC = 1, NB_IB = 2 };
 
 // Value seen from fluid cell c (grid coordinates ijk) at c + side e_a:
@@ -64,7 +78,7 @@ __device__ __forceinline__ T neighbour(const Dev &d, const T *f, int A, int k, i
             kind = NB_BC;
             nc = -1;
             pr = -1;
-            return (T)d.fs[A][k];
+            return (T)(d.fs[A][k] - fref<T>(d, A, k));
         }
         i = (i + d.n[a]) % d.n[a];
     }
@@ -73,7 +87,7 @@ __device__ __forceinline__ T neighbour(const Dev &d, const T *f, int A, int k, i
         kind = NB_IB;
         nc = -1;
         pr = d.pnb[6 * c + 2 * a + (side > 0 ? 1 : 0)];
-        return (T)d.ghost[A][(size_t)pr * d.NV + k];
+        return (T)(d.ghost[A][(size_t)pr * d.NV + k] - fref<T>(d, A, k));
     }
     kind = NB_FLUID;
     nc = n;
@@ -259,26 +273,28 @@ __device__ void fill_incident(const DR &d, int cur, int p, int chunk)
         for (int j = 0; j < ns; ++j) sum += upw(j);
         for (int A = 0; A < d.NA; ++A) {
             const T *f = (const T *)d.f[cur][A];
+            const double rf = fref<T>(d, A, k);
             // 1. shifted point from the donor and the auxiliary-cell slope
-            const double fdc = (double)f[(size_t)dc * NV + k];
-            const double sdc = ac >= 0 ? ((double)f[(size_t)ac * NV + k] - fdc) / (yac - ydc) : 0.0;
+            const double fdc = (double)f[(size_t)dc * NV + k] + rf;
+            const double sdc = ac >= 0 ? ((double)f[(size_t)ac * NV + k] + rf - fdc) / (yac - ydc) : 0.0;
             const double fspv = fdc + sdc * (ysp - ydc);
             // 2. upwind-weighted interpolation from the surface cells
             double fgc = 0.0;
             for (int j = 0; j < ns; ++j) {
                 const double wj = (uniform || sum == 0.0) ? 1.0 / ns : upw(j) / sum;
                 const int sj = P.sc[j];
-                const double fj = (double)f[(size_t)sj * NV + k];
+                const double fj = (double)f[(size_t)sj * NV + k] + rf;
                 double sr = 0.0;
                 for (int b = 0; b < D; ++b) {
                     const int L = P.snb[j][b][0], R = P.snb[j][b][1];
                     double sg = 0.0;
                     if (L >= 0 && R >= 0)
-                        sg = vanleer(fj - (double)f[(size_t)L * NV + k], (double)f[(size_t)R * NV + k] - fj) * d.inv_dx[b];
+                        sg = vanleer(fj - ((double)f[(size_t)L * NV + k] + rf), ((double)f[(size_t)R * NV + k] + rf) - fj) *
+                             d.inv_dx[b];
                     else if (R >= 0)
-                        sg = ((double)f[(size_t)R * NV + k] - fj) * d.inv_dx[b];
+                        sg = (((double)f[(size_t)R * NV + k] + rf) - fj) * d.inv_dx[b];
                     else if (L >= 0)
-                        sg = (fj - (double)f[(size_t)L * NV + k]) * d.inv_dx[b];
+                        sg = (fj - ((double)f[(size_t)L * NV + k] + rf)) * d.inv_dx[b];
                     sr += sg * P.r[j][b];
                 }
                 fgc += wj * (fj - sr);
@@ -427,20 +443,23 @@ __device__ void relax_cell(const DR &d, int cur, int c, double rho, const double
             cs += cc[a] * s[a];
         }
         const double a_ = c2 * iT, Ae = A * exp(-a_), w = d.w[k];
+        const double r0 = fref<T>(d, 0, k);
         double n0, e;
         if (D == 2) {
+            const double r1 = fref<T>(d, 1, k);
             const double g0 = Ae * (1.0 + cs * (2.0 * a_ - 4.0));
             const double g1 = halfT * Ae * (1.0 + cs * (2.0 * a_ - 2.0));
-            const T t0 = (T)(((double)f0[k] + r * g0) * c0), t1 = (T)(((double)f1[k] + r * g1) * c0);
+            const T t0 = (T)(((double)f0[k] + r0 + r * g0) * c0 - r0);
+            const T t1 = (T)(((double)f1[k] + r1 + r * g1) * c0 - r1);
             f0[k] = t0;
             f1[k] = t1;
-            n0 = (double)t0;
-            e = c2 * n0 + (double)t1;
+            n0 = (double)t0 + r0;
+            e = c2 * n0 + ((double)t1 + r1);
         } else {
             const double g = Ae * (1.0 + cs * (2.0 * a_ - 5.0));
-            const T t0 = (T)(((double)f0[k] + r * g) * c0);
+            const T t0 = (T)(((double)f0[k] + r0 + r * g) * c0 - r0);
             f0[k] = t0;
-            n0 = (double)t0;
+            n0 = (double)t0 + r0;
             e = c2 * n0;
         }
         acc[0] += w * n0;
@@ -612,14 +631,14 @@ __global__ __launch_bounds__(256) void k_moments_direct(Dev d, int cur, int slot
         const T *f1 = D == 2 ? (const T *)d.f[cur][1] + (size_t)c * d.NV : nullptr;
         double rho = 0, m[3] = {0, 0, 0}, E2 = 0;
         for (int k = lane; k < d.NV; k += 64) {
-            double h = (double)f0[k], x2 = 0.0;
+            double h = (double)f0[k] + fref<T>(d, 0, k), x2 = 0.0;
             for (int a = 0; a < D; ++a) {
                 double x = d.xi[a][k];
                 x2 += x * x;
                 m[a] += d.w[k] * x * h;
             }
             rho += d.w[k] * h;
-            E2 += d.w[k] * (x2 * h + (D == 2 ? (double)f1[k] : 0.0));
+            E2 += d.w[k] * (x2 * h + (D == 2 ? (double)f1[k] + fref<T>(d, 1, k) : 0.0));
         }
         rho = wave_sum(rho);
         E2 = wave_sum(E2);
@@ -636,7 +655,7 @@ __global__ __launch_bounds__(256) void k_moments_direct(Dev d, int cur, int slot
                 cc[a] = d.xi[a][k] - U[a];
                 c2 += cc[a] * cc[a];
             }
-            double E = c2 * (double)f0[k] + (D == 2 ? (double)f1[k] : 0.0);
+            double E = c2 * ((double)f0[k] + fref<T>(d, 0, k)) + (D == 2 ? (double)f1[k] + fref<T>(d, 1, k) : 0.0);
             for (int a = 0; a < D; ++a) q[a] += d.w[k] * cc[a] * E;
         }
         for (int a = 0; a < D; ++a) q[a] = 0.5 * wave_sum(q[a]);
@@ -879,13 +898,21 @@ template <typename T, typename DR>
 __device__ __forceinline__ T ghost_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
-    return (T)bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
+    const double g = bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
+    if constexpr (sizeof(T) == 4)
+        return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
+    else
+        return (T)g;
 }
 template <typename T, typename DR>
 __device__ __forceinline__ T facev_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
-    return (T)bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
+    const double g = bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
+    if constexpr (sizeof(T) == 4)
+        return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
+    else
+        return (T)g;
 }
 
 // One workgroup = TX wavefronts = TX adjacent columns i0..i0+TX-1, rows
@@ -969,6 +996,9 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     };
     int koff[V];
     double xx[V], xy[V], wk[V];
+    // FP32 storage: the stored values are offsets from the freestream (fref)
+    constexpr bool SHIFT = sizeof(T) == 4;
+    double rf0[V], rf1[V];
     // FP64 keeps fewer per-lane values, so its V = 2 form runs three
     // wavefronts per SIMD: the sign of the node velocity is XORed into the
     // half slope (ostate), |xi|/dx is formed where used, and the cell record
@@ -985,6 +1015,10 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         xx[v] = d.xi[0][kc];
         xy[v] = d.xi[1][kc];
         wk[v] = k < NV ? d.w[kc] : 0.0;
+        if constexpr (SHIFT) {
+            rf0[v] = d.fs[0][kc];
+            rf1[v] = d.fs[1][kc];
+        }
         pos[v] = xx[v] > 0.0;
         py[v] = xy[v] > 0.0;
         if constexpr (!LEAN) {
@@ -1259,13 +1293,22 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                 const double a = c2 * invT;
                 const double e = exp_neg(-a, etab);
                 const double t0 = fma(a, 2.0, -4.0);
-                const double g0 = (Ar * e) * fma(cs, t0, 1.0);
-                const double g1 = (ThAr * e) * fma(cs, t0 + 2.0, 1.0);
+                double g0 = (Ar * e) * fma(cs, t0, 1.0);
+                double g1 = (ThAr * e) * fma(cs, t0 + 2.0, 1.0);
+                if constexpr (SHIFT) {
+                    // relax the offset toward g - fref
+                    g0 = fma(-rate, rf0[v], g0);
+                    g1 = fma(-rate, rf1[v], g1);
+                }
                 const T st0 = (T)fma(-dt, (double)div[0], fma(c1, (double)f0[0][v], g0));
                 const T st1 = (T)fma(-dt, (double)div[1], fma(c1, (double)f0[1][v], g1));
                 bst(ws0, koff[v], st0);
                 bst(ws1, koff[v], st1);
-                const double n0 = (double)st0, n1 = (double)st1;
+                double n0 = (double)st0, n1 = (double)st1;
+                if constexpr (SHIFT) {
+                    n0 += rf0[v];
+                    n1 += rf1[v];
+                }
                 const double wh = wk[v] * n0, wE = wk[v] * fma(c2, n0, n1);
                 const double tx_ = cx * wh, ty_ = cy * wh;
                 m[0] += wh;
@@ -1345,7 +1388,7 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
     double out = 0.0;
     for (int k = threadIdx.x; k < NV; k += 256) {
         const double xn = sd * d.xi[a][k];
-        if (xn > 0.0) out += d.w[k] * xn * (double)h[k];
+        if (xn > 0.0) out += d.w[k] * xn * ((double)h[k] + fref<T>(d, 0, k));
     }
     out = block_sum(out);
     // wall_in sums e^{-c^2/T_w} without the prefactor A_w, so out / wall_in
@@ -1357,8 +1400,8 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
         const double xn = sd * d.xi[a][k];
         if (xn < 0.0) {
             const double hv = rA * ew(k);
-            g0[k] = (T)hv;
-            g1[k] = (T)(0.5 * d.Tw * hv);
+            g0[k] = (T)(hv - fref<T>(d, 0, k));
+            g1[k] = (T)(0.5 * d.Tw * hv - fref<T>(d, 1, k));
         } else {
             g0[k] = h[k];
             g1[k] = b[k];
@@ -1485,6 +1528,9 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
     int koff[V];
     double xv[3][V], wk[V];
     bool pos[3][V];
+    // FP32 storage: the stored values are offsets from the freestream (fref)
+    constexpr bool SHIFT = sizeof(T) == 4;
+    double rf[V];
     const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1], idz = (T)d.inv_dx[2];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -1492,6 +1538,7 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
         const int kc = min(k, NV - 1);
         koff[v] = k * ST;
         wk[v] = k < NV ? d.w[kc] : 0.0;
+        if constexpr (SHIFT) rf[v] = d.fs[0][kc];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             xv[a][v] = d.xi[a][kc];
@@ -1761,10 +1808,12 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
                 const double c2 = fma(cz, cz, fma(cy, cy, cx * cx)), cs = fma(cz, S2, fma(cy, S1, cx * S0));
                 const double a = c2 * invT;
                 const double e = exp_neg(-a, etab);
-                const double g = (Ar * e) * fma(cs, fma(a, 2.0, -5.0), 1.0);
+                double g = (Ar * e) * fma(cs, fma(a, 2.0, -5.0), 1.0);
+                if constexpr (SHIFT) g = fma(-rate, rf[v], g);  // relax the offset toward g - fref
                 const T st = (T)fma(-dt, (double)div, fma(c1r, (double)f0[v], g));
                 bst(ws, koff[v], st);
-                const double n0 = (double)st;
+                double n0 = (double)st;
+                if constexpr (SHIFT) n0 += rf[v];
                 const double wh = wk[v] * n0, wE = c2 * wh;
                 const double tx_ = cx * wh, ty_ = cy * wh, tz_ = cz * wh;
                 m[0] += wh;
@@ -1833,7 +1882,7 @@ __global__ __launch_bounds__(256) void k_force(Dev d, int cur)
             T vm = neighbour(d, f, 0, k, dc, ijk, a, -1, k1, n1, p1);
             T vp = neighbour(d, f, 0, k, dc, ijk, a, +1, k2, n2, p2);
             T v0 = f[(size_t)dc * NV + k];
-            st = (double)(v0 + T(side) * T(0.5) * vanleer(v0 - vm, vp - v0));
+            st = (double)(v0 + T(side) * T(0.5) * vanleer(v0 - vm, vp - v0)) + fref<T>(d, 0, k);
         } else {
             st = d.face[0][(size_t)p * NV + k];
         }
@@ -1867,8 +1916,10 @@ __global__ void k_state_from_freestream(Dev d, int buf, int A, const double *u, 
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const long long g = off + i;
         const int k = (int)(g % d.NV);
-        const double v = d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0));
-        ((T *)d.f[buf][A])[g] = (T)v;
+        if constexpr (sizeof(T) == 4)
+            ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (u ? amp * u[i] : 0.0));
+        else
+            ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0)));
     }
 }
 
@@ -1891,7 +1942,10 @@ __global__ void k_state_hashed(Dev d, int buf, int A, unsigned long long seed, d
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int k = (int)(i % d.NV);
         const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
-        ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
+        if constexpr (sizeof(T) == 4)
+            ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (amp * u));
+        else
+            ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
     }
 }
 
@@ -1899,14 +1953,14 @@ template <typename T>
 __global__ void k_state_set(Dev d, int buf, int A, const double *src, long long off, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        ((T *)d.f[buf][A])[off + i] = (T)src[i];
+        ((T *)d.f[buf][A])[off + i] = (T)(src[i] - fref<T>(d, A, (int)((off + i) % d.NV)));
 }
 
 template <typename T>
 __global__ void k_state_get(Dev d, int buf, int A, double *dst, long long off, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = (double)((const T *)d.f[buf][A])[off + i];
+        dst[i] = (double)((const T *)d.f[buf][A])[off + i] + fref<T>(d, A, (int)((off + i) % d.NV));
 }
 
 __global__ void k_ctrl_reset(Ctrl *c, int slot)
