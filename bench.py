@@ -8,9 +8,10 @@ velocity grid on [-6,6]^2, Kn 0.1, Ma 0.3, freestream Maxwellian with seeded
 1e-3 perturbation (synthetic input of the shape of the paper's cylinder
 cases).
 
-Prints one JSON line: cell-velocity updates/s of the FP64 step, the
+Prints one JSON line: cell-velocity updates/s of the FP64 step (the timed
+steps replayed from a captured HIP graph, inputs resident in HBM), the
 roofline of the update kernel (algorithmic HBM bytes per launch over its
-HIP-event duration), the FP32-storage form's rate and C_D difference, the
+HIP-event duration in eager steps of the same run), the FP32-storage form's rate and C_D difference, the
 3D sphere at 96^3 x 24^3 in both forms, the lid-driven cavity at 256^2 x
 100^2 in both forms, the semi-implicit collision against the explicit step on
 the cylinder at Kn 2e-4, the continuous-batching serving leg, and the CPU oracle timed on this host over one step of the same workload.
@@ -70,28 +71,45 @@ def _alu(workload, precision, tile, avg_ms):
 
 
 def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
+    """Warm-up steps, then `steps` eager steps with kernel timing (HIP events
+    around each launch on the solve's stream), then the timed region: the
+    same number of steps as one replay of a captured graph (an even count;
+    an odd count is timed as eager steps), bracketed by events on the
+    solve's stream."""
     import torch
     from paper_2512_20252_amd import cases, ibdvm
 
-    s = ibdvm.Solver(case, precision=precision)
+    stream = torch.cuda.Stream()
+    s = ibdvm.Solver(case, precision=precision, stream=stream)
     s.init_freestream(cases.noise(case, seed), 1e-3)
     if tile:
         s.set_tile(*tile)
     else:
         s.autotune(reps=3)
     s.step(warmup)
-    torch.cuda.synchronize()
+    prof = None
     if profile:
         s.profile(True)
+        s.step(steps)
+        prof = s.profile_read()
+        s.profile(False)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    g = None
+    if steps % 2 == 0:
+        g = ibdvm.Graph(s, steps)
+        g.launch()  # untimed: the first replay uploads the graph
     torch.cuda.synchronize()
-    t0.record()
-    s.step(steps)
-    t1.record()
+    t0.record(stream)
+    if g:
+        g.launch()
+    else:
+        s.step(steps)
+    t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    prof = s.profile_read() if profile else None
+    if g:
+        g.close()
     _, cd, _, _ = s.surface_forces()
     out = {"ms": ms, "prof": prof, "cd": cd, "nfluid": s.nfluid, "NV": s.NV, "dim": s.dim, "tile": s.get_tile()}
     del s

@@ -684,9 +684,10 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (e == hipSuccess) e = up(L.w, g.w.data(), g.w.size() * 8);
     if (e == hipSuccess) e = up(L.fs, fs.data(), fs.size() * 8);
     if (e == hipSuccess) e = up(L.hw, hw.data(), hw.size() * 8);
-    // the freestream rows in the storage type: FP32 storage holds offsets from
-    // the freestream, so its freestream rows are zero
+    // the freestream rows in the storage type: 2D FP32 storage holds offsets
+    // from the freestream, so its freestream rows are zero
     std::vector<float> fs32(fs.size(), 0.0f);
+    if (D == 3) fs32.assign(fs.begin(), fs.end());
     if (e == hipSuccess)
         e = c->precision == IBDVM_F32_STORE ? up(L.fsT, fs32.data(), fs32.size() * 4) : up(L.fsT, fs.data(), fs.size() * 8);
     std::vector<int> cflag32(g.cflag.begin(), g.cflag.end());

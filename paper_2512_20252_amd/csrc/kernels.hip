@@ -49,16 +49,18 @@ __device__ __forceinline__ T vanleer(T s1, T s2)
     return T(0);
 }
 
-// FP32 storage holds f minus the freestream Maxwellian, so that its
+// 2D FP32 storage holds f minus the freestream Maxwellian, so that its
 // rounding is relative to the deviation from the freestream (the rounding of
 // a steady state acts like a constant source, and the deviation is small
-// over most of the domain); FP64 storage holds f.  fref is the offset of a
-// stored value of node k of array A.
+// over most of the domain); FP64 storage and the 3D FP32 form hold f (there
+// the two extra live values per node cost the 4 x 4-tile update a fifth of
+// its speed in register spills).  fref is the offset of a stored value of
+// node k of array A.
 template <typename T, typename DR>
 __device__ __forceinline__ double fref(const DR &d, int A, int k)
 {
     if constexpr (sizeof(T) == 4)
-        return d.fs[A][k];
+        return d.D == 2 ? d.fs[A][k] : 0.0;
     else
         return 0.0;
 }
@@ -893,23 +895,24 @@ __device__ __forceinline__ double exp_neg(double x, const double *tab)
 }
 
 // ghost value / ghost-side face value of the pair seen from fluid cell c in
-// direction dir (2 axis + side), at byte offset k8 = 8 k of node k
-template <typename T, typename DR>
+// direction dir (2 axis + side), at byte offset k8 = 8 k of node k; OFF: as
+// an offset from the freestream (the 2D FP32 storage)
+template <typename T, bool OFF, typename DR>
 __device__ __forceinline__ T ghost_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     const double g = bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
-    if constexpr (sizeof(T) == 4)
+    if constexpr (OFF)
         return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
     else
         return (T)g;
 }
-template <typename T, typename DR>
+template <typename T, bool OFF, typename DR>
 __device__ __forceinline__ T facev_at(const DR &d, int A, int c, int dir, int k8)
 {
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     const double g = bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
-    if constexpr (sizeof(T) == 4)
+    if constexpr (OFF)
         return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
     else
         return (T)g;
@@ -1126,21 +1129,21 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 T fm = fm2[A][v], fp = R[0][A][v];
-                if (flm1 & CF_YM) fm = ghost_at<T>(d, A, c0 - nx, 2, koff[v] * (8 / ST));
-                if (flm1 & CF_YP) fp = ghost_at<T>(d, A, c0 - nx, 3, koff[v] * (8 / ST));
+                if (flm1 & CF_YM) fm = ghost_at<T, SHIFT>(d, A, c0 - nx, 2, koff[v] * (8 / ST));
+                if (flm1 & CF_YP) fp = ghost_at<T, SHIFT>(d, A, c0 - nx, 3, koff[v] * (8 / ST));
                 const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[A][v] - fm, fp - fm1[A][v]);
                 const T oym = osty(hm, fm1[A][v], v);
                 fm = fm1[A][v];
                 fp = R[1][A][v];
-                if (FL0 & CF_YM) fm = ghost_at<T>(d, A, c0, 2, koff[v] * (8 / ST));
-                if (FL0 & CF_YP) fp = ghost_at<T>(d, A, c0, 3, koff[v] * (8 / ST));
+                if (FL0 & CF_YM) fm = ghost_at<T, SHIFT>(d, A, c0, 2, koff[v] * (8 / ST));
+                if (FL0 & CF_YP) fp = ghost_at<T, SHIFT>(d, A, c0, 3, koff[v] * (8 / ST));
                 const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][A][v] - fm, fp - R[0][A][v]);
                 OY[0][A][v] = osty(h0, R[0][A][v], v);
                 T F;
                 if (py[v])
-                    F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0, 2, koff[v] * (8 / ST)));
+                    F = !(flm1 & CF_SOLID) ? oym : ((FL0 & CF_SOLID) ? T(0) : facev_at<T, SHIFT>(d, A, c0, 2, koff[v] * (8 / ST)));
                 else
-                    F = !(FL0 & CF_SOLID) ? OY[0][A][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c0 - nx, 3, koff[v] * (8 / ST)));
+                    F = !(FL0 & CF_SOLID) ? OY[0][A][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T, SHIFT>(d, A, c0 - nx, 3, koff[v] * (8 / ST)));
                 FD[0][A][v] = F;
             }
         __builtin_amdgcn_s_waitcnt(0);
@@ -1195,8 +1198,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     T fm = fb[A][p0][v * 64 + lane];
                     const T fc = fb[A][p0 + 1][v * 64 + lane];
                     T fp = fb[A][p0 + 2][v * 64 + lane];
-                    if (NEAR && (fl & CF_XM)) fm = ghost_at<T>(d, A, cc, 0, koff[v] * (8 / ST));
-                    if (NEAR && (fl & CF_XP)) fp = ghost_at<T>(d, A, cc, 1, koff[v] * (8 / ST));
+                    if (NEAR && (fl & CF_XM)) fm = ghost_at<T, SHIFT>(d, A, cc, 0, koff[v] * (8 / ST));
+                    if (NEAR && (fl & CF_XP)) fp = ghost_at<T, SHIFT>(d, A, cc, 1, koff[v] * (8 / ST));
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (fl & CF_SOLID)) h = T(0);
                     const T o = ostx(h, fc, v);
@@ -1227,8 +1230,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                     T fm = fb[hA][spos][v * 64 + lane];
                     const T fc = fb[hA][spos + 1][v * 64 + lane];
                     T fp = fb[hA][spos + 2][v * 64 + lane];
-                    if (NEAR && (flh & CF_XM)) fm = ghost_at<T>(d, hA, ch_, 0, koff[v] * (8 / ST));
-                    if (NEAR && (flh & CF_XP)) fp = ghost_at<T>(d, hA, ch_, 1, koff[v] * (8 / ST));
+                    if (NEAR && (flh & CF_XM)) fm = ghost_at<T, SHIFT>(d, hA, ch_, 0, koff[v] * (8 / ST));
+                    if (NEAR && (flh & CF_XP)) fp = ghost_at<T, SHIFT>(d, hA, ch_, 1, koff[v] * (8 / ST));
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (flh & CF_SOLID)) h = T(0);
                     ob[hA][spos][v * 64 + lane] = ostx(h, fc, v);
@@ -1261,24 +1264,24 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
 #pragma unroll
                 for (int A = 0; A < 2; ++A) {
                     T fm = f0[A][v], fp = f2[A][v];
-                    if (NEAR && (FL1 & CF_YM)) fm = ghost_at<T>(d, A, c + nx, 2, koff[v] * (8 / ST));
-                    if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T>(d, A, c + nx, 3, koff[v] * (8 / ST));
+                    if (NEAR && (FL1 & CF_YM)) fm = ghost_at<T, SHIFT>(d, A, c + nx, 2, koff[v] * (8 / ST));
+                    if (NEAR && (FL1 & CF_YP)) fp = ghost_at<T, SHIFT>(d, A, c + nx, 3, koff[v] * (8 / ST));
                     T h1 = vl_half(f1[A][v] - fm, fp - f1[A][v]);
                     if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
                     oy1[A][v] = osty(h1, f1[A][v], v);
                     T F = py[v] ? oy0[A][v] : oy1[A][v];
                     if (NEAR) {
                         if (py[v]) {
-                            if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c + nx, 2, koff[v] * (8 / ST));
+                            if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T, SHIFT>(d, A, c + nx, 2, koff[v] * (8 / ST));
                         } else {
-                            if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, A, c, 3, koff[v] * (8 / ST));
+                            if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T, SHIFT>(d, A, c, 3, koff[v] * (8 / ST));
                         }
                     }
                     Fup[A][v] = F;
                     // the upwind neighbour's outgoing state is the face state on the upwind side
                     T nbs = ob[A][pos[v] ? w : w + 2][v * 64 + lane];
-                    if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T>(d, A, c, 0, koff[v] * (8 / ST));
-                    if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T>(d, A, c, 1, koff[v] * (8 / ST));
+                    if (NEAR && pos[v] && (FL0 & CF_XM)) nbs = facev_at<T, SHIFT>(d, A, c, 0, koff[v] * (8 / ST));
+                    if (NEAR && !pos[v] && (FL0 & CF_XP)) nbs = facev_at<T, SHIFT>(d, A, c, 1, koff[v] * (8 / ST));
                     const T ax = LEAN ? (T)fabs(xx[v]) * idx : axp[v], ay = LEAN ? (T)xy[v] * idy : ayq[v];
                     div[A] = fma(ax, ox[A][v] - nbs, ay * (F - Fdn[A][v]));
                 }
@@ -1528,9 +1531,7 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
     int koff[V];
     double xv[3][V], wk[V];
     bool pos[3][V];
-    // FP32 storage: the stored values are offsets from the freestream (fref)
-    constexpr bool SHIFT = sizeof(T) == 4;
-    double rf[V];
+
     const T idx = (T)d.inv_dx[0], idy = (T)d.inv_dx[1], idz = (T)d.inv_dx[2];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -1538,7 +1539,6 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
         const int kc = min(k, NV - 1);
         koff[v] = k * ST;
         wk[v] = k < NV ? d.w[kc] : 0.0;
-        if constexpr (SHIFT) rf[v] = d.fs[0][kc];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             xv[a][v] = d.xi[a][kc];
@@ -1621,21 +1621,21 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
         for (int v = 0; v < V; ++v) {
             const int k8 = koff[v] * (8 / ST);
             T fm = fm2[v], fp = R[0][v];
-            if (flm1 & CF_ZM) fm = ghost_at<T>(d, 0, cm, 4, k8);
-            if (flm1 & CF_ZP) fp = ghost_at<T>(d, 0, cm, 5, k8);
+            if (flm1 & CF_ZM) fm = ghost_at<T, false>(d, 0, cm, 4, k8);
+            if (flm1 & CF_ZP) fp = ghost_at<T, false>(d, 0, cm, 5, k8);
             const T hm = (flm1 & CF_SOLID) ? T(0) : vl_half(fm1[v] - fm, fp - fm1[v]);
             const T ozm = ostate(hm, fm1[v], xv[2][v]);
             fm = fm1[v];
             fp = R[1][v];
-            if (FL0 & CF_ZM) fm = ghost_at<T>(d, 0, c0, 4, k8);
-            if (FL0 & CF_ZP) fp = ghost_at<T>(d, 0, c0, 5, k8);
+            if (FL0 & CF_ZM) fm = ghost_at<T, false>(d, 0, c0, 4, k8);
+            if (FL0 & CF_ZP) fp = ghost_at<T, false>(d, 0, c0, 5, k8);
             const T h0 = (FL0 & CF_SOLID) ? T(0) : vl_half(R[0][v] - fm, fp - R[0][v]);
             OZ[0][v] = ostate(h0, R[0][v], xv[2][v]);
             T F;
             if (pos[2][v])
-                F = !(flm1 & CF_SOLID) ? ozm : ((FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c0, 4, k8));
+                F = !(flm1 & CF_SOLID) ? ozm : ((FL0 & CF_SOLID) ? T(0) : facev_at<T, false>(d, 0, c0, 4, k8));
             else
-                F = !(FL0 & CF_SOLID) ? OZ[0][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, cm, 5, k8));
+                F = !(FL0 & CF_SOLID) ? OZ[0][v] : ((flm1 & CF_SOLID) ? T(0) : facev_at<T, false>(d, 0, cm, 5, k8));
             FD[0][v] = F;
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -1688,16 +1688,16 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
                 const int k8 = koff[v] * (8 / ST);
                 const T fc = f0[v];
                 T fm = fb[sown - 1][v * 64 + lane], fp = fb[sown + 1][v * 64 + lane];
-                if (NEAR && (FL0 & CF_XM)) fm = ghost_at<T>(d, 0, c, 0, k8);
-                if (NEAR && (FL0 & CF_XP)) fp = ghost_at<T>(d, 0, c, 1, k8);
+                if (NEAR && (FL0 & CF_XM)) fm = ghost_at<T, false>(d, 0, c, 0, k8);
+                if (NEAR && (FL0 & CF_XP)) fp = ghost_at<T, false>(d, 0, c, 1, k8);
                 T h = vl_half(fc - fm, fp - fc);
                 if (NEAR && (FL0 & CF_SOLID)) h = T(0);
                 ox[v] = ostate(h, fc, xv[0][v]);
                 obx[ty][tx + 1][v * 64 + lane] = ox[v];
                 fm = fb[xslot<TY>(tx, ty - 1)][v * 64 + lane];
                 fp = fb[xslot<TY>(tx, ty + 1)][v * 64 + lane];
-                if (NEAR && (FL0 & CF_YM)) fm = ghost_at<T>(d, 0, c, 2, k8);
-                if (NEAR && (FL0 & CF_YP)) fp = ghost_at<T>(d, 0, c, 3, k8);
+                if (NEAR && (FL0 & CF_YM)) fm = ghost_at<T, false>(d, 0, c, 2, k8);
+                if (NEAR && (FL0 & CF_YP)) fp = ghost_at<T, false>(d, 0, c, 3, k8);
                 h = vl_half(fc - fm, fp - fc);
                 if (NEAR && (FL0 & CF_SOLID)) h = T(0);
                 oy[v] = ostate(h, fc, xv[1][v]);
@@ -1744,8 +1744,8 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
                     T fm = fb[sm][v * 64 + lane];
                     const T fc = fb[sc][v * 64 + lane];
                     T fp = fb[sp][v * 64 + lane];
-                    if (NEAR && (flh & (CF_XM | CF_YM))) fm = ghost_at<T>(d, 0, ch_, dm, k8);
-                    if (NEAR && (flh & (CF_XP | CF_YP))) fp = ghost_at<T>(d, 0, ch_, dm + 1, k8);
+                    if (NEAR && (flh & (CF_XM | CF_YM))) fm = ghost_at<T, false>(d, 0, ch_, dm, k8);
+                    if (NEAR && (flh & (CF_XP | CF_YP))) fp = ghost_at<T, false>(d, 0, ch_, dm + 1, k8);
                     T h = vl_half(fc - fm, fp - fc);
                     if (NEAR && (flh & CF_SOLID)) h = T(0);
                     dst[v * 64 + lane] = ostate(h, fc, hox ? xv[0][v] : xv[1][v]);
@@ -1776,27 +1776,27 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
             for (int v = 0; v < V; ++v) {
                 const int k8 = koff[v] * (8 / ST);
                 T fm = f0[v], fp = f2[v];
-                if (NEAR && (FL1 & CF_ZM)) fm = ghost_at<T>(d, 0, c1, 4, k8);
-                if (NEAR && (FL1 & CF_ZP)) fp = ghost_at<T>(d, 0, c1, 5, k8);
+                if (NEAR && (FL1 & CF_ZM)) fm = ghost_at<T, false>(d, 0, c1, 4, k8);
+                if (NEAR && (FL1 & CF_ZP)) fp = ghost_at<T, false>(d, 0, c1, 5, k8);
                 T h1 = vl_half(f1[v] - fm, fp - f1[v]);
                 if (NEAR && (FL1 & CF_SOLID)) h1 = T(0);
                 oz1[v] = ostate(h1, f1[v], xv[2][v]);
                 T F = pos[2][v] ? oz0[v] : oz1[v];
                 if (NEAR) {
                     if (pos[2][v]) {
-                        if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c1, 4, k8);
+                        if (FL0 & CF_SOLID) F = (FL1 & CF_SOLID) ? T(0) : facev_at<T, false>(d, 0, c1, 4, k8);
                     } else {
-                        if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T>(d, 0, c, 5, k8);
+                        if (FL1 & CF_SOLID) F = (FL0 & CF_SOLID) ? T(0) : facev_at<T, false>(d, 0, c, 5, k8);
                     }
                 }
                 Fup[v] = F;
                 // upwind neighbours' outgoing states are the face states on the upwind side
                 T nx_ = obx[ty][pos[0][v] ? tx : tx + 2][v * 64 + lane];
                 T ny_ = oby[pos[1][v] ? ty : ty + 2][tx][v * 64 + lane];
-                if (NEAR && pos[0][v] && (FL0 & CF_XM)) nx_ = facev_at<T>(d, 0, c, 0, k8);
-                if (NEAR && !pos[0][v] && (FL0 & CF_XP)) nx_ = facev_at<T>(d, 0, c, 1, k8);
-                if (NEAR && pos[1][v] && (FL0 & CF_YM)) ny_ = facev_at<T>(d, 0, c, 2, k8);
-                if (NEAR && !pos[1][v] && (FL0 & CF_YP)) ny_ = facev_at<T>(d, 0, c, 3, k8);
+                if (NEAR && pos[0][v] && (FL0 & CF_XM)) nx_ = facev_at<T, false>(d, 0, c, 0, k8);
+                if (NEAR && !pos[0][v] && (FL0 & CF_XP)) nx_ = facev_at<T, false>(d, 0, c, 1, k8);
+                if (NEAR && pos[1][v] && (FL0 & CF_YM)) ny_ = facev_at<T, false>(d, 0, c, 2, k8);
+                if (NEAR && !pos[1][v] && (FL0 & CF_YP)) ny_ = facev_at<T, false>(d, 0, c, 3, k8);
                 const T ax = (T)fabs(xv[0][v]) * idx, ay = (T)fabs(xv[1][v]) * idy, az = (T)xv[2][v] * idz;
                 const T div = fma(ax, ox[v] - nx_, fma(ay, oy[v] - ny_, az * (F - Fdn[v])));
                 if (NEAR && !upd) {
@@ -1808,12 +1808,10 @@ void k_update3d(Dev d, int cur, int slot, int LZ, int ntx, int nty, int nzs, int
                 const double c2 = fma(cz, cz, fma(cy, cy, cx * cx)), cs = fma(cz, S2, fma(cy, S1, cx * S0));
                 const double a = c2 * invT;
                 const double e = exp_neg(-a, etab);
-                double g = (Ar * e) * fma(cs, fma(a, 2.0, -5.0), 1.0);
-                if constexpr (SHIFT) g = fma(-rate, rf[v], g);  // relax the offset toward g - fref
+                const double g = (Ar * e) * fma(cs, fma(a, 2.0, -5.0), 1.0);
                 const T st = (T)fma(-dt, (double)div, fma(c1r, (double)f0[v], g));
                 bst(ws, koff[v], st);
-                double n0 = (double)st;
-                if constexpr (SHIFT) n0 += rf[v];
+                const double n0 = (double)st;
                 const double wh = wk[v] * n0, wE = c2 * wh;
                 const double tx_ = cx * wh, ty_ = cy * wh, tz_ = cz * wh;
                 m[0] += wh;
@@ -1916,7 +1914,7 @@ __global__ void k_state_from_freestream(Dev d, int buf, int A, const double *u, 
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const long long g = off + i;
         const int k = (int)(g % d.NV);
-        if constexpr (sizeof(T) == 4)
+        if (sizeof(T) == 4 && d.D == 2)
             ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (u ? amp * u[i] : 0.0));
         else
             ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0)));
@@ -1942,7 +1940,7 @@ __global__ void k_state_hashed(Dev d, int buf, int A, unsigned long long seed, d
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int k = (int)(i % d.NV);
         const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
-        if constexpr (sizeof(T) == 4)
+        if (sizeof(T) == 4 && d.D == 2)
             ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (amp * u));
         else
             ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
