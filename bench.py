@@ -346,25 +346,34 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     return out
 
 
-def precision_sweep(cases_kn_ma, rtol, cap, block=100):
-    """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep:
-    each case from the same seeded state, in replays of a captured graph of
-    `block` steps; the FP64 form runs until C_D changes by less than rtol
-    relative over a replay (or `cap` steps), the FP32 form then runs the same
-    number of steps, so the two C_D differ by precision only; the updates/s
-    of each form over its run."""
+def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48):
+    """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep and
+    a sphere of sphere_n^3 cells (24^3 nodes, Kn 0.1, Ma 1.5): each case
+    from the same seeded state, in replays of a captured graph of `block`
+    steps; the FP64 form runs until C_D changes by less than rtol relative
+    over a replay (or `cap` steps), the FP32 form then runs the same number
+    of steps, so the two C_D differ by precision only; the updates/s of each
+    form over its run."""
     import torch
     from paper_2512_20252_amd import cases, ibdvm
 
     out = {"workload": "2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
+                       f"and 3D sphere on {sphere_n}^3 cells, 24^3 nodes; "
                        f"C_D change below {rtol:g} relative per {block} steps or {cap} steps", "cases": []}
-    for Kn, Ma in cases_kn_ma:
-        row = {"Kn": Kn, "Ma": Ma}
+    runs = [(f"cylinder Kn {Kn} Ma {Ma}", {"Kn": Kn, "Ma": Ma}, cases.cylinder_256(Kn=Kn, Ma=Ma))
+            for Kn, Ma in cases_kn_ma]
+    if sphere_n:
+        runs.append((f"sphere {sphere_n}^3", {"sphere_n": sphere_n, "Kn": 0.1, "Ma": 1.5},
+                     cases.sphere(n=sphere_n, vn=24)))
+    for label, row, case in runs:
+        row = dict(row)
         for prec in ("f64", "f32"):
-            case = cases.cylinder_256(Kn=Kn, Ma=Ma)
             s = ibdvm.Solver(case, precision=prec, stream=torch.cuda.Stream())
-            s.init_freestream(cases.noise(case, 0), 1e-3)
-            s.set_tile(2, 4, 32)
+            if case["dim"] == 2:
+                s.init_freestream(cases.noise(case, 0), 1e-3)
+                s.set_tile(2, 4, 32)
+            else:
+                s.init_freestream_hashed(0, 1e-3)  # a host array of the 3D state would be large
             g = ibdvm.Graph(s, block)
             cd_prev, steps, t = None, 0, time.perf_counter()
             limit = cap if prec == "f64" else row["f64"]["steps"]
@@ -379,8 +388,7 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100):
             row[prec] = {"CD": cd, "steps": steps, "converged": abs(cd - cd_prev) < rtol * abs(cd),
                          "last_rel_change": abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None,
                          "updates_per_s": s.nfluid * s.NV * steps / wall}
-            print(f"precision sweep: Kn {Kn} Ma {Ma} {prec}: C_D {cd:.8f} after {steps} steps", file=sys.stderr,
-                  flush=True)
+            print(f"precision sweep: {label} {prec}: C_D {cd:.8f} after {steps} steps", file=sys.stderr, flush=True)
             g.close()
             s.close()
             torch.cuda.empty_cache()
@@ -473,6 +481,7 @@ def main():
                     help="Knudsen number of the semi-implicit collision leg (0: skip)")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="add FP32 storage against FP64 over the cylinder's Kn x Ma sweep, run toward convergence")
+    ap.add_argument("--sweep-sphere-only", action="store_true", help="run only the sphere case of the precision sweep")
     ap.add_argument("--vmesh-study", action="store_true",
                     help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
     ap.add_argument("--cavity-study", action="store_true",
@@ -555,7 +564,8 @@ def main():
     if args.implicit_kn > 0:
         line["implicit_collision"] = implicit_collision(args.implicit_kn, 50, 3)
     if args.precision_sweep:
-        line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP, 1e-5, 20000)
+        line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP if not args.sweep_sphere_only else [], 1e-5,
+                                                  20000)
     if args.vmesh_study:
         line["vmesh_study"] = vmesh_study([8, 12, 16, 24, 32], 128, 30.0, 1.5)
     if args.cavity_study:
