@@ -87,14 +87,19 @@ def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     else:
         s.autotune(reps=3)
     s.step(warmup)
-    prof = None
-    if profile:
-        s.profile(True)
-        s.step(steps)
-        prof = s.profile_read()
-        s.profile(False)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    prof, ms_eager = None, None
+    if profile:
+        s.profile(True)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        s.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms_eager = t0.elapsed_time(t1)
+        prof = s.profile_read()
+        s.profile(False)
     g = None
     if steps % 2 == 0:
         g = ibdvm.Graph(s, steps)
@@ -111,7 +116,8 @@ def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     if g:
         g.close()
     _, cd, _, _ = s.surface_forces()
-    out = {"ms": ms, "prof": prof, "cd": cd, "nfluid": s.nfluid, "NV": s.NV, "dim": s.dim, "tile": s.get_tile()}
+    out = {"ms": ms, "ms_eager": ms_eager, "graph": g is not None, "prof": prof, "cd": cd, "nfluid": s.nfluid,
+           "NV": s.NV, "dim": s.dim, "tile": s.get_tile()}
     del s
     torch.cuda.empty_cache()
     return out
@@ -571,11 +577,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
                                "Kn 0.1, Ma 0.3, Shakhov, diffuse wall, FP64",
-                   "cells": 65536, "fluid_cells": r64["nfluid"], "velocity_nodes": r64["NV"]},
+                   "cells": 65536, "fluid_cells": r64["nfluid"], "velocity_nodes": r64["NV"],
+                   "timed_as": "one replay of a captured graph of the K steps" if r64["graph"] else "K eager steps"},
+        "value_eager": upd * args.steps / (r64["ms_eager"] * 1e-3) if r64["ms_eager"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "alu": _alu(workload, "f64", r64["tile"], avg_ms),
                      "kernel": "k_update2d<double, %d, %d, false>" % tuple(r64["tile"][:2]),
+                     "timing": "HIP events around each update launch on its stream, over K eager steps of this run "
+                               "(the steps before the timed graph replay)",
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": bytes_launch,
                      "fill_avg_launch_ms": prof["fill_ms"] / max(prof["fill_launches"], 1),
                      "tile": r64["tile"]},
