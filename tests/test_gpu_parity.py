@@ -831,6 +831,40 @@ SERVE_CASES = [cases.cylinder_small(),
                           aoa=0.3, Kn=0.1, Ma=0.8)]
 
 
+OPTION_CASES = [cases.case(**dict(cases.cavity(n=24, vn=10, lid_u=0.25), n=(24, 19))),
+                cases.case(**dict(cases.cylinder_small(), Kn=0.002, flags=("implicit",))),
+                cases.case(**dict(cases.cylinder_small(), rule="stretched", vstretch=1.3, vn=(15, 13), alpha=0.8)),
+                cases.cylinder_small()]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("fuse_below", [1 << 62, 0])
+def test_server_mixes_options(torch_cuda, precision, fuse_below):
+    """The server runs a cavity (outer walls, moving lid), a semi-implicit
+    solve, a stretched velocity grid and a plain cylinder together, fused
+    or standalone, and each result equals the same solve stepped alone."""
+    srv = ibdvm.Server(sum(ibdvm.footprint(c, precision) for c in OPTION_CASES) + (1 << 20),
+                       max_active=4, steps_per_replay=4, fuse_below=fuse_below)
+    ids = [srv.submit(c, precision, seed=21 + i, amp=1e-3, tol=0.0, max_steps=12, keep_moments=True)
+           for i, c in enumerate(OPTION_CASES)]
+    done = {}
+    while len(done) < len(ids):
+        for r in srv.poll(block=True):
+            done[r["id"]] = r
+    for i, (rid, c) in enumerate(zip(ids, OPTION_CASES)):
+        r = done[rid]
+        assert r["status"] == ibdvm.OK and r["steps"] == 12
+        s = ibdvm.Solver(c, precision=precision)
+        s.init_freestream_hashed(21 + i, 1e-3)
+        s.set_tile(*r["tile"])
+        s.step(12)
+        assert np.array_equal(s.moments(), r["moments"], equal_nan=True)
+        cd = s.surface_forces()[1]
+        assert cd == r["C_D"] or (np.isnan(cd) and np.isnan(r["C_D"]))
+    srv.close()
+
+
 # fusion limits: every solve in the fused group, none, and the first case
 # (262k updates per step) standalone beside a fused group of the others
 FUSION = {"fused": 1 << 62, "standalone": 0, "mixed": 150000}
