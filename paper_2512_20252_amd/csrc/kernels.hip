@@ -493,26 +493,50 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
     for (int i = 0; i < 2 * kResVars; ++i) rv[i] = 0.0;
     // one cell per wavefront: the cell's partial records are contiguous, lane
     // l sums word l % 16 of records l / 16, l / 16 + 4, ... in coalesced loads
+    // the flag word, the cell record and the partial records are read
+    // together (in bounds for every c < Nc), so the wavefront waits for
+    // one round trip to memory instead of three
     const int c = blk * 4 + wv;
-    if (c < d.Nc && !(d.cflag[c] & 1)) {
-        const double *pp = d.part + (size_t)c * d.nchunk * kPartialStride;
-        const int nw = d.nchunk * kPartialStride;
-        double acc = 0.0, acc2 = 0.0;
-        int ow = lane;
-        for (; ow + 64 < nw; ow += 128) {
-            acc += pp[ow];
-            acc2 += pp[ow + 64];
+    const bool cin = c < d.Nc;
+    const size_t cs = cin ? (size_t)c : 0;
+    const int fl = d.cflag[cs];
+    const double *cp = d.cellp + cs * kCellWords;
+    const double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
+    const double rho_old = cp[CW_RHO], T_old = cp[CW_T];
+    const double *pp = d.part + cs * d.nchunk * kPartialStride;
+    const int nw = d.nchunk * kPartialStride;
+    // words lane, lane + 64, ... alternate between two sums (even rows to
+    // acc, odd rows to acc2, in order); eight rows are loaded before they
+    // are added, the last block with the rows past the end read as zero
+    double acc = 0.0, acc2 = 0.0;
+    int ow = lane;
+    for (; ow + 7 * 64 < nw; ow += 8 * 64) {
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = pp[ow + 64 * m];
+#pragma unroll
+        for (int m = 0; m < 8; m += 2) {
+            acc += v[m];
+            acc2 += v[m + 1];
         }
-        if (ow < nw) acc += pp[ow];
+    }
+    if (ow < nw) {
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = ow + 64 * m < nw ? pp[ow + 64 * m] : 0.0;
+#pragma unroll
+        for (int m = 0; m < 8; m += 2) {
+            acc += v[m];
+            acc2 += v[m + 1];
+        }
+    }
+    if (cin && !(fl & 1)) {
         acc += acc2;
         acc += __shfl_xor(acc, 16, 64);
         acc += __shfl_xor(acc, 32, 64);
         double S[PW];
 #pragma unroll
         for (int j = 0; j < PW; ++j) S[j] = __shfl(acc, j, 64);
-        const double *cp = d.cellp + (size_t)c * kCellWords;
-        const double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
-        const double rho_old = cp[CW_RHO], T_old = cp[CW_T];
         double m0, U[3], T, q[3];
         moments_from_sums<D>(S, Uref, m0, U, T, q);
         // semi-implicit collision: the new heat flux in closed form, then
