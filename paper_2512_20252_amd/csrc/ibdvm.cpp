@@ -336,8 +336,10 @@ ibdvm_status fused_fill(ibdvm_ctx *const *cs, int n, bool fill, hipStream_t stre
                 const int m = (int)std::min<size_t>(ibdvm::kMaxBatch, grp.size() - b);
                 ibdvm::BatchArgs fin{}, spec{}, ghost{};
                 fin.n = spec.n = ghost.n = m;
+                bool implicit = false;
                 for (int q = 0; q < m; ++q) {
                     const ibdvm_ctx *c = grp[b + q];
+                    implicit = implicit || (c->pending && (c->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION));
                     const int nfc = (c->geo.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk;
                     const int nfill = fill ? c->dev.npairs * nfc : 0;
                     const int nfin = c->pending ? (c->geo.Nc + 3) / 4 : 0;
@@ -349,7 +351,7 @@ ibdvm_status fused_fill(ibdvm_ctx *const *cs, int n, bool fill, hipStream_t stre
                     spec.blk0[q + 1] = spec.blk0[q] + (c->dev.alpha < 1.0 ? nfill : 0);
                     ghost.blk0[q + 1] = ghost.blk0[q] + nfill;
                 }
-                HIP_CHECK(ibdvm::launch_fill_batch(D, prec, fin, spec, ghost, stream));
+                HIP_CHECK(ibdvm::launch_fill_batch(D, prec, fin, spec, ghost, implicit, stream));
             }
         }
     for (int i = 0; i < n; ++i) cs[i]->pending = false;

@@ -477,7 +477,10 @@ __device__ void relax_cell(const DR &d, int cur, int c, double rho, const double
     for (int j = 0; j < PW; ++j) S[j] = wave_sum(acc[j]);
 }
 
-template <int D, typename TS, typename DR>
+// IMPL: the instance that can take the semi-implicit branch (its relaxation
+// pass more than doubles the registers of the finish, so the explicit
+// instance leaves it out and runs at about twice the occupancy)
+template <int D, typename TS, bool IMPL, typename DR>
 __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
 {
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
@@ -542,7 +545,7 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
         // semi-implicit collision: the new heat flux in closed form, then
         // the backward-Euler relaxation of the cell's transported state and
         // the relaxed state's moments
-        if (d.flags & kFlagImplicit) {
+        if (IMPL && (d.flags & kFlagImplicit)) {
             const double r = d.ctrl->dt * (0.5 * m0 * T) / (d.mu0 * pow(T, d.omega));
             for (int a = 0; a < D; ++a) q[a] /= 1.0 + d.Pr * r;
             const double Us[3] = {U[0], U[1], U[2]};
@@ -573,7 +576,7 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
     tau_min_commit(d, slot, tmin);
 }
 
-template <int D, typename T>
+template <int D, typename T, bool IMPL>
 __global__ __launch_bounds__(256) void k_fill_fin(Dev d, int cur, int slot, int nfill, int dofin)
 {
     if ((int)blockIdx.x < nfill) {
@@ -581,7 +584,7 @@ __global__ __launch_bounds__(256) void k_fill_fin(Dev d, int cur, int slot, int 
         fill_incident<D, T>(d, cur, blockIdx.x / nfc, blockIdx.x % nfc);
         return;
     }
-    if (dofin) fin_cells<D, T>(d, cur, slot, blockIdx.x - nfill);
+    if (dofin) fin_cells<D, T, IMPL>(d, cur, slot, blockIdx.x - nfill);
 }
 
 template <int D>
@@ -613,7 +616,7 @@ __device__ __forceinline__ int batch_solve(const BatchArgs &a, long long L)
 typedef const __attribute__((address_space(4))) Dev *cdev_p;
 
 // the three fill phases over the (pair, chunk) workgroups of several solves
-template <int D, typename T>
+template <int D, typename T, bool IMPL>
 __global__ __launch_bounds__(256) void k_fill_fin_batch(BatchArgs a)
 {
     const int s = batch_solve(a, blockIdx.x);
@@ -624,7 +627,7 @@ __global__ __launch_bounds__(256) void k_fill_fin_batch(BatchArgs a)
         fill_incident<D, T>(d, a.cur[s], b / nfc, b % nfc);
         return;
     }
-    fin_cells<D, T>(d, a.cur[s], a.slot[s], b - a.nfill[s]);
+    fin_cells<D, T, IMPL>(d, a.cur[s], a.slot[s], b - a.nfill[s]);
 }
 
 template <int D>
@@ -2092,11 +2095,14 @@ hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const B
 }
 
 hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
-                             hipStream_t s)
+                             bool implicit, hipStream_t s)
 {
     hipError_t e = hipSuccess;
     if (fin.blk0[fin.n] > 0) {
-        DISPATCH(D, storage, hipLaunchKernelGGL((k_fill_fin_batch<DD, TT>), dim3((unsigned)fin.blk0[fin.n]), dim3(256), 0, s, fin));
+        if (implicit)
+            DISPATCH(D, storage, hipLaunchKernelGGL((k_fill_fin_batch<DD, TT, true>), dim3((unsigned)fin.blk0[fin.n]), dim3(256), 0, s, fin));
+        else
+            DISPATCH(D, storage, hipLaunchKernelGGL((k_fill_fin_batch<DD, TT, false>), dim3((unsigned)fin.blk0[fin.n]), dim3(256), 0, s, fin));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (spec.blk0[spec.n] > 0) {
@@ -2146,8 +2152,12 @@ hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fi
     const int nfill = fill ? d.npairs * ((d.NV + kFillChunk - 1) / kFillChunk) : 0;
     const int nfin = fin ? (int)blocks_for(d.Nc, 4) : 0;
     if (nfill + nfin == 0) return hipSuccess;
-    DISPATCH(d.D, storage,
-             hipLaunchKernelGGL((k_fill_fin<DD, TT>), dim3(nfill + nfin), dim3(256), 0, s, d, cur, slot, nfill, fin ? 1 : 0));
+    if (fin && (d.flags & kFlagImplicit))
+        DISPATCH(d.D, storage,
+                 hipLaunchKernelGGL((k_fill_fin<DD, TT, true>), dim3(nfill + nfin), dim3(256), 0, s, d, cur, slot, nfill, 1));
+    else
+        DISPATCH(d.D, storage,
+                 hipLaunchKernelGGL((k_fill_fin<DD, TT, false>), dim3(nfill + nfin), dim3(256), 0, s, d, cur, slot, nfill, fin ? 1 : 0));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nfill == 0) return e;
     if (d.alpha < 1.0) {

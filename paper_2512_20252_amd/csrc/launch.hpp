@@ -17,10 +17,11 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
 hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const Tile &t, hipStream_t s);
 // launches over several solves: the 2D update of solves sharing (storage, V,
 // TX, outer walls or not), and the three fill phases of solves sharing (D,
-// storage)
+// storage); implicit: some solve of the fill batch has the semi-implicit
+// collision and a moment finish in it
 hipError_t launch_update2d_batch(int storage, int V, int TX, bool walls, const BatchArgs &a, hipStream_t s);
 hipError_t launch_fill_batch(int D, int storage, const BatchArgs &fin, const BatchArgs &spec, const BatchArgs &ghost,
-                             hipStream_t s);
+                             bool implicit, hipStream_t s);
 // the FP64 forms of the two above, defined in their own translation unit
 hipError_t launch_update2d_f64(const Dev &d, int V, int TX, int cur, int slot, int LY, int ntx, int nys, int ncv,
                                dim3 grid, dim3 block, hipStream_t s);
