@@ -31,6 +31,8 @@
 #define OR_FREESTREAM 0
 #define OR_PERIODIC 1
 #define OR_WALLS 2 /* 2D: diffuse walls on all four sides, the side y = hi moving along x */
+/* 2D: specular walls on all four sides (reading R32) */
+#define OR_SPECULAR 3
 
 #define OR_G_NONE 0
 #define OR_G_CIRCLE 1
@@ -50,6 +52,16 @@
  * Shakhov relaxation taken implicitly with the moments of the transported
  * state */
 #define OR_FLAG_IMPLICIT 4u
+/* reading R28(2) as an option: the ghost-side face value is taken on the
+ * shifted-point -> wall line no further than the wall */
+#define OR_FLAG_FACE_LIMIT 8u
+/* ablation of Section 3.3.3: the intermediate ghost value is the naive
+ * linear extrapolation of donor and auxiliary cell along the pair's axis
+ * instead of the upwind-weighted surface-cell interpolation */
+#define OR_FLAG_NAIVE 16u
+/* ablation: no donor slope (reading R10 on every pair), the shifted-point
+ * value is the donor value */
+#define OR_FLAG_NO_AUX 32u
 
 /* velocity-node classes of one pair (Section 3.2.3): fully incident ("gas"),
  * fully reflected ("solid"), cut with node on the incident side (set G) and
@@ -75,12 +87,17 @@ typedef struct {
     int flags;
     double lid_u; /* OR_WALLS: velocity of the wall at y = hi, along x */
     double vstretch; /* OR_RULE_STRETCHED: beta */
+    /* body wall velocity at the wall point x_w: Uw + Ow x (x_w - centre),
+     * a translation plus a rigid rotation about the geometry centre (in 2D
+     * only Ow[2] acts); the wall Maxwellian of Section 2.3 moves with it */
+    double Uw[3], Ow[3];
 } or_case;
 
 typedef struct {
     int gc, dc, ac; /* ghost, donor, auxiliary cell (ac = -1: none) */
     int axis, sign; /* dc = gc + sign * e_axis */
     double xw[3], nw[3], xsp[3];
+    double uw[3]; /* wall velocity at x_w */
     int ns;
     int sc[26];
     double r[26][3], rh[26][3];
@@ -618,12 +635,15 @@ void *or_create(const or_case *cs, int *err)
             for (int a = 0; a < D; ++a)
                 if (ijk[a] < 3 || ijk[a] > cs->n[a] - 4) *err = 2;
     }
-    if (cs->outer == OR_WALLS && D != 2) *err = 1;
+    if ((cs->outer == OR_WALLS || cs->outer == OR_SPECULAR) && D != 2) *err = 1;
+    if (cs->outer == OR_SPECULAR)
+        for (int a = 0; a < D; ++a)
+            if (cs->vlo[a] != -cs->vhi[a]) *err = 1; /* mirrored nodes must be nodes */
     if (*err) {
         or_destroy(s);
         return NULL;
     }
-    if (cs->outer == OR_WALLS)
+    if (cs->outer == OR_WALLS || cs->outer == OR_SPECULAR)
         for (int A = 0; A < s->NA; ++A)
             s->wgh[A] = (double *)calloc((size_t)2 * (cs->n[0] + cs->n[1]) * s->NV, sizeof(double));
     /* pairs: one per (ghost, fluid face neighbour), ordered by ghost index,
@@ -665,13 +685,21 @@ void *or_create(const or_case *cs, int *err)
                 for (int b = 0; b < 3; ++b) p->xw[b] = xg[b];
                 p->xw[a] = seg_root(s, xg, xd, a);
                 normal(s, p->xw, p->nw);
+                {
+                    double r[3] = {0, 0, 0};
+                    for (int b = 0; b < D; ++b) r[b] = p->xw[b] - cs->gcen[b];
+                    const double *O = cs->Ow;
+                    double ox[3] = {O[1] * r[2] - O[2] * r[1], O[2] * r[0] - O[0] * r[2], O[0] * r[1] - O[1] * r[0]};
+                    for (int b = 0; b < 3; ++b) p->uw[b] = b < D ? cs->Uw[b] + ox[b] : 0.0;
+                }
                 /* shifted point y_sp = y_w + (y_dc - y_gc)/2 (shifted-point equation) */
                 for (int b = 0; b < 3; ++b) p->xsp[b] = p->xw[b];
                 p->xsp[a] = p->xw[a] + (xd[a] - xg[a]) / 2.0;
                 /* auxiliary cell next to the donor along the same axis */
                 int an[3] = {nb[0], nb[1], nb[2]};
                 an[a] += sg;
-                p->ac = (in_grid(s, an) && !s->solid[cell_id(s, an)]) ? cell_id(s, an) : -1;
+                p->ac = (in_grid(s, an) && !s->solid[cell_id(s, an)] && !(cs->flags & OR_FLAG_NO_AUX)) ? cell_id(s, an)
+                                                                                                   : -1;
                 /* surface cells: fluid cells of the Moore neighbourhood */
                 p->ns = 0;
                 for (int dz = (D == 3 ? -1 : 0); dz <= (D == 3 ? 1 : 0); ++dz)
@@ -884,13 +912,15 @@ static double vel_interp(const or_state *s, const double *g, const double v[3])
     return acc;
 }
 
-/* wall density and wall distribution at one wall point with normal n,
- * from the incident distribution fi and its mirrored part fs (arrays offset
- * by o): zero net normal mass flux with cut-cell weights (cut-cell
- * no-penetration equation; readings R2, R3), Maxwell reflection with
- * accommodation alpha, general wall condition and cut-cell blend */
-static void wall_distribution(const or_state *s, const double n[3], const unsigned char *cls, const double *wg,
-                              double *const fi[2], double *const fs[2], size_t o, double *rhow, double *const fw[2])
+/* wall density and wall distribution at one wall point with normal n and
+ * wall velocity uw, from the incident distribution fi and its mirrored part
+ * fs (arrays offset by o): zero net normal mass flux with cut-cell weights
+ * (cut-cell no-penetration equation; readings R2, R3), Maxwell reflection
+ * with accommodation alpha and the wall Maxwellian at (uw, T_w) (Section
+ * 2.3), general wall condition and cut-cell blend */
+static void wall_distribution(const or_state *s, const double n[3], const double uw[3], const unsigned char *cls,
+                              const double *wg, double *const fi[2], double *const fs[2], size_t o, double *rhow,
+                              double *const fw[2])
 {
     int D = s->D, NV = s->NV;
     double Tw = s->c.Tw, al = s->c.alpha;
@@ -901,7 +931,7 @@ static void wall_distribution(const or_state *s, const double n[3], const unsign
         double dn = 0.0, x2 = 0.0;
         for (int b = 0; b < D; ++b) {
             dn += x[b] * n[b];
-            x2 += x[b] * x[b];
+            x2 += (x[b] - uw[b]) * (x[b] - uw[b]);
         }
         double Hw = hw_pref * exp(-x2 / Tw);
         if (cls[k] == CL_GAS) {
@@ -920,7 +950,7 @@ static void wall_distribution(const or_state *s, const double n[3], const unsign
     for (int A = 0; A < s->NA; ++A)
         for (int k = 0; k < NV; ++k) {
             double x2 = 0.0;
-            for (int b = 0; b < D; ++b) x2 += s->xi[3 * k + b] * s->xi[3 * k + b];
+            for (int b = 0; b < D; ++b) x2 += (s->xi[3 * k + b] - uw[b]) * (s->xi[3 * k + b] - uw[b]);
             double Hw = hw_pref * exp(-x2 / Tw);
             if (A == 1) Hw *= 0.5 * Tw;
             double f_i = fi[A][o + k];
@@ -992,6 +1022,12 @@ static void ib_fill(or_state *s)
                     sdc = (f[(size_t)p->ac * NV + k] - fdc) / (xc(s, a, aij[a]) - ydc);
                 }
                 double fsp = fdc + sdc * (ysp - ydc);
+                double fgc = 0.0;
+                if (s->c.flags & OR_FLAG_NAIVE) {
+                    /* 2'. naive linear extrapolation of donor and auxiliary
+                     * cell along the axis (Section 3.3.3 ablation) */
+                    fgc = fdc + sdc * (ygc - ydc);
+                } else {
                 /* 2. upwind-weighted ghost interpolation (reading R4 for the sign) */
                 double m2[26], sum = 0.0;
                 for (int j = 0; j < p->ns; ++j) {
@@ -1000,7 +1036,6 @@ static void ib_fill(or_state *s)
                     m2[j] = m * m;
                     sum += m2[j];
                 }
-                double fgc = 0.0;
                 for (int j = 0; j < p->ns; ++j) {
                     double wj;
                     if (s->c.flags & OR_FLAG_NO_UPWIND)
@@ -1010,6 +1045,7 @@ static void ib_fill(or_state *s)
                     double sr = 0.0;
                     for (int b = 0; b < D; ++b) sr += fluid_slope(s, f, p->sc[j], b, k) * p->r[j][b];
                     fgc += wj * (f[(size_t)p->sc[j] * NV + k] - sr);
+                }
                 }
                 /* 3. incident distribution at the intersect point */
                 double fiw = fsp + (fgc - fsp) / (ygc - ysp) * (yw - ysp);
@@ -1025,18 +1061,18 @@ static void ib_fill(or_state *s)
                 for (int k = 0; k < NV; ++k) s->fss[A][o + k] = 0.0;
         }
         double yface = ygc + 0.5 * p->sign * s->dx[a];
-        wall_distribution(s, p->nw, p->cls, p->wg, s->fiw, s->fss, o, &s->rhow[ip], s->fw);
+        wall_distribution(s, p->nw, p->uw, p->cls, p->wg, s->fiw, s->fss, o, &s->rhow[ip], s->fw);
         for (int A = 0; A < s->NA; ++A)
             for (int k = 0; k < NV; ++k) {
                 double fsp = s->fsp[A][o + k], fw = s->fw[A][o + k];
                 double sig = (fw - fsp) / (yw - ysp); /* ghost-side slope (reading R8) */
                 double gval = fsp + sig * (ygc - ysp);
                 /* reading R28: the ghost value and the face value stay
-                 * non-negative, and the face value, taken on the same line,
-                 * goes no further than the wall value when the face lies
-                 * beyond the wall */
+                 * non-negative; with the face limit option the face value,
+                 * taken on the same line, goes no further than the wall
+                 * value when the face lies beyond the wall */
                 double t = (yface - ysp) / (yw - ysp);
-                if (t > 1.0) t = 1.0;
+                if ((s->c.flags & OR_FLAG_FACE_LIMIT) && t > 1.0) t = 1.0;
                 double fval = fsp + (fw - fsp) * t;
                 s->gh[A][o + k] = gval < 0.0 ? 0.0 : gval;
                 s->fc[A][o + k] = fval < 0.0 ? 0.0 : fval;
@@ -1044,8 +1080,8 @@ static void ib_fill(or_state *s)
     }
 }
 
-/* OR_WALLS: ghost row of boundary cell (i, j) for the wall on side `side`
- * of axis a */
+/* OR_WALLS, OR_SPECULAR: ghost row of boundary cell (i, j) for the wall on
+ * side `side` of axis a */
 static size_t wall_row(const or_state *s, int a, int side, const int ijk[3])
 {
     const int nx = s->c.n[0], ny = s->c.n[1];
@@ -1095,6 +1131,38 @@ static void wall_fill(or_state *s)
     free(bw);
 }
 
+/* Specular outer walls (reading R32: the wall model of Section 2.3 with
+ * alpha = 0 at the domain faces, in the form of reading R29).  For each
+ * boundary cell and wall, the ghost layer holds on the velocities leaving
+ * the wall the cell's own value at the mirrored velocity (the velocity with
+ * its normal component reversed, a node of the symmetric velocity grid),
+ * and on the others the cell's own value; both ghost layers are equal.  The
+ * face values of a velocity and of its mirror are then the same cell value,
+ * so the walls pass no mass and no energy. */
+static void specular_fill(or_state *s)
+{
+    const int NV = s->NV;
+    for (int a = 0; a < 2; ++a)
+        for (int sd = -1; sd <= 1; sd += 2) {
+            const int nb = s->c.n[1 - a];
+            for (int b = 0; b < nb; ++b) {
+                int ijk[3] = {0, 0, 0};
+                ijk[a] = sd < 0 ? 0 : s->c.n[a] - 1;
+                ijk[1 - a] = b;
+                const size_t o = (size_t)cell_id(s, ijk) * NV;
+                const size_t r = wall_row(s, a, sd, ijk) * NV;
+                for (int k = 0; k < NV; ++k) {
+                    const double xn = sd * s->xi[3 * k + a]; /* > 0: toward the wall */
+                    int id[2] = {k % s->c.vn[0], k / s->c.vn[0]};
+                    id[a] = s->c.vn[a] - 1 - id[a];
+                    const int km = xn < 0.0 ? id[0] + s->c.vn[0] * id[1] : k;
+                    s->wgh[0][r + k] = s->f[0][o + km];
+                    s->wgh[1][r + k] = s->f[1][o + km];
+                }
+            }
+        }
+}
+
 /* value seen by fluid cell c at c + side*e_a; kind: 0 fluid, 1 outer
  * freestream or wall ghost, 2 immersed-boundary ghost.  *nbc returns the fluid
  * neighbour index (after periodic wrap) or -1. */
@@ -1109,7 +1177,7 @@ static double nb_value(const or_state *s, int A, int c, int a, int side, int k, 
             *nbc = -1;
             return s->fs[A][k];
         }
-        if (s->c.outer == OR_WALLS) {
+        if (s->c.outer == OR_WALLS || s->c.outer == OR_SPECULAR) {
             int bc[3];
             cell_ijk(s, c, bc);
             *kind = 1;
@@ -1242,6 +1310,7 @@ void or_step(void *h, int n)
         double dt = time_step(s);
         ib_fill(s);
         if (s->c.outer == OR_WALLS) wall_fill(s);
+        if (s->c.outer == OR_SPECULAR) specular_fill(s);
         update(s, dt);
         if (s->c.flags & OR_FLAG_IMPLICIT) implicit_relax(s, dt);
         s->dt = dt;
@@ -1513,7 +1582,7 @@ double or_wall_distribution(void *h, const double *n3, const double *fi0, const 
     for (int A = 0; A < s->NA; ++A)
         if (s->c.alpha < 1.0) specular_part(s, n3, fi[A], fs[A]);
     double rw;
-    wall_distribution(s, n3, cls, wg, fi, fs, 0, &rw, fw);
+    wall_distribution(s, n3, s->c.Uw, cls, wg, fi, fs, 0, &rw, fw);
     free(cls);
     free(wg);
     free(fs[0]);

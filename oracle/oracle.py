@@ -16,9 +16,9 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
-OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
+OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
 RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2}
-FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4}
+FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4, "face_limit": 8, "naive": 16, "no_aux": 32}
 
 CL_GAS, CL_SOLID, CL_CUT_G, CL_CUT_S = 0, 1, 2, 3
 
@@ -41,7 +41,7 @@ class _Case(ctypes.Structure):
                 ("Pr", ctypes.c_double), ("gam", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("Tw", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
                 ("avhs", ctypes.c_double), ("flags", ctypes.c_int), ("lid_u", ctypes.c_double),
-                ("vstretch", ctypes.c_double)]
+                ("vstretch", ctypes.c_double), ("Uw", ctypes.c_double * 3), ("Ow", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -125,6 +125,10 @@ def _case_struct(case):
     c.flags = fl
     c.lid_u = case.get("lid_u", 0.0)
     c.vstretch = case.get("vstretch", 0.0)
+    Uw, Ow = case.get("U_w", (0.0, 0.0, 0.0)), case.get("Omega_w", (0.0, 0.0, 0.0))
+    for a in range(3):
+        c.Uw[a] = Uw[a] if a < len(Uw) else 0.0
+        c.Ow[a] = Ow[a] if a < len(Ow) else 0.0
     return c
 
 
