@@ -70,6 +70,35 @@ def _alu(workload, precision, tile, avg_ms):
             "lane_instr_per_update": rec["valu_lane_instr_per_update"], "busy_frac_counter": rec["valu_busy_frac"]}
 
 
+def copy_ceiling(gib=1.0, reps=5):
+    """Practical HBM ceiling: the library's plain streaming copy kernel
+    (every byte read once and written once) over two buffers of `gib` GiB,
+    timed with HIP events on its stream; GB/s counts read plus written
+    bytes, the best of `reps` launches."""
+    import torch
+    from paper_2512_20252_amd import ibdvm
+
+    n = int(gib * 2 ** 30)
+    src = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    ibdvm.stream_copy(src, dst, stream)
+    best = None
+    for _ in range(reps):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        ibdvm.stream_copy(src, dst, stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        best = ms if best is None else min(best, ms)
+    assert torch.equal(src[:1024], dst[:1024])
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": 2 * n / (best * 1e-3) / 1e9, "bytes_each_way": n, "ms": best,
+            "kernel": "k_stream_copy (ibdvm_stream_copy), 16-byte lanes"}
+
+
 def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     """Warm-up steps, then `steps` eager steps with kernel timing (HIP events
     around each launch on the solve's stream), then the timed region: the
@@ -179,7 +208,10 @@ def hypersonic(steps, warmup):
 
     out = {"workload": "2D airfoil and ellipse at Ma 5, Kn 0.05, alpha 0.8, 512x384 cells, 64x64 velocity nodes "
                        "on [-10,10]^2", "steps": steps, "warmup": warmup}
+    out["f32_storage"] = "f itself (IBDVM_FLAG_F32_ABSOLUTE): the wakes empty toward vacuum, where offsets " \
+                         "from the freestream Maxwellian would cancel the digits of f"
     for body, case in zip(("airfoil", "ellipse"), cases.hypersonic_bodies(0)):
+        case = cases.case(**dict(case, flags=("f32_absolute",)))
         for prec in ("f64", "f32"):
             s = ibdvm.Solver(case, precision=prec)
             s.init_freestream()
@@ -416,19 +448,20 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48):
             else:
                 s.init_freestream_hashed(0, 1e-3)  # a host array of the 3D state would be large
             g = ibdvm.Graph(s, block)
-            cd_prev, steps, t = None, 0, time.perf_counter()
+            cd_prev, change, steps, t = None, None, 0, time.perf_counter()
             limit = cap if prec == "f64" else row["f64"]["steps"]
             while steps < limit:
                 g.launch()
                 steps += block
                 cd = s.surface_forces()[1]
-                if prec == "f64" and cd_prev is not None and abs(cd - cd_prev) < rtol * abs(cd):
-                    break
+                change = abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None
                 cd_prev = cd
+                if prec == "f64" and change is not None and change < rtol:
+                    break
             wall = time.perf_counter() - t
-            row[prec] = {"CD": cd, "steps": steps, "converged": abs(cd - cd_prev) < rtol * abs(cd),
-                         "last_rel_change": abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None,
-                         "updates_per_s": s.nfluid * s.NV * steps / wall}
+            # the change over the last replay, taken before cd_prev moved on
+            row[prec] = {"CD": cd, "steps": steps, "converged": change is not None and change < rtol,
+                         "last_rel_change": change, "updates_per_s": s.nfluid * s.NV * steps / wall}
             print(f"precision sweep: {label} {prec}: C_D {cd:.8f} after {steps} steps", file=sys.stderr, flush=True)
             g.close()
             s.close()
@@ -440,7 +473,50 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48):
     return out
 
 
+def fixed_cd_error(block=100):
+    """FP32 storage against FP64 at a fixed C_D error: the cylinder's Kn x Ma
+    sweep at the 64^2 x 24^2 reduction, each case run on the GPU in both
+    forms for the step count at which the FP64 oracle's C_D had converged
+    (|dC_D| < 1e-6 per 100 steps), against the oracle's converged C_D stored
+    in tests/golden by a script that runs only the oracle."""
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    path = os.path.join(ROOT, "tests", "golden", "converged_cd_cylinder_64x64_v24x24.json")
+    if not os.path.exists(path):
+        return None
+    rows = json.load(open(path))["rows"]
+    out = {"workload": "2D cylinder R=0.5 on [-8,8]^2, 64x64 cells, 24x24 velocity nodes on [-6,6]^2, "
+                       "Kn {0.01,0.1,1} x Ma {0.3,2}, to the oracle's converged step count",
+           "reference": "FP64 CPU oracle, converged C_D (tests/golden/converged_cd_cylinder_64x64_v24x24.json)",
+           "cases": []}
+    for row in rows:
+        c = cases.cylinder_256(Kn=row["Kn"], Ma=row["Ma"], n=64, vn=24)
+        u = cases.noise(c, row["seed"])
+        r = {"Kn": row["Kn"], "Ma": row["Ma"], "steps": row["steps"], "CD_oracle": row["C_D"]}
+        for prec in ("f64", "f32"):
+            s = ibdvm.Solver(c, precision=prec, stream=torch.cuda.Stream())
+            s.init_freestream(u, 1e-3)
+            g = ibdvm.Graph(s, block)
+            t = time.perf_counter()
+            for _ in range(row["steps"] // block):
+                g.launch()
+            s.step(row["steps"] % block)
+            cd = s.surface_forces()[1]
+            r[prec] = {"CD": cd, "dCD_vs_oracle": abs(cd - row["C_D"]), "seconds": time.perf_counter() - t}
+            g.close()
+            s.close()
+        out["cases"].append(r)
+    out["max_dCD_f64_vs_oracle"] = max(r["f64"]["dCD_vs_oracle"] for r in out["cases"])
+    out["max_dCD_f32_vs_oracle"] = max(r["f32"]["dCD_vs_oracle"] for r in out["cases"])
+    return out
+
+
 def cpu_baseline(case, seed=0):
+    """The FP64 oracle on this host: one step of the full workload on all
+    its OpenMP threads, and one step of a 128^2-cell window of the same
+    workload (the same cell size, body and velocity grid on [-4,4]^2) on one
+    thread, each as cell-velocity updates per second."""
     from oracle import oracle as oracle_mod
     from paper_2512_20252_amd import cases
 
@@ -449,15 +525,35 @@ def cpu_baseline(case, seed=0):
     t = time.perf_counter()
     o.step(1)
     dt = time.perf_counter() - t
-    return {"value": o.nfluid * o.NV / dt, "unit": "cell*vel updates/s", "cores": oracle_mod.threads(),
-            "kind": "oracle", "sample": "1 step of the same 256x256 x 48x48 workload (all fluid cells), "
-                                        "OpenMP over cells, sequential velocity sums", "seconds": dt}
+    out = {"value": o.nfluid * o.NV / dt, "unit": "cell*vel updates/s", "cores": oracle_mod.threads(),
+           "kind": "oracle", "sample": "1 step of the same 256x256 x 48x48 workload (all fluid cells), "
+                                       "OpenMP over cells, sequential velocity sums", "seconds": dt}
+    del o
+    window = cases.case(**dict(case, n=(128, 128), lo=(-4.0, -4.0), hi=(4.0, 4.0)))
+    nthreads = oracle_mod.threads()
+    oracle_mod.set_threads(1)
+    try:
+        o = oracle_mod.Oracle(window)
+        o.init_freestream(cases.noise(window, seed), 1e-3)
+        t = time.perf_counter()
+        o.step(1)
+        dt1 = time.perf_counter() - t
+        out["one_thread"] = {"value": o.nfluid * o.NV / dt1, "cores": oracle_mod.threads(), "seconds": dt1,
+                             "sample": "1 step of the 128x128-cell window [-4,4]^2 of the workload (same cell "
+                                       "size, body and 48x48 velocity grid)"}
+    finally:
+        oracle_mod.set_threads(nthreads)
+    return out
 
 
-def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
+def serving(nreq, cap, tol, gap_s, max_active=8, seed=0, min_p99=20):
     """Continuous-batching leg: a seeded Poisson stream of mixed 2D solves
-    (FP32 storage) through one server; time-to-converged-C_D percentiles and
-    aggregate updates/s."""
+    (FP32 storage; f itself for Ma > 2, whose wakes empty toward vacuum)
+    through one server; a request converges when C_D changes by less than
+    tol relative over a replay of 100 steps, or stops at the step cap.
+    Time-to-converged-C_D percentiles with their sample counts (p99 only
+    from at least min_p99 samples), the converged fraction and aggregate
+    updates/s."""
     import numpy as np
     import torch
     from paper_2512_20252_amd import cases, ibdvm
@@ -472,7 +568,10 @@ def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
     while len(done) < nreq:
         now = srv.clock() - t0
         while sub < nreq and arrivals[sub] <= now:
-            index[srv.submit(reqs[sub], "f32", seed=sub, amp=1e-3, tol=tol, max_steps=cap)] = sub
+            rq = reqs[sub]
+            if rq["Ma"] > 2.0:
+                rq = cases.case(**dict(rq, flags=("f32_absolute",)))
+            index[srv.submit(rq, "f32", seed=sub, amp=1e-3, tol=tol, max_steps=cap)] = sub
             sub += 1
         new = srv.poll(block=False)
         for r in new:
@@ -485,12 +584,16 @@ def serving(nreq, cap, tol, gap_s, max_active=8, seed=0):
     lat = np.array([r["t_done"] - r["t_submit"] for r in done])
     conv = np.array([r["converged"] == 1 for r in done])
     ups = sum(r["updates"] for r in done) / (max(r["t_done"] for r in done) - min(r["t_submit"] for r in done))
-    pct = lambda x, q: float(np.percentile(x, q)) if len(x) else None
-    return {"requests": nreq, "precision": "f32", "step_cap": cap, "tol_dCD_per_100_steps": tol,
+    ok = np.array([r["status"] == 0 for r in done])
+    pct = lambda x, q, m=1: float(np.percentile(x, q)) if len(x) >= m else None
+    return {"requests": nreq, "precision": "f32", "step_cap": cap,
+            "criterion": f"|C_D(n) - C_D(n-100)| < {tol:g} |C_D(n)|", "rel_tol_dCD_per_100_steps": tol,
             "mean_arrival_gap_s": gap_s, "max_active": max_active, "workspace_GiB": ws / 2 ** 30,
-            "converged": int(conv.sum()), "failed": int(sum(r["status"] != 0 for r in done)),
-            "p50_time_to_converged_s": pct(lat[conv], 50), "p99_time_to_converged_s": pct(lat[conv], 99),
-            "p50_time_to_done_s": pct(lat, 50), "p99_time_to_done_s": pct(lat, 99),
+            "converged": int(conv.sum()), "converged_fraction": float(conv.mean()),
+            "capped": int((~conv & ok).sum()), "failed": int((~ok).sum()),
+            "p50_time_to_converged_s": pct(lat[conv], 50), "p99_time_to_converged_s": pct(lat[conv], 99, min_p99),
+            "n_time_to_converged": int(conv.sum()), "p99_min_samples": min_p99,
+            "p50_time_to_done_s": pct(lat, 50), "p99_time_to_done_s": pct(lat, 99, min_p99), "n_time_to_done": len(lat),
             "mean_active": float(np.mean(samples)), "aggregate_updates_per_s": ups,
             "steps": [int(r["steps"]) for r in done],
             "failures": [{"request": index[r["id"]], "status": int(r["status"]), "steps": int(r["steps"]),
@@ -511,6 +614,8 @@ def main():
     ap.add_argument("--serving", type=int, default=12, help="requests in the serving leg (0: skip)")
     ap.add_argument("--serving-cap", type=int, default=2000, help="step cap per serving request")
     ap.add_argument("--serving-gap", type=float, default=0.5, help="mean arrival gap of the serving stream, seconds")
+    ap.add_argument("--serving-tol", type=float, default=1e-4,
+                    help="relative C_D change per 100 steps below which a serving request has converged")
     ap.add_argument("--sphere", type=int, default=96, help="cells per side of the 3D sphere leg (0: skip)")
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
@@ -521,6 +626,8 @@ def main():
     ap.add_argument("--cavity-steps", type=int, default=20)
     ap.add_argument("--implicit-kn", type=float, default=2e-4,
                     help="Knudsen number of the semi-implicit collision leg (0: skip)")
+    ap.add_argument("--no-fixed-cd", action="store_true",
+                    help="skip the converged-C_D comparison of both forms with the oracle (64^2 x 24^2 sweep)")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="add FP32 storage against FP64 over the cylinder's Kn x Ma sweep, run toward convergence")
     ap.add_argument("--sweep-sphere-only", action="store_true", help="run only the sphere case of the precision sweep")
@@ -562,6 +669,7 @@ def main():
     bytes_launch = upd * B_ALG[(r64["dim"], "f64")]
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     traffic = _traffic(workload, "f64", r64["tile"])
+    ceiling = copy_ceiling()
     line = {
         "metric": "cell*vel updates/s & %HBM peak, FP32-store vs FP64 at fixed C_D err; p50/p99",
         "value": value,
@@ -582,6 +690,9 @@ def main():
         "value_eager": upd * args.steps / (r64["ms_eager"] * 1e-3) if r64["ms_eager"] else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "copy_ceiling_GBs": ceiling["GBs"], "frac_of_copy_ceiling": achieved / ceiling["GBs"],
+                     "traffic_GBs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "copy_ceiling": ceiling,
                      "alu": _alu(workload, "f64", r64["tile"], avg_ms),
                      "kernel": "k_update2d<double, %d, %d, false>" % tuple(r64["tile"][:2]),
                      "timing": "HIP events around each update launch on its stream, over K eager steps of this run "
@@ -595,7 +706,8 @@ def main():
         line["precision_form_tile"] = r32["tile"]
         v32 = upd * args.steps / (r32["ms"] * 1e-3)
         avg32 = r32["prof"]["update_ms"] / max(r32["prof"]["update_launches"], 1)
-        line["precision_form"] = {"dtype": "f32 storage, f64 moments/equilibrium/wall", "value": v32,
+        line["precision_form"] = {"dtype": "f32 storage of f minus the freestream Maxwellian (offsets), "
+                                           "f64 moments/equilibrium/wall", "value": v32,
                                   "ratio_vs_f64": v32 / value, "dCD_vs_f64": abs(r32["cd"] - r64["cd"]),
                                   "CD_f64": r64["cd"], "update_avg_launch_ms": avg32,
                                   "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9,
@@ -611,6 +723,12 @@ def main():
         line["cavity"] = cavity(args.cavity, args.cavity_vn, args.cavity_steps, 2, {"f64": None, "f32": None})
     if args.implicit_kn > 0:
         line["implicit_collision"] = implicit_collision(args.implicit_kn, 50, 3)
+    if not args.no_fixed_cd:
+        fc = fixed_cd_error()
+        if fc is not None:
+            line["fixed_cd_error"] = fc
+            if "precision_form" in line:
+                line["precision_form"]["max_dCD_vs_oracle_converged"] = fc["max_dCD_f32_vs_oracle"]
     if args.precision_sweep:
         line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP if not args.sweep_sphere_only else [], 1e-5,
                                                   20000)
@@ -619,7 +737,7 @@ def main():
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:
-        line["serving"] = serving(args.serving, args.serving_cap, 1e-4, args.serving_gap)
+        line["serving"] = serving(args.serving, args.serving_cap, args.serving_tol, args.serving_gap)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(case)
     print(json.dumps(line), flush=True)

@@ -54,15 +54,20 @@ typedef enum {
     IBDVM_E_DEVICE = 4,      /* a HIP runtime call failed */
     IBDVM_E_UNSTABLE = 5,    /* the device health word reported NaN, rho<=0 or T<=0 */
     IBDVM_E_UNSUPPORTED = 6, /* combination not implemented */
-    IBDVM_E_STATE = 7        /* context unusable (host-only or previously unstable) */
+    IBDVM_E_STATE = 7,       /* context unusable (host-only or previously unstable) */
+    IBDVM_E_CANCELLED = 8    /* serving: the request was cancelled (ibdvm_server_cancel) */
 } ibdvm_status;
 
 /* outer boundary of the box: freestream ghost cells (Section 4 external
  * flows), periodic, or (2D only) diffuse walls at T_w on all four sides with
  * the wall y = hi moving along +x at lid_u (lid-driven cavity, Section 4):
  * the wall model of Section 2.3 applied at the domain faces, with the wall
- * density from zero normal mass flux through each boundary face */
-enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1, IBDVM_OUTER_WALLS = 2 };
+ * density from zero normal mass flux through each boundary face; or (2D
+ * only) specular walls on all four sides (the Section 2.3 model with
+ * alpha = 0): a boundary cell's velocities leaving the wall see its own
+ * value at the mirrored velocity, so the walls pass no mass and no energy
+ * (needs a velocity grid symmetric about 0, which every grid here is) */
+enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1, IBDVM_OUTER_WALLS = 2, IBDVM_OUTER_SPECULAR = 3 };
 enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1, IBDVM_RULE_STRETCHED = 2 };
 enum {
     IBDVM_GEOM_NONE = 0,
@@ -83,6 +88,26 @@ enum {
      * Section 2.1); dt = cfl / sum_a max|xi_a|/dx_a, without the
      * relaxation-time bound */
     IBDVM_FLAG_IMPLICIT_COLLISION = 1u << 2,
+    /* positivity option of the ghost-side face value: taken on the
+     * shifted-point -> wall line of Section 3.2.1 no further than the wall
+     * when the face lies beyond it (inside the solid); without it the face
+     * value is that line's value at the face (second order on smooth data) */
+    IBDVM_FLAG_FACE_LIMIT = 1u << 3,
+    /* ablation of Section 3.3.3: the intermediate ghost value is the naive
+     * linear extrapolation of donor and auxiliary cell along the pair's axis,
+     * f_gc = 2 f_dc - f_ac, instead of the upwind-weighted surface-cell
+     * interpolation of Section 3.2.2 */
+    IBDVM_FLAG_NAIVE_EXTRAPOLATION = 1u << 4,
+    /* ablation: no donor slope, the shifted-point value of Section 3.2.1 is
+     * the donor value (the construction used where no fluid auxiliary cell
+     * exists, applied to every pair) */
+    IBDVM_FLAG_NO_AUX_SLOPE = 1u << 5,
+    /* 2D FP32 storage of f itself instead of its offset from the freestream
+     * Maxwellian (the default, whose rounding scales with the departure
+     * from the freestream): for flows with near-vacuum regions, such as
+     * hypersonic wakes, where f is far below the freestream value at the
+     * freestream's velocities and the offset would cancel its digits */
+    IBDVM_FLAG_F32_ABSOLUTE = 1u << 6,
     IBDVM_FLAG_HOST_ONLY = 1u << 8   /* build the geometry tables only; no device work */
 };
 
@@ -126,11 +151,18 @@ typedef struct {
     void *workspace;        /* device buffer, >= ibdvm_footprint() bytes, 256-byte aligned */
     size_t workspace_bytes;
     void *stream;           /* hipStream_t */
+    /* velocity of the body's wall (Section 2.3 wall Maxwellian at (U_w,
+     * T_w)) at wall point x_w: U_w + Omega_w x (x_w - centre), a translation
+     * plus a rigid rotation about the geometry centre (2D: only Omega_w[2]
+     * acts).  The velocity cells are still split by xi . n = 0 (Section
+     * 3.2.3); zero for a wall at rest. */
+    double U_w[3];
+    double Omega_w[3];
 } ibdvm_opts;
 
 /* one wall point per ghost-donor pair: intersect point, unit normal n (into
  * the gas), wall density rho_w (Section 3.2.3), and moments of the wall
- * distribution f*_w (wall at rest, xi_n = xi . n): pressure p_w = sum w
+ * distribution f*_w in the frame of the grid (xi_n = xi . n): pressure p_w = sum w
  * xi_n^2 f*_w, shear stress tau_w = sum w xi_n (xi - xi_n n) f*_w (the
  * tangential part of the momentum flux), normal heat flux q_n = 1/2 sum w
  * xi_n (|xi|^2 h + b) (2D; 3D: |xi|^2 f), and the pressure coefficient of
@@ -278,6 +310,13 @@ ibdvm_status ibdvm_autotune(ibdvm_ctx *ctx, int32_t reps, int32_t out[3]);
 ibdvm_status ibdvm_profile(ibdvm_ctx *ctx, int32_t enable);
 ibdvm_status ibdvm_profile_read(ibdvm_ctx *ctx, double ms[2], int64_t counts[2]);
 
+/* Measurement: enqueues a plain streaming copy of `bytes` bytes from src to
+ * dst (device pointers, 16-byte aligned, size a multiple of 16, buffers not
+ * overlapping) on stream: every byte read once and written once with
+ * coalesced 16-byte accesses.  Its rate is the practical HBM ceiling the
+ * update kernels are compared with.  Only enqueues. */
+ibdvm_status ibdvm_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Thread-local message describing the last failure on this thread. */
 const char *ibdvm_last_error(void);
 
@@ -319,8 +358,8 @@ void ibdvm_graph_destroy(ibdvm_graph *graph);
  * stream and captured graph of K steps, concurrently with the group.  A new
  * solve is created on its own stream while replays run and joins the group
  * at its next replay.  After each replay the C_D of every solve in it is
- * checked; a solve finishes when |C_D(n) - C_D(n - K)| < tol (tol <= 0:
- * never) or max_steps steps are done, and its memory and slot go back to the
+ * checked; a solve finishes when |C_D(n) - C_D(n - K)| < tol |C_D(n)|
+ * (tol <= 0: never) or max_steps steps are done, and its memory and slot go back to the
  * queue.  A tile shape per (grid, velocity grid, precision)
  * is chosen once by ibdvm_autotune and reused.  Single-threaded: one thread
  * submits and polls. */
@@ -352,6 +391,14 @@ ibdvm_status ibdvm_server_submit(ibdvm_server *srv, const ibdvm_grid *grid, cons
  * admits queued requests, relaunches.  block != 0 waits until at least one
  * solve finishes (or none is active).  Returns up to cap finished results. */
 ibdvm_status ibdvm_server_poll(ibdvm_server *srv, int32_t block, ibdvm_result *done, int32_t cap, int32_t *n_done);
+/* Cancels request id, queued or active.  A queued request leaves the queue;
+ * an active one waits for its replay in flight to end and is released: its
+ * workspace block and slot go back to the queue at the next poll.  Either way
+ * poll returns its result with status IBDVM_E_CANCELLED and the steps done
+ * (moments_out is not written).  IBDVM_E_INVALID_ARG if no queued or active
+ * request has this id (for instance one already finished).  Creating a
+ * server, queueing and cancelling queued requests touch no device. */
+ibdvm_status ibdvm_server_cancel(ibdvm_server *srv, int64_t id);
 /* out = queued, active, finished, workspace bytes in use, workspace bytes. */
 ibdvm_status ibdvm_server_info(const ibdvm_server *srv, int64_t out[5]);
 double ibdvm_server_clock(const ibdvm_server *srv);

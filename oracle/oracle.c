@@ -1468,6 +1468,13 @@ void or_freestream(void *h, double *f0, double *f1)
 
 double or_mu0(void *h) { return ((or_state *)h)->mu0; }
 
+/* threads the OpenMP loops of the oracle use from now on (CPU timing at a
+ * given core count) */
+void or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
 /* threads the OpenMP loops of the oracle use */
 int or_threads(void)
 {

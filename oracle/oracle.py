@@ -18,7 +18,10 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
 RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2}
-FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4, "face_limit": 8, "naive": 16, "no_aux": 32}
+# "f32_absolute" selects how the library stores FP32 values; the FP64 oracle
+# has no such choice and ignores it
+FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4, "face_limit": 8, "naive": 16, "no_aux": 32,
+         "f32_absolute": 0}
 
 CL_GAS, CL_SOLID, CL_CUT_G, CL_CUT_S = 0, 1, 2, 3
 
@@ -73,6 +76,7 @@ def lib():
         L.or_freestream.argtypes = [vp, dp, dp]
         L.or_mu0.argtypes = [vp]
         L.or_mu0.restype = ctypes.c_double
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_threads.argtypes = []
         L.or_threads.restype = ctypes.c_int
         L.or_index_sets.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_int32),
@@ -135,6 +139,11 @@ def _case_struct(case):
 def threads():
     """OpenMP threads the oracle's cell loops run on."""
     return int(lib().or_threads())
+
+
+def set_threads(n):
+    """Run the oracle's cell loops on n OpenMP threads from now on."""
+    lib().or_set_threads(int(n))
 
 
 class Oracle:

@@ -33,8 +33,14 @@ constexpr int kResVars = 5;
 // sum w xi f [3], sum w (|xi|^2 h + b) (3D: |xi|^2 f)
 constexpr int kForceWords = 13;
 
-// Dev::flags bit of the semi-implicit collision (IBDVM_FLAG_IMPLICIT_COLLISION)
+// Dev::flags bits: semi-implicit collision (IBDVM_FLAG_IMPLICIT_COLLISION),
+// face limit, naive extrapolation (IBDVM_FLAG_FACE_LIMIT,
+// IBDVM_FLAG_NAIVE_EXTRAPOLATION)
 constexpr unsigned kFlagImplicit = 1u << 2;
+constexpr unsigned kFlagFaceLimit = 1u << 3;
+constexpr unsigned kFlagNaive = 1u << 4;
+// Dev::outer values
+enum { kOuterFreestream = 0, kOuterPeriodic = 1, kOuterWalls = 2, kOuterSpecular = 3 };
 constexpr int kChunk = 64;       // velocity nodes per wavefront
 constexpr int kFillChunk = 256;  // velocity nodes per ghost-fill workgroup
 constexpr int kMaxVn = 256;
@@ -73,7 +79,12 @@ struct Dev {
     const double *w;
     const double *fs[2];
     const void *fsT[2];  // freestream rows in the storage type
+    // 2D FP32 storage: reference the stored values are offsets from (the
+    // freestream rows, or zeros); foff = 1 when it is the freestream
+    const double *fr[2];
+    int foff, pad2;
     const double *hw;
+    const double *hwp;  // moving body wall: [pair][node] unit wall Maxwellian at the pair's wall velocity; else null
     void *f[2][2];  // [buffer][array]
     double *cellp;
     double *cellq;  // 2D: kQWords per cell

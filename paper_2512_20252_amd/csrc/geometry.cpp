@@ -9,6 +9,8 @@
 // integration of exact cross-sections (3D).  Compile without FP contraction.
 #include "geometry.hpp"
 
+#include "ibdvm.h"
+
 #include <algorithm>
 #include <cmath>
 
@@ -354,7 +356,18 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
                 for (int b = 0; b < 3; ++b) pr.xsp[b] = pr.xw[b];
                 pr.xsp[a] = pr.xw[a] + 0.5 * (xd_a - xg[a]);
                 int ai = ijk[a] + 2 * sg;
-                pr.ac = (ai >= 0 && ai < p.n[a] && !solid(c + 2 * sg * stride[a])) ? c + 2 * sg * stride[a] : -1;
+                // auxiliary cell next to the donor (none with the no-donor-slope ablation)
+                const bool no_aux = (p.flags & IBDVM_FLAG_NO_AUX_SLOPE) != 0;
+                pr.ac = (ai >= 0 && ai < p.n[a] && !solid(c + 2 * sg * stride[a]) && !no_aux) ? c + 2 * sg * stride[a]
+                                                                                              : -1;
+                // wall velocity at the intersect point: translation plus rotation about the centre
+                {
+                    double r[3] = {0, 0, 0};
+                    for (int b = 0; b < D; ++b) r[b] = pr.xw[b] - p.gcen[b];
+                    const double *O = p.Ow;
+                    const double rot[3] = {O[1] * r[2] - O[2] * r[1], O[2] * r[0] - O[0] * r[2], O[0] * r[1] - O[1] * r[0]};
+                    for (int b = 0; b < 3; ++b) pr.uw[b] = b < D ? p.Uw[b] + rot[b] : 0.0;
+                }
                 // surface cells: fluid members of the Moore neighbourhood
                 pr.ns = 0;
                 int zr = D == 3 ? 1 : 0;

@@ -28,6 +28,8 @@ struct Problem {
     int gkind = 0;
     double gcen[3] = {0, 0, 0}, gsize[3] = {0, 0, 0}, aoa = 0;
     uint32_t flags = 0;
+    double Uw[3] = {0, 0, 0}, Ow[3] = {0, 0, 0};  // body wall: translation and rotation about gcen
+    bool moving_wall = false;
 };
 
 struct PairGeom {
@@ -35,6 +37,7 @@ struct PairGeom {
     int sc[kMaxSurface];
     int snb[kMaxSurface][3][2];  // fluid neighbours of each surface cell along each axis (-1: none)
     double xw[3], nw[3], xsp[3];
+    double uw[3];  // wall velocity at x_w
     double r[kMaxSurface][3], rh[kMaxSurface][3];
 };
 

@@ -18,6 +18,10 @@
 #include "launch.hpp"
 
 static_assert(ibdvm::kFlagImplicit == IBDVM_FLAG_IMPLICIT_COLLISION, "device flag bit of the semi-implicit collision");
+static_assert(ibdvm::kFlagFaceLimit == IBDVM_FLAG_FACE_LIMIT, "device flag bit of the face limit");
+static_assert(ibdvm::kFlagNaive == IBDVM_FLAG_NAIVE_EXTRAPOLATION, "device flag bit of the naive extrapolation");
+static_assert(ibdvm::kOuterWalls == IBDVM_OUTER_WALLS && ibdvm::kOuterSpecular == IBDVM_OUTER_SPECULAR &&
+                  ibdvm::kOuterPeriodic == IBDVM_OUTER_PERIODIC, "device codes of the outer boundaries");
 
 namespace {
 
@@ -33,6 +37,8 @@ constexpr double kPi = 3.14159265358979323846;
 
 struct Layout {
     size_t f[2][2], cellp, cellq, part, xi, xa, w, fs, fsT, hw, cflag, pnb, pairs, cls, wg, ghost, face, fiw, fsp, fwall, rhow, fillpart, pforce, ctrl;
+    size_t hwp;      // moving body wall: per pair the unit wall Maxwellian at its wall velocity
+    size_t fr;       // 2D FP32 storage: the reference its values are offsets from
     size_t respart;  // moment-finish workgroups x 2 kResVars
     size_t wallT;    // outer walls: NA x 2(nx + ny) ghost rows in the storage type
     size_t devcopy;  // the context's Dev, read by launches over several solves
@@ -66,6 +72,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision, const ibdvm:
     L.w = take((size_t)g.NV * 8);
     L.fs = take((size_t)2 * g.NV * 8);
     L.fsT = take((size_t)2 * g.NV * es);
+    L.fr = take((size_t)2 * g.NV * 8);
     L.hw = take((size_t)g.NV * 8);
     L.cflag = take((size_t)g.Nc * 4);
     L.pnb = take((size_t)g.Nc * 6 * 4);
@@ -81,7 +88,10 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision, const ibdvm:
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * ibdvm::kForceWords * 8);
     L.respart = take((size_t)((g.Nc + 3) / 4) * 2 * ibdvm::kResVars * 8);
-    L.wallT = take(p.outer == IBDVM_OUTER_WALLS ? (size_t)NA * 2 * (p.n[0] + p.n[1]) * g.NV * es : 0);
+    L.wallT = take(p.outer == IBDVM_OUTER_WALLS || p.outer == IBDVM_OUTER_SPECULAR
+                       ? (size_t)NA * 2 * (p.n[0] + p.n[1]) * g.NV * es
+                       : 0);
+    L.hwp = take(p.moving_wall ? np * g.NV * 8 : 0);
     L.ctrl = take(sizeof(ibdvm::Ctrl));
     L.devcopy = take(sizeof(ibdvm::Dev));
     L.total = off;
@@ -113,9 +123,9 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
             return fail(IBDVM_E_INVALID_ARG, "velocity box must be symmetric about 0");
     }
     if (grid->outer_bc != IBDVM_OUTER_FREESTREAM && grid->outer_bc != IBDVM_OUTER_PERIODIC &&
-        grid->outer_bc != IBDVM_OUTER_WALLS)
+        grid->outer_bc != IBDVM_OUTER_WALLS && grid->outer_bc != IBDVM_OUTER_SPECULAR)
         return fail(IBDVM_E_INVALID_ARG, "unknown outer boundary condition");
-    if (grid->outer_bc == IBDVM_OUTER_WALLS && grid->dim != 2)
+    if ((grid->outer_bc == IBDVM_OUTER_WALLS || grid->outer_bc == IBDVM_OUTER_SPECULAR) && grid->dim != 2)
         return fail(IBDVM_E_UNSUPPORTED, "outer walls are implemented for dim 2 only");
     if (grid->outer_bc == IBDVM_OUTER_WALLS && !std::isfinite(grid->lid_u))
         return fail(IBDVM_E_INVALID_ARG, "lid speed must be finite");
@@ -137,6 +147,13 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
     p.gkind = k;
     p.aoa = geom->aoa_rad;
     p.flags = opts->flags;
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(opts->U_w[a]) || !std::isfinite(opts->Omega_w[a]))
+            return fail(IBDVM_E_INVALID_ARG, "wall velocity must be finite");
+        p.Uw[a] = opts->U_w[a];
+        p.Ow[a] = opts->Omega_w[a];
+        if (p.Uw[a] != 0.0 || p.Ow[a] != 0.0) p.moving_wall = k != IBDVM_GEOM_NONE;
+    }
     if (opts->precision != IBDVM_F64 && opts->precision != IBDVM_F32_STORE) return fail(IBDVM_E_INVALID_ARG, "unknown precision");
     if (!(opts->cfl > 0.0 && opts->cfl <= 1.0)) return fail(IBDVM_E_INVALID_ARG, "cfl must be in (0, 1]");
     if (!(opts->omega_vhs > 0.0 && opts->omega_vhs < 2.5) || !(opts->a_vhs > 0.0))
@@ -371,7 +388,7 @@ ibdvm_status fused_step(ibdvm_ctx *const *cs, int n, hipStream_t stream)
                     for (int i = 0; i < n; ++i) {
                         const ibdvm_ctx *c = cs[i];
                         if (c->prob.dim == 2 && c->precision == prec && c->tile.V == V && c->tile.TX == TX &&
-                            (c->prob.outer == IBDVM_OUTER_WALLS) == (walls == 1))
+                            (c->prob.outer == IBDVM_OUTER_WALLS || c->prob.outer == IBDVM_OUTER_SPECULAR) == (walls == 1))
                             grp.push_back(cs[i]);
                     }
                     for (size_t b = 0; b < grp.size(); b += ibdvm::kMaxBatch) {
@@ -541,6 +558,17 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
         fs[k] = Af * std::exp(-c2);
         fs[(size_t)NV + k] = 0.5 * fs[k];
     }
+    // moving body wall: the unit wall Maxwellian of each pair at its wall velocity
+    std::vector<double> hwp(c->prob.moving_wall ? np * NV : 0);
+    for (size_t ip = 0; ip < np && c->prob.moving_wall; ++ip)
+        for (int k = 0; k < NV; ++k) {
+            double c2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                const double cc = g.xi[3 * k + a] - g.pairs[ip].uw[a];
+                c2 += cc * cc;
+            }
+            hwp[ip * NV + k] = Aw * std::exp(-c2 / T_w);
+        }
     std::vector<ibdvm::DPair> dp(np);
     for (size_t ip = 0; ip < np; ++ip) {
         const ibdvm::PairGeom &p = g.pairs[ip];
@@ -583,7 +611,7 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
             double ws = cl == ibdvm::VC_SOLID ? g.w[k] : (cl >= 2 ? g.w[k] - g.wg[ip * NV + k] : 0.0);
             double dn = 0.0;
             for (int b = 0; b < D; ++b) dn += g.xi[3 * k + b] * p.nw[b];
-            den += ws * dn * hw[k];
+            den += ws * dn * (c->prob.moving_wall ? hwp[ip * NV + k] : hw[k]);
         }
         q.den = den;
     }
@@ -644,6 +672,11 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     d.fs[0] = (const double *)(ws + L.fs);
     d.fs[1] = (const double *)(ws + L.fs) + NV;
     d.hw = (const double *)(ws + L.hw);
+    d.hwp = c->prob.moving_wall ? (const double *)(ws + L.hwp) : nullptr;
+    // 2D FP32 storage keeps offsets from the freestream unless asked for f itself
+    d.foff = (D == 2 && c->precision == IBDVM_F32_STORE && !(c->prob.flags & IBDVM_FLAG_F32_ABSOLUTE)) ? 1 : 0;
+    d.fr[0] = (const double *)(ws + L.fr);
+    d.fr[1] = (const double *)(ws + L.fr) + NV;
     d.fsT[0] = ws + L.fsT;
     d.fsT[1] = ws + L.fsT + (c->precision == IBDVM_F32_STORE ? 4 : 8) * (size_t)NV;
     for (int b = 0; b < 2; ++b)
@@ -672,7 +705,9 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     {
         const size_t wrow = (size_t)2 * (c->prob.n[0] + c->prob.n[1]) * NV * (c->precision == IBDVM_F32_STORE ? 4 : 8);
         for (int A = 0; A < 2; ++A)
-            d.wallT[A] = c->prob.outer == IBDVM_OUTER_WALLS ? (void *)(ws + L.wallT + (A < c->NA ? A : 0) * wrow) : nullptr;
+            d.wallT[A] = c->prob.outer == IBDVM_OUTER_WALLS || c->prob.outer == IBDVM_OUTER_SPECULAR
+                             ? (void *)(ws + L.wallT + (A < c->NA ? A : 0) * wrow)
+                             : nullptr;
     }
     d.ctrl = (ibdvm::Ctrl *)(ws + L.ctrl);
 
@@ -686,10 +721,14 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
     if (e == hipSuccess) e = up(L.w, g.w.data(), g.w.size() * 8);
     if (e == hipSuccess) e = up(L.fs, fs.data(), fs.size() * 8);
     if (e == hipSuccess) e = up(L.hw, hw.data(), hw.size() * 8);
+    if (e == hipSuccess) e = up(L.hwp, hwp.data(), hwp.size() * 8);
     // the freestream rows in the storage type: 2D FP32 storage holds offsets
     // from the freestream, so its freestream rows are zero
     std::vector<float> fs32(fs.size(), 0.0f);
-    if (D == 3) fs32.assign(fs.begin(), fs.end());
+    if (!d.foff) fs32.assign(fs.begin(), fs.end());
+    std::vector<double> fr(fs.size(), 0.0);
+    if (d.foff) fr = fs;
+    if (e == hipSuccess) e = up(L.fr, fr.data(), fr.size() * 8);
     if (e == hipSuccess)
         e = c->precision == IBDVM_F32_STORE ? up(L.fsT, fs32.data(), fs32.size() * 4) : up(L.fsT, fs.data(), fs.size() * 8);
     std::vector<int> cflag32(g.cflag.begin(), g.cflag.end());
@@ -1223,6 +1262,15 @@ ibdvm_status ibdvm_profile_read(ibdvm_ctx *c, double ms[2], int64_t counts[2])
         for (hipEvent_t e : v) HIP_CHECK(hipEventDestroy(e));
         v.clear();
     }
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
+{
+    if (!src || !dst) return fail(IBDVM_E_INVALID_ARG, "null buffer");
+    if (bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+        return fail(IBDVM_E_INVALID_ARG, "copy size and addresses must be multiples of 16 bytes");
+    HIP_CHECK(ibdvm::launch_stream_copy(src, dst, (long long)(bytes / 16), (hipStream_t)stream));
     return IBDVM_OK;
 }
 

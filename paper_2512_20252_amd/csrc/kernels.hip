@@ -21,6 +21,7 @@
 // second pass over the distribution.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -49,18 +50,20 @@ __device__ __forceinline__ T vanleer(T s1, T s2)
     return T(0);
 }
 
-// 2D FP32 storage holds f minus the freestream Maxwellian, so that its
-// rounding is relative to the deviation from the freestream (the rounding of
-// a steady state acts like a constant source, and the deviation is small
-// over most of the domain); FP64 storage and the 3D FP32 form hold f (there
-// the two extra live values per node cost the 4 x 4-tile update a fifth of
-// its speed in register spills).  fref is the offset of a stored value of
-// node k of array A.
+// 2D FP32 storage holds f minus a reference d.fr: by default the
+// freestream Maxwellian, so that its rounding is relative to the deviation
+// from the freestream (the rounding of a steady state acts like a constant
+// source, and the deviation is small over most of the domain), or zero
+// (f itself) for flows with near-vacuum regions, where f is far below the
+// freestream value and the offset would cancel its digits.  FP64 storage
+// and the 3D FP32 form hold f (there the two extra live values per node
+// cost the 4 x 4-tile update a fifth of its speed in register spills).
+// fref is the offset of a stored value of node k of array A.
 template <typename T, typename DR>
 __device__ __forceinline__ double fref(const DR &d, int A, int k)
 {
     if constexpr (sizeof(T) == 4)
-        return d.D == 2 ? d.fs[A][k] : 0.0;
+        return d.D == 2 ? d.fr[A][k] : 0.0;
     else
         return 0.0;
 }
@@ -255,6 +258,7 @@ __device__ void fill_incident(const DR &d, int cur, int p, int chunk)
     const size_t po = (size_t)p * d.NV;
     const int NV = d.NV, k = chunk * kFillChunk + threadIdx.x;
     const bool uniform = (d.flags & 2u) != 0;  // NO_UPWIND ablation
+    const bool naive = (d.flags & kFlagNaive) != 0;
     double num = 0.0;
     if (k < NV) {
         double xk[3] = {0, 0, 0}, x2 = 0.0;
@@ -280,9 +284,11 @@ __device__ void fill_incident(const DR &d, int cur, int p, int chunk)
             const double fdc = (double)f[(size_t)dc * NV + k] + rf;
             const double sdc = ac >= 0 ? ((double)f[(size_t)ac * NV + k] + rf - fdc) / (yac - ydc) : 0.0;
             const double fspv = fdc + sdc * (ysp - ydc);
-            // 2. upwind-weighted interpolation from the surface cells
-            double fgc = 0.0;
-            for (int j = 0; j < ns; ++j) {
+            // 2. upwind-weighted interpolation from the surface cells (the
+            // naive ablation of Section 3.3.3: linear extrapolation of donor
+            // and auxiliary cell along the axis instead)
+            double fgc = naive ? fdc + sdc * (ygc - ydc) : 0.0;
+            for (int j = 0; j < ns && !naive; ++j) {
                 const double wj = (uniform || sum == 0.0) ? 1.0 / ns : upw(j) / sum;
                 const int sj = P.sc[j];
                 const double fj = (double)f[(size_t)sj * NV + k] + rf;
@@ -362,16 +368,17 @@ __device__ void fill_ghost(const DR &d, int p, int chunk)
     for (int A = 0; A < d.NA; ++A) {
         const double fi = d.fiw[A][po + k];
         const double fsv = (al < 1.0 && cl != 0) ? vel_interp(d, d.fiw[A] + po, v, D) : 0.0;
-        const double Hw = d.hw[k] * (A == 1 ? 0.5 * d.Tw : 1.0);
+        const double Hw = (d.hwp ? d.hwp[po + k] : d.hw[k]) * (A == 1 ? 0.5 * d.Tw : 1.0);
         const double fr = al * rw * Hw + (1.0 - al) * fsv;
         const double fw = cl == 0 ? fi : (cl == 1 ? fr : (d.wg[po + k] * fi + (d.w[k] - d.wg[po + k]) * fr) / d.w[k]);
         const double fspv = d.fsp[A][po + k];
         const double sig = (fw - fspv) / (yw - ysp);
         const double gv = fspv + sig * (ygc - ysp);
-        // R28: ghost and face values stay non-negative; the face value goes
-        // no further than the wall value when the face lies beyond the wall
+        // R28: ghost and face values stay non-negative; with the face limit
+        // the face value goes no further than the wall value when the face
+        // lies beyond the wall
         double t = (yface - ysp) / (yw - ysp);
-        if (t > 1.0) t = 1.0;
+        if ((d.flags & kFlagFaceLimit) && t > 1.0) t = 1.0;
         const double fv = fspv + (fw - fspv) * t;
         d.ghost[A][po + k] = gv < 0.0 ? 0.0 : gv;
         d.face[A][po + k] = fv < 0.0 ? 0.0 : fv;
@@ -930,7 +937,7 @@ __device__ __forceinline__ T ghost_at(const DR &d, int A, int c, int dir, int k8
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     const double g = bld(mk_rsrc(d.ghost[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
     if constexpr (OFF)
-        return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
+        return (T)(g - bld(mk_rsrc(d.fr[A], d.NV * 8), k8, double()));
     else
         return (T)g;
 }
@@ -940,7 +947,7 @@ __device__ __forceinline__ T facev_at(const DR &d, int A, int c, int dir, int k8
     const int p = ((cint_p)d.pnb)[6 * c + dir];
     const double g = bld(mk_rsrc(d.face[A] + (size_t)p * d.NV, d.NV * 8), k8, double());
     if constexpr (OFF)
-        return (T)(g - bld(mk_rsrc(d.fs[A], d.NV * 8), k8, double()));
+        return (T)(g - bld(mk_rsrc(d.fr[A], d.NV * 8), k8, double()));
     else
         return (T)g;
 }
@@ -988,7 +995,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
     const int w = uni(threadIdx.x >> 6);
     const int i = i0 + w;
     const bool col_in = i < nx;
-    // WALLS: the outer boundary is the diffuse walls (a separate
+    // WALLS: the outer boundary is walls, diffuse or specular (a separate
     // instantiation, so the other boundaries keep their row addressing)
     const bool per = !WALLS && d.outer != 0;
     const int rowb = NV * ST;
@@ -1046,8 +1053,8 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         xy[v] = d.xi[1][kc];
         wk[v] = k < NV ? d.w[kc] : 0.0;
         if constexpr (SHIFT) {
-            rf0[v] = d.fs[0][kc];
-            rf1[v] = d.fs[1][kc];
+            rf0[v] = d.fr[0][kc];
+            rf1[v] = d.fr[1][kc];
         }
         pos[v] = xx[v] > 0.0;
         py[v] = xy[v] > 0.0;
@@ -1392,6 +1399,10 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
 // Maxwellian depends on the wall side only and comes from the host (wall_in);
 // the outgoing flux of the cell is summed here in FP64; the rows are written
 // in the storage type.
+//
+// Specular outer walls: velocities leaving the wall carry the cell's own
+// value at the mirrored velocity (the normal component reversed: node index
+// N - 1 - i along the wall's axis), the others the cell's value.
 template <typename T>
 __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
 {
@@ -1409,10 +1420,28 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
         sd = q < nx ? -1 : 1;
         cell = i + nx * (sd < 0 ? 0 : ny - 1);
     }
-    const double Ux = (a == 1 && sd > 0) ? d.lid_u : 0.0;
-    const double iTw = 1.0 / d.Tw;
     const T *h = (const T *)d.f[cur][0] + (size_t)cell * NV;
     const T *b = (const T *)d.f[cur][1] + (size_t)cell * NV;
+    T *g0 = (T *)d.wallT[0] + (size_t)r * NV;
+    T *g1 = (T *)d.wallT[1] + (size_t)r * NV;
+    if (d.outer == kOuterSpecular) {
+        const int N0 = d.vn[0];
+        for (int k = threadIdx.x; k < NV; k += 256) {
+            const double xn = sd * d.xi[a][k];
+            int ix = k % N0, iy = k / N0;
+            if (a == 0)
+                ix = N0 - 1 - ix;
+            else
+                iy = d.vn[1] - 1 - iy;
+            const int km = xn < 0.0 ? ix + N0 * iy : k;
+            // stored values are offsets from node k's freestream value in the 2D FP32 form
+            g0[k] = km == k ? h[k] : (T)((double)h[km] + fref<T>(d, 0, km) - fref<T>(d, 0, k));
+            g1[k] = km == k ? b[k] : (T)((double)b[km] + fref<T>(d, 1, km) - fref<T>(d, 1, k));
+        }
+        return;
+    }
+    const double Ux = (a == 1 && sd > 0) ? d.lid_u : 0.0;
+    const double iTw = 1.0 / d.Tw;
     // e^{-c^2/T_w} of the wall Maxwellian at node k
     auto ew = [&](int k) {
         const double cx = d.xi[0][k] - Ux, cy = d.xi[1][k];
@@ -1427,8 +1456,6 @@ __global__ __launch_bounds__(256) void k_wall_fill(Dev d, int cur)
     // wall_in sums e^{-c^2/T_w} without the prefactor A_w, so out / wall_in
     // is rho_w A_w: the factor of e^{-c^2/T_w} in the ghost
     const double rA = out / d.wall_in[2 * a + (sd > 0 ? 1 : 0)];
-    T *g0 = (T *)d.wallT[0] + (size_t)r * NV;
-    T *g1 = (T *)d.wallT[1] + (size_t)r * NV;
     for (int k = threadIdx.x; k < NV; k += 256) {
         const double xn = sd * d.xi[a][k];
         if (xn < 0.0) {
@@ -1944,7 +1971,7 @@ __global__ void k_state_from_freestream(Dev d, int buf, int A, const double *u, 
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const long long g = off + i;
         const int k = (int)(g % d.NV);
-        if (sizeof(T) == 4 && d.D == 2)
+        if (sizeof(T) == 4 && d.D == 2 && d.foff)
             ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (u ? amp * u[i] : 0.0));
         else
             ((T *)d.f[buf][A])[g] = (T)(d.fs[A][k] * (1.0 + (u ? amp * u[i] : 0.0)));
@@ -1970,7 +1997,7 @@ __global__ void k_state_hashed(Dev d, int buf, int A, unsigned long long seed, d
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int k = (int)(i % d.NV);
         const double u = hashed_uniform(seed, (unsigned long long)A * (unsigned long long)n + (unsigned long long)i);
-        if (sizeof(T) == 4 && d.D == 2)
+        if (sizeof(T) == 4 && d.D == 2 && d.foff)
             ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (amp * u));
         else
             ((T *)d.f[buf][A])[i] = (T)(d.fs[A][k] * (1.0 + amp * u));
@@ -1989,6 +2016,24 @@ __global__ void k_state_get(Dev d, int buf, int A, double *dst, long long off, l
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         dst[i] = (double)((const T *)d.f[buf][A])[off + i] + fref<T>(d, A, (int)((off + i) % d.NV));
+}
+
+// ---------------------------------------------------------------- measurement
+// Streaming copy of n 16-byte words: the practical HBM ceiling the update
+// kernels are measured against (every byte read once and written once,
+// coalesced 16-byte lanes, the grid covering the chip several times over).
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, long long n)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], e = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = e;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_ctrl_reset(Ctrl *c, int slot)
@@ -2062,7 +2107,7 @@ hipError_t launch_update2d(const Dev &d, int storage, int cur, int slot, const T
     if (storage == 0) return launch_update2d_f64(d, t.V, t.TX, cur, slot, t.LY, ntx, nys, ncv, grid, block, s);
 #define U2D(VV, XX)                                                                                                   \
     if (t.V == VV && t.TX == XX) {                                                                                 \
-        if (d.outer == 2)                                                                                          \
+        if (d.outer >= kOuterWalls)                                                                                \
             hipLaunchKernelGGL((k_update2d<float, VV, XX, true>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv);  \
         else                                                                                                       \
             hipLaunchKernelGGL((k_update2d<float, VV, XX, false>), grid, block, 0, s, d, cur, slot, t.LY, ntx, nys, ncv); \
@@ -2176,7 +2221,7 @@ hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fi
 
 hipError_t launch_wall_fill(const Dev &d, int storage, int cur, hipStream_t s)
 {
-    if (d.outer != 2) return hipSuccess;
+    if (d.outer != kOuterWalls && d.outer != kOuterSpecular) return hipSuccess;
     if (d.D != 2 || !d.wallT[0] || !d.wallT[1]) return hipErrorInvalidValue;
     const dim3 g((unsigned)(2 * (d.n[0] + d.n[1])));
     if (storage == 0)
@@ -2241,6 +2286,15 @@ hipError_t launch_state_get(const Dev &d, int storage, int buf, int A, double *d
     return hipGetLastError();
 }
 
+hipError_t launch_stream_copy(const void *src, void *dst, long long words16, hipStream_t s)
+{
+    if (words16 <= 0) return hipSuccess;
+    // 8 workgroups of 256 threads per CU on 256 CUs, each thread 4 words per pass
+    const long long blocks = std::min<long long>((words16 + 255) / 256, 256 * 8);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4 *)src, (uint4 *)dst, words16);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments_out(const Dev &d, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_moments_out, dim3(blocks_for(d.Nc, 256)), dim3(256), 0, s, d, out);
@@ -2258,7 +2312,7 @@ hipError_t launch_update2d_f64(const Dev &d, int V, int TX, int cur, int slot, i
 {
 #define U2D(VV, XX)                                                                                                    \
     if (V == VV && TX == XX) {                                                                                      \
-        if (d.outer == 2)                                                                                           \
+        if (d.outer >= kOuterWalls)                                                                                 \
             hipLaunchKernelGGL((k_update2d<double, VV, XX, true>), grid, block, 0, s, d, cur, slot, LY, ntx, nys, ncv);  \
         else                                                                                                        \
             hipLaunchKernelGGL((k_update2d<double, VV, XX, false>), grid, block, 0, s, d, cur, slot, LY, ntx, nys, ncv); \

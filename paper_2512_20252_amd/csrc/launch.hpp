@@ -41,5 +41,7 @@ hipError_t launch_state_set(const Dev &d, int storage, int buf, int A, const dou
 hipError_t launch_state_get(const Dev &d, int storage, int buf, int A, double *dst, long long off, long long n,
                             hipStream_t s);
 hipError_t launch_moments_out(const Dev &d, double *out, hipStream_t s);
+// plain streaming copy of words16 16-byte words (measurement)
+hipError_t launch_stream_copy(const void *src, void *dst, long long words16, hipStream_t s);
 
 }  // namespace ibdvm

@@ -12,8 +12,8 @@
 // steps, concurrent with the group.  A new solve is prepared on its own
 // stream while replays run and joins the group at the group's next replay.
 // After each replay the drag coefficient of every solve in it is checked; a
-// solve ends when |C_D(n) - C_D(n - K)| < tol or a step cap is reached, and
-// releases its memory and slot to the queue.
+// solve ends when |C_D(n) - C_D(n - K)| < tol |C_D(n)| or a step cap is
+// reached, and releases its memory and slot to the queue.
 //
 // Built on the public C ABI only (ibdvm_create, ibdvm_batch_graph_create, ...).
 #include <hip/hip_runtime_api.h>
@@ -232,7 +232,8 @@ bool harvest(ibdvm_server *s, Active &a)
         retire(s, a, st, 0);
         return false;
     }
-    const bool conv = a.rq.tol > 0.0 && std::isfinite(a.cd_prev) && std::fabs(a.cd - a.cd_prev) < a.rq.tol;
+    const bool conv =
+        a.rq.tol > 0.0 && std::isfinite(a.cd_prev) && std::fabs(a.cd - a.cd_prev) < a.rq.tol * std::fabs(a.cd);
     a.cd_prev = a.cd;
     if (conv || a.steps >= a.rq.max_steps) {
         retire(s, a, IBDVM_OK, conv ? 1 : 0);
@@ -431,6 +432,49 @@ ibdvm_status ibdvm_server_poll(ibdvm_server *s, int32_t block, ibdvm_result *don
     }
     *n_done = n;
     return st;
+}
+
+ibdvm_status ibdvm_server_cancel(ibdvm_server *s, int64_t id)
+{
+    if (!s) return IBDVM_E_INVALID_ARG;
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it)
+        if (it->id == id) {
+            ibdvm_result r{};
+            r.id = id;
+            r.status = IBDVM_E_CANCELLED;
+            r.t_submit = it->t_submit;
+            r.t_admit = r.t_done = s->now();
+            s->queue.erase(it);
+            s->ready.push_back(r);
+            s->finished += 1;
+            return IBDVM_OK;
+        }
+    for (size_t i = 0; i < s->active.size(); ++i) {
+        Active &a = s->active[i];
+        if (a.rq.id != id) continue;
+        // the replay in flight that runs this solve ends before its memory is
+        // released: its own (standalone, or fused but not yet joined), or the
+        // group's (joined); a finished group replay is harvested by the next
+        // pass for the other members
+        hipError_t e = hipSuccess;
+        bool ran = false;  // a replay of this solve was in flight and has now ended
+        if (a.joined) {
+            ran = s->inflight;
+            if (ran) e = hipEventSynchronize(s->done);
+        } else if (a.inflight) {
+            ran = true;
+            e = hipEventSynchronize(a.done);
+        } else if (a.stream) {
+            e = hipStreamSynchronize(a.stream);
+        }
+        if (e != hipSuccess) return hip_fail(s, e, "cancel");
+        if (ran) a.steps += s->K;
+        retire(s, a, IBDVM_E_CANCELLED, 0);
+        s->active.erase(s->active.begin() + (long)i);
+        return IBDVM_OK;
+    }
+    s->err = "no queued or active request with this id";
+    return IBDVM_E_INVALID_ARG;
 }
 
 ibdvm_status ibdvm_server_info(const ibdvm_server *s, int64_t out[5])

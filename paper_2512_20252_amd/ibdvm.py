@@ -14,12 +14,13 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libibdvm.so")
 
-OK, E_INVALID_ARG, E_GEOMETRY, E_NO_MEMORY, E_DEVICE, E_UNSTABLE, E_UNSUPPORTED, E_STATE = range(8)
+OK, E_INVALID_ARG, E_GEOMETRY, E_NO_MEMORY, E_DEVICE, E_UNSTABLE, E_UNSUPPORTED, E_STATE, E_CANCELLED = range(9)
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
-OUTER = {"freestream": 0, "periodic": 1, "walls": 2}
+OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
 RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2}
 PRECISION = {"f64": 0, "f32": 1}
-FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "implicit": 1 << 2, "host_only": 1 << 8}
+FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "implicit": 1 << 2, "face_limit": 1 << 3, "naive": 1 << 4,
+         "no_aux": 1 << 5, "f32_absolute": 1 << 6, "host_only": 1 << 8}
 
 c_int32, c_double, c_size_t, c_void_p = ctypes.c_int32, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
 
@@ -41,7 +42,7 @@ class Geom(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("cfl", c_double), ("omega_vhs", c_double), ("a_vhs", c_double),
                 ("flags", ctypes.c_uint32), ("workspace", c_void_p), ("workspace_bytes", c_size_t),
-                ("stream", c_void_p)]
+                ("stream", c_void_p), ("U_w", c_double * 3), ("Omega_w", c_double * 3)]
 
 
 class WallPoint(ctypes.Structure):
@@ -70,7 +71,7 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_batch_graph_create", "ibdvm_graph_launch",
            "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
            "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy", "ibdvm_set_stream",
-           "ibdvm_server_set_fusion", "ibdvm_residual"]
+           "ibdvm_server_set_fusion", "ibdvm_residual", "ibdvm_server_cancel", "ibdvm_stream_copy"]
 _NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
                "ibdvm_server_error", "ibdvm_server_destroy")
 
@@ -122,6 +123,8 @@ def lib():
                                           c_double, ctypes.c_int64, dp, P(ctypes.c_int64)]
         L.ibdvm_server_poll.argtypes = [c_void_p, c_int32, P(Result), c_int32, P(c_int32)]
         L.ibdvm_server_info.argtypes = [c_void_p, P(ctypes.c_int64)]
+        L.ibdvm_server_cancel.argtypes = [c_void_p, ctypes.c_int64]
+        L.ibdvm_stream_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
         L.ibdvm_server_clock.argtypes = [c_void_p]
         L.ibdvm_server_clock.restype = c_double
         L.ibdvm_server_error.argtypes = [c_void_p]
@@ -179,6 +182,10 @@ def structs(case, precision="f64", flags=(), workspace=0, nbytes=0, stream=0):
     o.workspace = workspace
     o.workspace_bytes = nbytes
     o.stream = stream
+    Uw, Ow = case.get("U_w", (0.0, 0.0, 0.0)), case.get("Omega_w", (0.0, 0.0, 0.0))
+    for a in range(3):
+        o.U_w[a] = Uw[a] if a < len(Uw) else 0.0
+        o.Omega_w[a] = Ow[a] if a < len(Ow) else 0.0
     return g, v, ge, o
 
 
@@ -342,6 +349,16 @@ class Solver:
                 "wg": wg[: self.npairs]}
 
 
+def stream_copy(src, dst, stream=None):
+    """Enqueue the library's streaming copy of the torch tensor src into dst
+    (same byte size) on stream (default: the current stream)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = stream if stream is not None else torch.cuda.current_stream()
+    check(lib().ibdvm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, s.cuda_stream))
+
+
 def batch_step(solvers, n):
     arr = (c_void_p * len(solvers))(*[s.handle for s in solvers])
     check(lib().ibdvm_batch_step(arr, len(solvers), int(n)))
@@ -378,12 +395,17 @@ class Server:
     """Continuous batching of 2D solves in one device workspace (a torch
     uint8 tensor of ``nbytes``)."""
 
-    def __init__(self, nbytes, max_active=4, steps_per_replay=100, fuse_below=None):
-        import torch
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    def __init__(self, nbytes, max_active=4, steps_per_replay=100, fuse_below=None, workspace_ptr=None):
+        """workspace_ptr: an existing device buffer of nbytes (256-byte
+        aligned) instead of a torch allocation."""
+        if workspace_ptr is None:
+            import torch
+            self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            ptr, nbytes = self.workspace.data_ptr(), self.workspace.numel()
+        else:
+            self.workspace, ptr = None, int(workspace_ptr)
         h = c_void_p(0)
-        code = lib().ibdvm_server_create(self.workspace.data_ptr(), self.workspace.numel(), int(max_active),
-                                         int(steps_per_replay), ctypes.byref(h))
+        code = lib().ibdvm_server_create(ptr, int(nbytes), int(max_active), int(steps_per_replay), ctypes.byref(h))
         if code != OK:
             raise IbdvmError(code, "server_create")
         self._h = h
@@ -420,6 +442,9 @@ class Server:
             d["moments"] = self._outs.pop(r.id, None)
             out.append(d)
         return out
+
+    def cancel(self, rid):
+        self._check(lib().ibdvm_server_cancel(self._h, int(rid)))
 
     def info(self):
         a = (ctypes.c_int64 * 5)()

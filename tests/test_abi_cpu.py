@@ -46,6 +46,8 @@ GEOMS = {
     # stretched velocity grids (non-uniform dual cells in the cut-cell sets)
     "stretched_2d": lambda: dict(cases.cylinder_small(), rule="stretched", vstretch=1.5, vn=(17, 14)),
     "stretched_3d": lambda: dict(cases.sphere(n=28, vn=9), rule="stretched", vstretch=1.1),
+    # the no-donor-slope ablation: every pair without an auxiliary cell (R10)
+    "no_aux": lambda: dict(cases.cylinder_small(), flags=("no_aux",)),
 }
 
 
@@ -166,3 +168,26 @@ def test_server_argument_checks():
     assert L.ibdvm_server_info(h, info) == ibdvm.OK
     assert list(info)[:3] == [0, 0, 0] and info[4] == 1 << 20
     L.ibdvm_server_destroy(h)
+
+
+def test_server_cancel_queued_requests_host_only():
+    """Serving: creating a server, queueing requests and cancelling queued
+    ones touch no device (the workspace address is only stored), so this
+    runs on the host: cancelled requests leave the queue and come back from
+    poll with IBDVM_E_CANCELLED; an unknown id is refused."""
+    srv = ibdvm.Server(1 << 34, max_active=2, steps_per_replay=10, workspace_ptr=1 << 20)
+    ids = [srv.submit(cases.cylinder_small(), seed=i, tol=1e-6, max_steps=100) for i in range(3)]
+    assert srv.info()["queued"] == 3
+    srv.cancel(ids[1])
+    assert srv.info()["queued"] == 2
+    with pytest.raises(ibdvm.IbdvmError) as e:
+        srv.cancel(ids[1])
+    assert e.value.code == ibdvm.E_INVALID_ARG
+    srv.cancel(ids[0])
+    srv.cancel(ids[2])
+    info = srv.info()
+    assert info["queued"] == 0 and info["active"] == 0 and info["finished"] == 3 and info["bytes_used"] == 0
+    res = srv.poll()
+    assert sorted(r["id"] for r in res) == sorted(ids)
+    assert all(r["status"] == ibdvm.E_CANCELLED and r["steps"] == 0 for r in res)
+    srv.close()
