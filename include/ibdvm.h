@@ -237,6 +237,22 @@ ibdvm_status ibdvm_moments(ibdvm_ctx *ctx, double *out, int32_t out_is_device);
 ibdvm_status ibdvm_surface_forces(ibdvm_ctx *ctx, double force[3], double *C_D, double *C_L, ibdvm_wall_point *pts,
                                   int32_t cap, int32_t *n_pts);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the outputs of ibdvm_surface_forces, computed the same way,
+ * enqueued on the context stream and written to the device array out:
+ * out[0..2] force, out[3] C_D, out[4] C_L, then for the first min(pairs,
+ * cap) ghost-donor pairs 17 doubles each, the fields of ibdvm_wall_point in
+ * order (x_w[3], n_w[3], rho_w, p_w, tau_w[3], q_n, C_p, T_s, u_s[3]); out
+ * holds 5 + 17 cap doubles.  Allocates nothing and does not synchronise:
+ * the per-pair force records live in a static device array of the library
+ * that holds 16384 pairs (1.7 MB per device, kept until the process ends);
+ * a solve with more pairs is refused with IBDVM_E_INVALID_ARG.  Calls on one
+ * device share that array, so calls that overlap on one device (contexts on
+ * different streams) race; calls ordered on one stream do not.  The device
+ * health word is checked at the next synchronising call. */
+ibdvm_status ibdvm_surface_forces_static(ibdvm_ctx *ctx, double *out, int32_t cap);
+
 /* Time step of the last step, simulated time and step count.  Synchronises. */
 ibdvm_status ibdvm_clock(ibdvm_ctx *ctx, double *dt, double *time, int64_t *step);
 

@@ -32,6 +32,11 @@ constexpr int kResVars = 5;
 // tau_w[3], q_n, and the raw moments of the wall distribution: sum w f,
 // sum w xi f [3], sum w (|xi|^2 h + b) (3D: |xi|^2 f)
 constexpr int kForceWords = 13;
+// allocation-free surface forces: pairs the static force-record scratch holds
+constexpr int kStaticMaxPairs = 16384;
+// doubles per wall point in the device output of the allocation-free
+// surface forces: x_w[3], n_w[3], rho_w, p_w, tau_w[3], q_n, C_p, T_s, u_s[3]
+constexpr int kWallPointWords = 17;
 
 // Dev::flags bits: semi-implicit collision (IBDVM_FLAG_IMPLICIT_COLLISION),
 // face limit, naive extrapolation (IBDVM_FLAG_FACE_LIMIT,
@@ -53,6 +58,7 @@ struct DPair {
     double den;  // sum over reflected measure of omega^s xi_n Hw
     double dS;   // face area
     double nw[3];
+    double xw[3];  // intersect point
     double r[26][3];
     double rh[26][3];
 };

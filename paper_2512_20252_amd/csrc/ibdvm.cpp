@@ -595,7 +595,10 @@ ibdvm_status ibdvm_create(const ibdvm_grid *grid, const ibdvm_vgrid *vgrid, cons
         q.dS = 1.0;
         for (int b = 0; b < D; ++b)
             if (b != a) q.dS *= g.dx[b];
-        for (int b = 0; b < 3; ++b) q.nw[b] = p.nw[b];
+        for (int b = 0; b < 3; ++b) {
+            q.nw[b] = p.nw[b];
+            q.xw[b] = p.xw[b];
+        }
         for (int j = 0; j < p.ns; ++j) {
             q.sc[j] = p.sc[j];
             for (int b = 0; b < 3; ++b) {
@@ -1130,6 +1133,25 @@ ibdvm_status ibdvm_surface_forces(ibdvm_ctx *c, double force[3], double *C_D, do
             pts[m].T_s = 4.0 * (0.5 * r[4] - 0.5 * r[0] * u2) / (3.0 * r[0]);
         }
     if (n_pts) *n_pts = pts ? m : (int32_t)np;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_surface_forces_static(ibdvm_ctx *c, double *out, int32_t cap)
+{
+    if (!c) return fail(IBDVM_E_INVALID_ARG, "null context");
+    if (!out || cap < 0) return fail(IBDVM_E_INVALID_ARG, "null output or negative capacity");
+    const size_t np = c->geo.pairs.size();
+    if (np > (size_t)ibdvm::kStaticMaxPairs)
+        return fail(IBDVM_E_INVALID_ARG, "the solve has " + std::to_string(np) + " ghost-donor pairs, more than the " +
+                                             std::to_string(ibdvm::kStaticMaxPairs) +
+                                             " the static scratch of ibdvm_surface_forces_static holds");
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    HIP_CHECK(hipSetDevice(c->device));
+    if ((st = finish_pending(c))) return st;
+    HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), true, false, c->stream));
+    HIP_CHECK(ibdvm::launch_force_static(c->dev, c->precision, c->cur, out, cap, 0.5 * c->Uinf * c->Uinf * c->Lref,
+                                         c->Uinf, c->stream));
     return IBDVM_OK;
 }
 

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "device.hpp"
@@ -2066,6 +2067,84 @@ __global__ void k_moments_out(Dev d, double *out)
 
 #ifndef IBDVM_FP64_UPDATE2D_UNIT
 
+// ---------------------------------------------------------------- allocation-free surface forces
+// Scratch of ibdvm_surface_forces_static: the per-pair force records of the
+// force kernel (kForceWords doubles per pair, at most kStaticMaxPairs
+// pairs), 1.7 MB.  Every device that runs the library holds its own copy
+// for the life of the process; calls on one device share it.
+static __device__ __align__(256) double scratch[kStaticMaxPairs * kForceWords];
+
+namespace {
+
+// one workgroup: thread 0 sums the force over the pairs in pair order (the
+// order of the host sum in ibdvm_surface_forces) and forms C_D, C_L; the
+// threads then write the wall points of the first cap pairs
+template <int D>
+__global__ __launch_bounds__(256) void k_force_out(Dev d, const double *pf, double *out, int cap, double qd,
+                                                   double Uinf)
+{
+    const int np = d.npairs;
+    if (threadIdx.x == 0) {
+        double F[3] = {0.0, 0.0, 0.0};
+        for (int p = 0; p < np; ++p)
+            for (int b = 0; b < 3; ++b) F[b] += pf[kForceWords * p + b];
+        for (int b = 0; b < 3; ++b) out[b] = F[b];
+        out[3] = qd > 0.0 ? F[0] / qd : NAN;
+        out[4] = qd > 0.0 ? F[1] / qd : NAN;
+    }
+    const int m = np < cap ? np : cap;
+    for (int p = threadIdx.x; p < m; p += blockDim.x) {
+        const DPair &P = d.pairs[p];
+        const double *r = pf + kForceWords * p;
+        double *w = out + 5 + (size_t)kWallPointWords * p;
+        for (int b = 0; b < 3; ++b) {
+            w[b] = P.xw[b];
+            w[3 + b] = P.nw[b];
+            w[8 + b] = r[4 + b];
+        }
+        w[6] = d.rhow[p];
+        w[7] = r[3];
+        w[11] = r[7];
+        // Section 4: C_p = 2 (p_w - p_0) / (rho_0 U_0^2), freestream p_0 = 1/2
+        w[12] = Uinf > 0.0 ? 2.0 * (r[3] - 0.5) / (Uinf * Uinf) : NAN;
+        // gas at the wall point: rho, U, then T = 4 (rho E - rho |U|^2 / 2) / (3 rho)
+        const double *mw = r + 8;
+        double u2 = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            const double u = b < D ? mw[1 + b] / mw[0] : 0.0;
+            w[14 + b] = u;
+            u2 += u * u;
+        }
+        w[13] = 4.0 * (0.5 * mw[4] - 0.5 * mw[0] * u2) / (3.0 * mw[0]);
+    }
+}
+
+// device address of `scratch` per device, looked up at the first call on a
+// device with that device current (the host-side name of the array is not a
+// device address)
+constexpr int kMaxDevices = 64;
+void *g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- launchers
 #define DISPATCH(D_, S_, ...)                                      \
     do {                                                           \
@@ -2235,6 +2314,24 @@ hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, h
 {
     hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, d.ctrl, slot);
     DISPATCH(d.D, storage, hipLaunchKernelGGL((k_moments_direct<DD, TT>), dim3(blocks_for(d.Nc, 4)), dim3(256), 0, s, d, cur, slot));
+    return hipGetLastError();
+}
+
+hipError_t launch_force_static(const Dev &d, int storage, int cur, double *out, int cap, double qd, double Uinf,
+                               hipStream_t s)
+{
+    if (d.npairs > kStaticMaxPairs || cap < 0 || !out) return hipErrorInvalidValue;
+    void *ptr = nullptr;
+    hipError_t e = scratch_address(&ptr);
+    if (e != hipSuccess) return e;
+    Dev ds = d;
+    ds.pforce = (double *)ptr;
+    if (d.npairs > 0)
+        DISPATCH(d.D, storage, hipLaunchKernelGGL((k_force<DD, TT>), dim3(d.npairs), dim3(256), 0, s, ds, cur));
+    if (d.D == 2)
+        hipLaunchKernelGGL((k_force_out<2>), dim3(1), dim3(256), 0, s, ds, (const double *)ptr, out, cap, qd, Uinf);
+    else
+        hipLaunchKernelGGL((k_force_out<3>), dim3(1), dim3(256), 0, s, ds, (const double *)ptr, out, cap, qd, Uinf);
     return hipGetLastError();
 }
 

@@ -32,6 +32,11 @@ hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fi
 hipError_t launch_wall_fill(const Dev &d, int storage, int cur, hipStream_t s);
 hipError_t launch_moments_direct(const Dev &d, int storage, int cur, int slot, hipStream_t s);
 hipError_t launch_force(const Dev &d, int storage, int cur, hipStream_t s);
+// the force kernel with its per-pair records in the library's static device
+// scratch (at most kStaticMaxPairs pairs), then the totals, C_D, C_L and up to
+// cap wall points written to the device array out; allocates nothing
+hipError_t launch_force_static(const Dev &d, int storage, int cur, double *out, int cap, double qd, double Uinf,
+                               hipStream_t s);
 hipError_t launch_state_freestream(const Dev &d, int storage, int buf, int A, const double *u, double amp, long long off,
                                    long long n, hipStream_t s);
 hipError_t launch_state_hashed(const Dev &d, int storage, int buf, int A, unsigned long long seed, double amp,

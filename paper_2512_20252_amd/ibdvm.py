@@ -71,7 +71,8 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_last_error", "ibdvm_init_freestream_hashed", "ibdvm_graph_create", "ibdvm_batch_graph_create", "ibdvm_graph_launch",
            "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
            "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy", "ibdvm_set_stream",
-           "ibdvm_server_set_fusion", "ibdvm_residual", "ibdvm_server_cancel", "ibdvm_stream_copy"]
+           "ibdvm_server_set_fusion", "ibdvm_residual", "ibdvm_server_cancel", "ibdvm_stream_copy",
+           "ibdvm_surface_forces_static"]
 _NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
                "ibdvm_server_error", "ibdvm_server_destroy")
 
@@ -125,6 +126,7 @@ def lib():
         L.ibdvm_server_info.argtypes = [c_void_p, P(ctypes.c_int64)]
         L.ibdvm_server_cancel.argtypes = [c_void_p, ctypes.c_int64]
         L.ibdvm_stream_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
+        L.ibdvm_surface_forces_static.argtypes = [c_void_p, c_void_p, c_int32]
         L.ibdvm_server_clock.argtypes = [c_void_p]
         L.ibdvm_server_clock.restype = c_double
         L.ibdvm_server_error.argtypes = [c_void_p]
@@ -293,6 +295,12 @@ class Solver:
         wall = np.array([list(p.xw) + list(p.nw) + [p.rho_w, p.p_w] + list(p.tau_w) + [p.q_n, p.C_p, p.T_s]
                          + list(p.u_s) for p in pts[: n.value]]).reshape(-1, 17)
         return F, cd.value, cl.value, wall
+
+    def surface_forces_static(self, out, cap):
+        """Enqueue the allocation-free surface forces into the device float64
+        tensor out (at least 5 + 17 cap elements) on the solve's stream."""
+        assert out.numel() >= 5 + 17 * cap
+        check(lib().ibdvm_surface_forces_static(self._h, out.data_ptr(), int(cap)))
 
     def residual(self):
         """Convergence residual of the last step: per variable (rho, rho U[3],
