@@ -45,6 +45,11 @@
 /* stretched tensor grid (reading R31): the midpoint grid of u in [-1, 1]
  * mapped by x(u) = V sinh(beta u) / sinh(beta), finer near xi = 0 */
 #define OR_RULE_STRETCHED 2
+/* locally refined tensor grid (reading R35): per axis the node density
+ * 1 + A (exp(-(x/w)^2) + exp(-((x - c)/w)^2)) (one bump when c = 0),
+ * nodes and dual cells the images of the uniform u-cells under the inverse
+ * of its normalised cumulative */
+#define OR_RULE_REFINED 3
 
 #define OR_FLAG_NO_CUTCELL 1u
 #define OR_FLAG_NO_UPWIND 2u
@@ -91,6 +96,8 @@ typedef struct {
      * a translation plus a rigid rotation about the geometry centre (in 2D
      * only Ow[2] acts); the wall Maxwellian of Section 2.3 moves with it */
     double Uw[3], Ow[3];
+    /* OR_RULE_REFINED: amplitude A, width w and second centre c per axis */
+    double vref_amp, vref_width, vref_centre[3];
 } or_case;
 
 typedef struct {
@@ -284,10 +291,68 @@ static double stretch_map(double V, double beta, int m, int N)
     return V * sinh(beta * ((double)m / (double)N)) / sinh(beta);
 }
 
+/* cumulative node density of the refined rule (reading R35) from -V to x:
+ * the integral of 1 + A sum_c exp(-((x - c)/w)^2), each bump integrating
+ * to A w sqrt(pi)/2 (erf(.) - erf(.)) */
+static double refine_cum(double x, double V, double A, double w, const double *cs, int nc)
+{
+    double s = x + V;
+    for (int i = 0; i < nc; ++i) s += A * w * 0.5 * sqrt(M_PI) * (erf((x - cs[i]) / w) - erf((-V - cs[i]) / w));
+    return s;
+}
+
+/* the point where the normalised cumulative reaches u in [-1, 1]: bisection
+ * on [-V, V] to the last representable midpoint (the cumulative is
+ * increasing), ends exact */
+static double refine_inverse(double u, double V, double A, double w, const double *cs, int nc)
+{
+    if (u <= -1.0) return -V;
+    if (u >= 1.0) return V;
+    const double t = 0.5 * (u + 1.0) * refine_cum(V, V, A, w, cs, nc);
+    double lo = -V, hi = V;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (refine_cum(mid, V, A, w, cs, nc) < t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* nodes, weights and dual cells [e0, e1] of one axis */
 static void velocity_axis(int N, double lo, double hi, int rule, double beta, double *x, double *w, double *e0,
-                          double *e1, double *d)
+                          double *e1, double *d, double ramp, double rwidth, double rcentre)
 {
+    if (rule == OR_RULE_REFINED) {
+        /* node i at u = (2i + 1 - N)/N, its dual cell between the images of
+         * (2i - N)/N and (2i + 2 - N)/N; with the one bump at 0 the density
+         * is even, and the negative half is the mirror of the positive one
+         * so that nodes and faces are exactly antisymmetric */
+        const double V = hi;
+        double cs[2] = {0.0, rcentre};
+        const int nc = rcentre != 0.0 ? 2 : 1;
+        for (int m = 0; m <= 2 * N; ++m) {
+            const int k = m - N; /* u = k / N */
+            double v;
+            if (nc == 1 && k == 0)
+                v = 0.0; /* the centre of an even density */
+            else if (nc == 1 && k < 0)
+                v = -refine_inverse((double)(-k) / (double)N, V, ramp, rwidth, cs, nc);
+            else
+                v = refine_inverse((double)k / (double)N, V, ramp, rwidth, cs, nc);
+            if (m % 2 == 0) {
+                if (m / 2 < N) e0[m / 2] = v;
+                if (m / 2 > 0) e1[m / 2 - 1] = v;
+            } else {
+                x[m / 2] = v;
+            }
+        }
+        for (int i = 0; i < N; ++i) w[i] = e1[i] - e0[i];
+        *d = 0.0;
+        return;
+    }
     if (rule == OR_RULE_STRETCHED) {
         /* node i at u = (2i + 1 - N)/N, its dual cell between the images of
          * u = (2i - N)/N and (2i + 2 - N)/N; the weight is the cell width */
@@ -595,6 +660,14 @@ void *or_create(const or_case *cs, int *err)
     if (cs->vrule == OR_RULE_STRETCHED)
         for (int a = 0; a < D; ++a)
             if (!(cs->vstretch > 0.0) || cs->vlo[a] != -cs->vhi[a]) *err = 1;
+    if (cs->vrule == OR_RULE_REFINED)
+        for (int a = 0; a < D; ++a)
+            if (!(cs->vref_amp >= 0.0) || !(cs->vref_width > 0.0) || cs->vlo[a] != -cs->vhi[a] ||
+                !(fabs(cs->vref_centre[a]) < cs->vhi[a]))
+                *err = 1;
+    if (cs->vrule == OR_RULE_REFINED && cs->outer == OR_SPECULAR)
+        for (int a = 0; a < D; ++a)
+            if (cs->vref_centre[a] != 0.0) *err = 1; /* mirrored nodes must be nodes */
     /* velocity grid */
     for (int a = 0; a < D; ++a) {
         s->xi1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
@@ -602,7 +675,7 @@ void *or_create(const or_case *cs, int *err)
         s->ed0[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
         s->ed1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
         velocity_axis(cs->vn[a], cs->vlo[a], cs->vhi[a], cs->vrule, cs->vstretch, s->xi1[a], s->w1[a], s->ed0[a],
-                      s->ed1[a], &s->dxi[a]);
+                      s->ed1[a], &s->dxi[a], cs->vref_amp, cs->vref_width, cs->vref_centre[a]);
         s->maxabs[a] = 0.0;
         for (int i = 0; i < cs->vn[a]; ++i)
             if (fabs(s->xi1[a][i]) > s->maxabs[a]) s->maxabs[a] = fabs(s->xi1[a][i]);

@@ -17,7 +17,7 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
-RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2}
+RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2, "refined": 3}
 # "f32_absolute" selects how the library stores FP32 values; the FP64 oracle
 # has no such choice and ignores it
 FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4, "face_limit": 8, "naive": 16, "no_aux": 32,
@@ -44,7 +44,8 @@ class _Case(ctypes.Structure):
                 ("Pr", ctypes.c_double), ("gam", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("Tw", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
                 ("avhs", ctypes.c_double), ("flags", ctypes.c_int), ("lid_u", ctypes.c_double),
-                ("vstretch", ctypes.c_double), ("Uw", ctypes.c_double * 3), ("Ow", ctypes.c_double * 3)]
+                ("vstretch", ctypes.c_double), ("Uw", ctypes.c_double * 3), ("Ow", ctypes.c_double * 3),
+                ("vref_amp", ctypes.c_double), ("vref_width", ctypes.c_double), ("vref_centre", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -133,6 +134,11 @@ def _case_struct(case):
     for a in range(3):
         c.Uw[a] = Uw[a] if a < len(Uw) else 0.0
         c.Ow[a] = Ow[a] if a < len(Ow) else 0.0
+    c.vref_amp = case.get("vref_amp", 0.0)
+    c.vref_width = case.get("vref_width", 1.0)
+    rc = case.get("vref_centre", (0.0, 0.0, 0.0))
+    for a in range(3):
+        c.vref_centre[a] = rc[a] if a < len(rc) else 0.0
     return c
 
 
