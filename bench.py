@@ -343,6 +343,61 @@ def _steady(case, t_end, tag, block=1000):
     return r
 
 
+def slip_study(n, t_end, modes=6, block=500):
+    """Wall slip of the hypersonic cylinder (the Section 4 comparison of the
+    slip velocity along the wall with and without the upwind-weighted
+    interpolation): R = 1 at Ma 5, Kn 0.1, T_w = 1 on a uniform n x n grid
+    of [-6,10] x [-8,8] with 60^2 velocity nodes on [-10,10]^2, run to time
+    t_end with the upwind weights of Section 3.2.2, with uniform weights
+    (NO_UPWIND) and with the naive axis extrapolation of Section 3.3.3.  Per
+    run: the tangential slip velocity u_s . t of the wall gas at every wall
+    point (t anticlockwise), and the zigzag amplitude: the RMS residual of a
+    least-squares fit of u_s . t by Fourier modes up to `modes` in the polar
+    angle, relative to the largest |u_s . t|."""
+    import numpy as np
+    import torch
+    from paper_2512_20252_amd import cases, ibdvm
+
+    base = cases.case(dim=2, n=(n, n), lo=(-6.0, -8.0), hi=(10.0, 8.0), vn=(60, 60), vlo=(-10.0, -10.0),
+                      vhi=(10.0, 10.0), geometry="circle", size=(1.0, 0.0, 0.0), Kn=0.1, Ma=5.0)
+    out = {"workload": f"2D cylinder R=1 at Ma 5, Kn 0.1, T_w 1, {n}x{n} cells on [-6,10]x[-8,8], 60^2 velocity "
+                       f"nodes on [-10,10]^2, to t = {t_end}", "modes": modes}
+    for tag, flags in (("upwind", ()), ("uniform_weights", ("no_upwind",)), ("naive", ("naive",))):
+        c = cases.case(**dict(base, flags=flags))
+        s = ibdvm.Solver(c, stream=torch.cuda.Stream())
+        s.init_freestream()
+        g = ibdvm.Graph(s, block)
+        r, done = {"status": "ok"}, 0
+        try:
+            while s.clock()["time"] < t_end:
+                g.launch()
+                done += block
+            _, cd, _, w = s.surface_forces()
+            xw, nw, us = w[:, 0:2], w[:, 3:5], w[:, 14:16]
+            tang = np.stack([-nw[:, 1], nw[:, 0]], 1)
+            ut = np.sum(us * tang, axis=1)
+            th = np.arctan2(xw[:, 1], xw[:, 0])
+            cols = [np.ones_like(th)] + [f(k * th) for k in range(1, modes + 1) for f in (np.cos, np.sin)]
+            Amat = np.stack(cols, 1)
+            coef, *_ = np.linalg.lstsq(Amat, ut, rcond=None)
+            resid = ut - Amat @ coef
+            order = np.argsort(th)
+            r.update({"CD": cd, "steps": s.clock()["step"], "wall_points": int(len(ut)),
+                      "max_abs_slip": float(np.max(np.abs(ut))),
+                      "zigzag_rms_rel": float(np.sqrt(np.mean(resid ** 2)) / np.max(np.abs(ut))),
+                      "theta": [round(float(x), 4) for x in th[order]],
+                      "slip": [round(float(x), 5) for x in ut[order]]})
+        except ibdvm.IbdvmError as e:
+            # an unstable context answers every later call with IBDVM_E_STATE
+            r = {"status": f"failed: {e}", "steps_launched": done}
+        g.close()
+        s.close()
+        torch.cuda.empty_cache()
+        out[tag] = r
+        print(f"slip study: {tag}: {r.get('zigzag_rms_rel', r['status'])}", file=sys.stderr, flush=True)
+    return out
+
+
 def _l1(a, b):
     import numpy as np
     return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
@@ -368,6 +423,41 @@ def vmesh_study(levels, nref, t_end, beta):
         errs = {}
         for vn in levels:
             r = _steady(cases.case(**dict(base, vn=(vn, vn), **extra)), t_end, f"vmesh {tag} {vn}^2")
+            w = r["wall"][3]
+            errs[str(vn)] = {"CD": abs(r["wall"][1] - cd_ref) / abs(cd_ref), "p_w": _l1(w[:, 7], W[:, 7]),
+                             "tau_w": _l1(w[:, 8:10], W[:, 8:10]), "q_n": _l1(w[:, 11], W[:, 11]),
+                             "steps": r["steps"]}
+        out[tag] = errs
+    return out
+
+
+def refined_study(levels, nref, n, t_end, amp, width):
+    """Locally refined velocity grid (R35) against uniform grids on the
+    hypersonic cylinder, where the freestream Maxwellian (centred at
+    U_inf = 4.56) and the wall Maxwellian (centred at 0) are narrow against
+    the [-10,10]^2 velocity box (the reason for the paper's refined sphere
+    mesh in Section 4): R = 1 at Ma 5, Kn 0.1, T_w = 1 on n x n cells of
+    [-6,10] x [-8,8], steady state at t_end; velocity grids of levels^2
+    nodes, uniform midpoint and refined (density 1 + amp(exp(-(x/w)^2) +
+    exp(-((x - U_inf)/w)^2)) on x, one bump at 0 on y), against a uniform
+    nref^2 reference.  Relative C_D error and L1 errors of p_w, tau_w and q_n
+    over the wall points; the same N costs the same per step."""
+    from paper_2512_20252_amd import cases
+
+    uinf = 5.0 * (5.0 / 6.0) ** 0.5
+    base = cases.case(dim=2, n=(n, n), lo=(-6.0, -8.0), hi=(10.0, 8.0), vlo=(-10.0, -10.0), vhi=(10.0, 10.0),
+                      geometry="circle", size=(1.0, 0.0, 0.0), Kn=0.1, Ma=5.0)
+    ref = _steady(cases.case(**dict(base, vn=(nref, nref))), t_end, f"refined study reference {nref}^2", 500)
+    cd_ref, W = ref["wall"][1], ref["wall"][3]
+    out = {"workload": f"2D cylinder R=1 at Ma 5, Kn 0.1, {n}^2 cells on [-6,10]x[-8,8], velocity grids "
+                       f"{'/'.join(str(v) for v in levels)} squared on [-10,10]^2, uniform and refined (amp {amp}, "
+                       f"width {width}, centres 0 and U_inf on x), against uniform {nref}^2, t = {t_end}",
+           "reference": {"CD": cd_ref, "steps": ref["steps"]}}
+    for tag, extra in (("uniform", {}), ("refined", {"rule": "refined", "vref_amp": amp, "vref_width": width,
+                                                     "vref_centre": (uinf, 0.0, 0.0)})):
+        errs = {}
+        for vn in levels:
+            r = _steady(cases.case(**dict(base, vn=(vn, vn), **extra)), t_end, f"refined study {tag} {vn}^2", 500)
             w = r["wall"][3]
             errs[str(vn)] = {"CD": abs(r["wall"][1] - cd_ref) / abs(cd_ref), "p_w": _l1(w[:, 7], W[:, 7]),
                              "tau_w": _l1(w[:, 8:10], W[:, 8:10]), "q_n": _l1(w[:, 11], W[:, 11]),
@@ -633,6 +723,11 @@ def main():
     ap.add_argument("--sweep-sphere-only", action="store_true", help="run only the sphere case of the precision sweep")
     ap.add_argument("--vmesh-study", action="store_true",
                     help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
+    ap.add_argument("--refined-study", action="store_true",
+                    help="add the refined-vs-uniform velocity-grid study on the Ma-5 cylinder (about 2 minutes)")
+    ap.add_argument("--slip-study", action="store_true",
+                    help="add the wall-slip comparison of the upwind weights, uniform weights and the naive "
+                         "extrapolation on the Ma-5 cylinder (about a minute)")
     ap.add_argument("--cavity-study", action="store_true",
                     help="add the cavity's velocity-space convergence study (about 4 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -734,6 +829,10 @@ def main():
                                                   20000)
     if args.vmesh_study:
         line["vmesh_study"] = vmesh_study([8, 12, 16, 24, 32], 128, 30.0, 1.5)
+    if args.refined_study:
+        line["refined_study"] = refined_study([24, 32, 48], 120, 96, 12.0, 3.0, 1.0)
+    if args.slip_study:
+        line["slip_study"] = slip_study(256, 12.0)
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:

@@ -68,7 +68,7 @@ typedef enum {
  * value at the mirrored velocity, so the walls pass no mass and no energy
  * (needs a velocity grid symmetric about 0, which every grid here is) */
 enum { IBDVM_OUTER_FREESTREAM = 0, IBDVM_OUTER_PERIODIC = 1, IBDVM_OUTER_WALLS = 2, IBDVM_OUTER_SPECULAR = 3 };
-enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1, IBDVM_RULE_STRETCHED = 2 };
+enum { IBDVM_RULE_MIDPOINT = 0, IBDVM_RULE_TRAPEZOID = 1, IBDVM_RULE_STRETCHED = 2, IBDVM_RULE_REFINED = 3 };
 enum {
     IBDVM_GEOM_NONE = 0,
     IBDVM_GEOM_CIRCLE = 1,  /* 2D, size[0] = radius */
@@ -133,6 +133,16 @@ typedef struct {
     double lo[3], hi[3];
     int32_t rule;
     double stretch; /* IBDVM_RULE_STRETCHED: beta in (0, 20]; else ignored */
+    /* IBDVM_RULE_REFINED (a locally refined tensor grid, the refined
+     * velocity mesh of the Section 4 sphere case in tensor form): per axis a
+     * node density 1 + refine_amp (exp(-(x/w)^2) + exp(-((x - c)/w)^2)),
+     * w = refine_width, c = refine_centre[a] (one bump when c = 0; e.g. c =
+     * U_inf on x refines around both the wall and the freestream
+     * Maxwellians); nodes and dual cells are the images of the uniform
+     * midpoint cells of u in [-1, 1] under the inverse of the normalised
+     * cumulative density, each weight its cell's width; refine_amp >= 0,
+     * refine_width > 0, |c| < hi; else ignored */
+    double refine_amp, refine_width, refine_centre[3];
 } ibdvm_vgrid;
 
 typedef struct {

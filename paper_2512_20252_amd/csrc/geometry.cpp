@@ -240,6 +240,47 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
         g.wa[a].resize(N);
         g.ea0[a].resize(N);
         g.ea1[a].resize(N);
+        if (p.rule == 3) {
+            // refined grid: density 1 + A sum_c exp(-((x - c)/w)^2) over the
+            // centres 0 and c_a; its cumulative from -V in closed form (erf)
+            // is inverted by bisection at u = m/N; an axis with the one
+            // centre at 0 has an even density, and its negative half is the
+            // mirror of the positive one
+            const double V = p.vhi[a], A = p.vref_amp, w = p.vref_width;
+            const double cen[2] = {0.0, p.vref_centre[a]};
+            const int nc = p.vref_centre[a] != 0.0 ? 2 : 1;
+            auto cum = [&](double x) {
+                double s = x + V;
+                for (int i = 0; i < nc; ++i)
+                    s += A * w * 0.5 * std::sqrt(M_PI) * (std::erf((x - cen[i]) / w) - std::erf((-V - cen[i]) / w));
+                return s;
+            };
+            const double total = cum(V);
+            auto inv = [&](int k) {  // the point where the normalised cumulative reaches k/N
+                if (k <= -N) return -V;
+                if (k >= N) return V;
+                const double t = 0.5 * ((double)k / (double)N + 1.0) * total;
+                double lo = -V, hi = V;
+                for (int it = 0; it < 200; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (mid == lo || mid == hi) break;
+                    if (cum(mid) < t)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                return 0.5 * (lo + hi);
+            };
+            auto map = [&](int k) { return nc == 1 && k == 0 ? 0.0 : (nc == 1 && k < 0 ? -inv(-k) : inv(k)); };
+            g.dxi[a] = 0.0;
+            for (int i = 0; i < N; ++i) {
+                g.xa[a][i] = map(2 * i + 1 - N);
+                g.ea0[a][i] = map(2 * i - N);
+                g.ea1[a][i] = map(2 * i + 2 - N);
+                g.wa[a][i] = g.ea1[a][i] - g.ea0[a][i];
+            }
+            continue;
+        }
         if (p.rule == 2) {
             const double V = p.vhi[a], beta = p.vstretch;
             auto map = [&](int m) { return V * std::sinh(beta * ((double)m / (double)N)) / std::sinh(beta); };

@@ -25,6 +25,7 @@ struct Problem {
     double vlo[3] = {0, 0, 0}, vhi[3] = {0, 0, 0};
     int rule = 0;
     double vstretch = 0;
+    double vref_amp = 0, vref_width = 1, vref_centre[3] = {0, 0, 0};  // refined rule
     int gkind = 0;
     double gcen[3] = {0, 0, 0}, gsize[3] = {0, 0, 0}, aoa = 0;
     uint32_t flags = 0;

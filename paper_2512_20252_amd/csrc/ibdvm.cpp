@@ -20,8 +20,8 @@
 static_assert(ibdvm::kFlagImplicit == IBDVM_FLAG_IMPLICIT_COLLISION, "device flag bit of the semi-implicit collision");
 static_assert(ibdvm::kFlagFaceLimit == IBDVM_FLAG_FACE_LIMIT, "device flag bit of the face limit");
 static_assert(ibdvm::kFlagNaive == IBDVM_FLAG_NAIVE_EXTRAPOLATION, "device flag bit of the naive extrapolation");
-static_assert(ibdvm::kOuterWalls == IBDVM_OUTER_WALLS && ibdvm::kOuterSpecular == IBDVM_OUTER_SPECULAR &&
-                  ibdvm::kOuterPeriodic == IBDVM_OUTER_PERIODIC, "device codes of the outer boundaries");
+static_assert((int)ibdvm::kOuterWalls == (int)IBDVM_OUTER_WALLS && (int)ibdvm::kOuterSpecular == (int)IBDVM_OUTER_SPECULAR &&
+                  (int)ibdvm::kOuterPeriodic == (int)IBDVM_OUTER_PERIODIC, "device codes of the outer boundaries");
 
 namespace {
 
@@ -131,8 +131,23 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
         return fail(IBDVM_E_INVALID_ARG, "lid speed must be finite");
     p.outer = grid->outer_bc;
     p.lid_u = grid->outer_bc == IBDVM_OUTER_WALLS ? grid->lid_u : 0.0;
-    if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID && vg->rule != IBDVM_RULE_STRETCHED)
+    if (vg->rule != IBDVM_RULE_MIDPOINT && vg->rule != IBDVM_RULE_TRAPEZOID && vg->rule != IBDVM_RULE_STRETCHED &&
+        vg->rule != IBDVM_RULE_REFINED)
         return fail(IBDVM_E_INVALID_ARG, "unknown quadrature rule");
+    if (vg->rule == IBDVM_RULE_REFINED) {
+        if (!(vg->refine_amp >= 0.0 && std::isfinite(vg->refine_amp)) ||
+            !(vg->refine_width > 0.0 && std::isfinite(vg->refine_width)))
+            return fail(IBDVM_E_INVALID_ARG, "refinement amplitude must be >= 0 and width > 0");
+        for (int a = 0; a < grid->dim; ++a) {
+            if (!(std::fabs(vg->refine_centre[a]) < vg->hi[a]))
+                return fail(IBDVM_E_INVALID_ARG, "refinement centre must lie inside the velocity box");
+            if (grid->outer_bc == IBDVM_OUTER_SPECULAR && vg->refine_centre[a] != 0.0)
+                return fail(IBDVM_E_INVALID_ARG, "specular walls need nodes symmetric about 0 (refinement centre 0)");
+            p.vref_centre[a] = vg->refine_centre[a];
+        }
+        p.vref_amp = vg->refine_amp;
+        p.vref_width = vg->refine_width;
+    }
     if (vg->rule == IBDVM_RULE_STRETCHED && !(vg->stretch > 0.0 && vg->stretch <= 20.0))
         return fail(IBDVM_E_INVALID_ARG, "stretch must be in (0, 20]");
     p.rule = vg->rule;

@@ -2,50 +2,63 @@
 drag and lift of the 2D cylinder at the 64^2 x 24^2 reduction of the
 256^2 x 48^2 workload (domain [-8,8]^2, radius 0.5, velocity grid on
 [-6,6]^2) for Kn in {0.01, 0.1, 1} x Ma in {0.3, 2}, each from the seed
-perturbation of its case index, run until |C_D(n) - C_D(n - 100)| < 1e-6.
+perturbation of its case index, run until C_D changes by less than 1e-6
+relative over 100 steps (or 20000 steps).
 
-Calls only the CPU oracle and the seeded case definitions.  Run from the
+Calls only the CPU oracle and the seeded case definitions; the six cases
+run in parallel processes of one OpenMP thread each.  Run from the
 repository root: python tests/golden/make_converged_cd.py
 """
 import json
+import multiprocessing as mp
 import os
 import sys
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-sys.path.insert(0, ROOT)
-from oracle import oracle as oracle_mod  # noqa: E402
-from paper_2512_20252_amd import cases  # noqa: E402
-
-N, VN, BLOCK, TOL, CAP = 64, 24, 100, 1e-6, 40000
+N, VN, BLOCK, RTOL, CAP = 64, 24, 100, 1e-6, 20000
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "converged_cd_cylinder_64x64_v24x24.json")
 
 
+def run_case(seed):
+    sys.path.insert(0, ROOT)
+    from oracle import oracle as oracle_mod
+    from paper_2512_20252_amd import cases
+
+    oracle_mod.set_threads(1)
+    Kn, Ma = cases.CYLINDER_256_SWEEP[seed]
+    c = cases.cylinder_256(Kn=Kn, Ma=Ma, n=N, vn=VN)
+    o = oracle_mod.Oracle(c)
+    o.init_freestream(cases.noise(c, seed), 1e-3)
+    prev, steps, change = None, 0, None
+    while steps < CAP:
+        o.step(BLOCK)
+        steps += BLOCK
+        _, cd, cl, _ = o.forces()
+        change = abs(cd - prev) / abs(cd) if prev is not None else None
+        prev = cd
+        if change is not None and change < RTOL:
+            break
+    m = o.moments()
+    ok = np.isfinite(m[:, 0])
+    row = {"Kn": Kn, "Ma": Ma, "seed": seed, "steps": steps, "converged": change is not None and change < RTOL,
+           "C_D": cd, "C_L": cl, "last_block_rel_change": change,
+           "rho_l2": float(np.linalg.norm(m[ok, 0])), "T_l2": float(np.linalg.norm(m[ok, 4])),
+           "time": o.clock()["time"]}
+    print(row, flush=True)
+    return row
+
+
 def main():
-    rows = []
-    for seed, (Kn, Ma) in enumerate(cases.CYLINDER_256_SWEEP):
-        c = cases.cylinder_256(Kn=Kn, Ma=Ma, n=N, vn=VN)
-        o = oracle_mod.Oracle(c)
-        o.init_freestream(cases.noise(c, seed), 1e-3)
-        prev, steps = None, 0
-        while steps < CAP:
-            o.step(BLOCK)
-            steps += BLOCK
-            _, cd, cl, _ = o.forces()
-            if prev is not None and abs(cd - prev) < TOL:
-                break
-            prev = cd
-        m = o.moments()
-        ok = np.isfinite(m[:, 0])
-        rows.append({"Kn": Kn, "Ma": Ma, "seed": seed, "steps": steps, "converged": steps < CAP,
-                     "C_D": cd, "C_L": cl, "last_block_change": abs(cd - prev),
-                     "rho_l2": float(np.linalg.norm(m[ok, 0])), "T_l2": float(np.linalg.norm(m[ok, 4])),
-                     "time": o.clock()["time"]})
-        print(rows[-1], flush=True)
+    sys.path.insert(0, ROOT)
+    from paper_2512_20252_amd import cases
+
+    with mp.get_context("spawn").Pool(len(cases.CYLINDER_256_SWEEP)) as pool:
+        rows = pool.map(run_case, range(len(cases.CYLINDER_256_SWEEP)))
     doc = {"source": "tests/golden/make_converged_cd.py (CPU oracle, FP64)",
            "case": {"n": N, "vn": VN, "domain": [-8.0, 8.0], "radius": 0.5, "velocity_box": [-6.0, 6.0],
-                    "noise_amp": 1e-3, "block": BLOCK, "tol": TOL},
+                    "noise_amp": 1e-3, "block": BLOCK, "rel_tol": RTOL, "cap": CAP},
            "rows": rows}
     with open(OUT, "w") as fh:
         json.dump(doc, fh, indent=1)

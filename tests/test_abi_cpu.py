@@ -46,6 +46,12 @@ GEOMS = {
     # stretched velocity grids (non-uniform dual cells in the cut-cell sets)
     "stretched_2d": lambda: dict(cases.cylinder_small(), rule="stretched", vstretch=1.5, vn=(17, 14)),
     "stretched_3d": lambda: dict(cases.sphere(n=28, vn=9), rule="stretched", vstretch=1.1),
+    # locally refined velocity grids (R35), symmetric and with a second centre
+    "refined_2d": lambda: dict(cases.cylinder_small(), rule="refined", vref_amp=3.0, vref_width=0.9,
+                               vref_centre=(0.45, 0.0, 0.0), vn=(21, 18)),
+    "refined_2d_sym": lambda: dict(cases.cylinder_small(), rule="refined", vref_amp=2.0, vref_width=1.3, vn=(19, 19)),
+    "refined_3d": lambda: dict(cases.sphere(n=20, vn=9), rule="refined", vref_amp=2.0, vref_width=1.1,
+                               vref_centre=(1.3, 0.0, 0.0)),
     # the no-donor-slope ablation: every pair without an auxiliary cell (R10)
     "no_aux": lambda: dict(cases.cylinder_small(), flags=("no_aux",)),
 }

@@ -211,3 +211,44 @@ def test_specular_and_moving_wall_in_batches(torch_cuda):
         for a, b in zip(s.get_state(), ref):
             assert np.array_equal(a, b)
     g.close()
+
+
+REFINED = dict(rule="refined", vref_amp=3.0, vref_width=0.9, vref_centre=(0.45, 0.0, 0.0), vn=(21, 18))
+
+
+@pytest.mark.parametrize("precision,tile", [("f64", (2, 4, 64)), ("f64", (1, 8, 5)), ("f32", (2, 4, 32))])
+def test_refined_velocity_grid_agrees_with_oracle(oracle_mod, torch_cuda, precision, tile):
+    """The locally refined velocity grid (R35, second centre on x) on the
+    32^2 cylinder with partial accommodation (the specular part
+    interpolates on the non-uniform nodes): ghost values, state, moments
+    and C_D agree with the oracle."""
+    c = cases.case(**dict(cases.cylinder_small(), alpha=0.7, **REFINED))
+    o, s = _pair(oracle_mod, c, precision=precision, tile=tile)
+    if precision == "f64":
+        ws, od = s.wall_state(), o.fill_debug()
+        for A in range(2):
+            assert _rel(ws["ghost"][A], od["ghost"][A]) <= TOL64
+    o.step(8)
+    s.step(8)
+    _, cdo, _, _ = o.forces()
+    _, cdg, _, _ = s.surface_forces()
+    if precision == "f64":
+        _compare(o, s)
+        assert abs(cdg - cdo) <= TOL64 * abs(cdo)
+    else:
+        mg, mo = s.moments(), o.moments()
+        ok = np.isfinite(mo[:, 0])
+        for j in (0, 1, 2, 4):
+            assert np.linalg.norm(mg[ok, j] - mo[ok, j]) / np.linalg.norm(mo[ok, j]) <= 1e-5, j
+        assert abs(cdg - cdo) <= 1e-4
+
+
+def test_refined_velocity_grid_3d(oracle_mod, torch_cuda):
+    """The refined grid in 3D (centres 0 and 1.3 on x) on a sphere with
+    alpha = 0.8 (trilinear mirror interpolation on non-uniform nodes)."""
+    c = cases.case(**dict(cases.sphere(n=20, vn=9), alpha=0.8, rule="refined", vref_amp=2.0, vref_width=1.1,
+                          vref_centre=(1.3, 0.0, 0.0)))
+    o, s = _pair(oracle_mod, c, tile=(1, 16, 9))
+    o.step(4)
+    s.step(4)
+    _compare(o, s)
