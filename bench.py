@@ -320,22 +320,24 @@ def implicit_collision(Kn, steps, warmup):
     return out
 
 
-def _steady(case, t_end, tag, block=1000):
+def _steady(case, t_end, tag, block=1000, precision="f64"):
     """Run a solve from its freestream (rest for Ma 0) to time t_end in
     replays of a captured graph of `block` steps; moments, wall points,
     step count, last residual and wall time."""
     import torch
     from paper_2512_20252_amd import ibdvm
 
-    s = ibdvm.Solver(case, stream=torch.cuda.Stream())
+    s = ibdvm.Solver(case, precision=precision, stream=torch.cuda.Stream())
     s.init_freestream()
     g = ibdvm.Graph(s, block)
     t0, k = time.perf_counter(), 0
+    last = t0
     try:
         while s.clock()["time"] < t_end:
             g.launch()
             k += 1
-            if k % 20 == 0:
+            if time.perf_counter() - last > 20.0:
+                last = time.perf_counter()
                 print(f"{tag}: t = {s.clock()['time']:.1f}", file=sys.stderr, flush=True)
         s.step(2)
         r = {"m": s.moments(), "wall": s.surface_forces(), "steps": s.clock()["step"],
@@ -447,7 +449,8 @@ def refined_study(levels, nref, n, t_end, amp, width, shapes=None):
     mesh in Section 4): R = 1 at Ma 5, Kn 0.1, T_w = 1 on n x n cells of
     [-6,10] x [-8,8], steady state at t_end; velocity grids of levels^2
     nodes, uniform midpoint and refined (density 1 + amp(exp(-(x/w)^2) +
-    exp(-((x - U_inf)/w)^2)) on x, one bump at 0 on y), against a uniform
+    exp(-((x - U_inf)/w)^2)) on x, one bump at 0 on y) with dual-cell weights
+    (R35) and with the map's derivative as weight (R36), against a uniform
     nref^2 reference.  Relative C_D error and L1 errors of p_w, tau_w and q_n
     over the wall points; the same N costs the same per step."""
     from paper_2512_20252_amd import cases
@@ -461,9 +464,10 @@ def refined_study(levels, nref, n, t_end, amp, width, shapes=None):
                        f"{'/'.join(str(v) for v in levels)} squared on [-10,10]^2, uniform and refined (amp {amp}, "
                        f"width {width}, centres 0 and U_inf on x), against uniform {nref}^2, t = {t_end}",
            "reference": {"CD": cd_ref, "steps": ref["steps"]}}
-    runs = [("uniform", {})] + [(f"refined_A{a}_w{w}", {"rule": "refined", "vref_amp": a, "vref_width": w,
-                                                         "vref_centre": (uinf, 0.0, 0.0)})
-                                for a, w in (shapes or [(amp, width)])]
+    runs = [("uniform", {})] + [(f"refined_A{a}_w{w}" + ("_jacobian" if wt == "jacobian" else ""),
+                                 {"rule": "refined", "vref_amp": a, "vref_width": w, "vref_centre": (uinf, 0.0, 0.0),
+                                  "vweights": wt})
+                                for wt in ("cell", "jacobian") for a, w in (shapes or [(amp, width)])]
     for tag, extra in runs:
         errs = {}
         for vn in levels:
@@ -475,6 +479,51 @@ def refined_study(levels, nref, n, t_end, amp, width, shapes=None):
             errs[str(vn)] = {"CD": abs(r["wall"][1] - cd_ref) / abs(cd_ref), "p_w": _l1(w[:, 7], W[:, 7]),
                              "tau_w": _l1(w[:, 8:10], W[:, 8:10]), "q_n": _l1(w[:, 11], W[:, 11]),
                              "steps": r["steps"]}
+        out[tag] = errs
+    return out
+
+
+def sphere_vmesh_study(n, levels, nref, t_end, amp, width, block=200):
+    """Velocity meshes of the Section 4 sphere: Ma 3.834, wall at the
+    stagnation temperature T_w = 1 + (gamma - 1) Ma^2 / 2, velocity box
+    [-3 sqrt(T_w), 3 sqrt(T_w)]^3, here at Kn 0.1 on n^3 cells of [-4,4]^3
+    (R = 0.5), FP32 storage of f; uniform midpoint grids of levels^3 nodes
+    and refined grids with the map's derivative as weight (R36; density
+    1 + amp(exp(-(x/w)^2) + exp(-((x - U_inf)/w)^2)) on x, one bump at 0 on
+    y and z), against a uniform nref^3 reference, each run to time t_end.
+    Relative C_D error and L1 errors of p_w, tau_w and q_n over the wall
+    points."""
+    from paper_2512_20252_amd import cases
+
+    Ma, gam = 3.834, 5.0 / 3.0
+    Tw = 1.0 + 0.5 * (gam - 1.0) * Ma * Ma
+    V = 3.0 * Tw ** 0.5
+    uinf = Ma * (gam / 2.0) ** 0.5
+    base = cases.case(**dict(cases.sphere(n=n, vn=nref), Ma=Ma, Tw=Tw, vlo=(-V,) * 3, vhi=(V,) * 3))
+
+    def run(vn, extra, tag):
+        return _steady(cases.case(**dict(base, vn=(vn,) * 3, **extra)), t_end, tag, block, precision="f32")
+
+    ref = run(nref, {}, f"sphere study reference {nref}^3")
+    cd_ref, W = ref["wall"][1], ref["wall"][3]
+    out = {"workload": f"3D sphere R=0.5 at Ma {Ma}, Kn 0.1, T_w {Tw:.3f}, {n}^3 cells on [-4,4]^3, velocity box "
+                       f"[-{V:.3f},{V:.3f}]^3, uniform and refined (amp {amp}, width {width}, Jacobian weights) grids "
+                       f"of {'/'.join(str(v) for v in levels)} cubed against uniform {nref}^3, FP32 storage of f, "
+                       f"t = {t_end}",
+           "reference": {"CD": cd_ref, "steps": ref["steps"], "seconds": ref["seconds"]}}
+    refined = {"rule": "refined", "vref_amp": amp, "vref_width": width, "vref_centre": (uinf, 0.0, 0.0),
+               "vweights": "jacobian"}
+    for tag, extra in (("uniform", {}), ("refined_jacobian", refined)):
+        errs = {}
+        for vn in levels:
+            r = run(vn, extra, f"sphere study {tag} {vn}^3")
+            if "failed" in r:
+                errs[str(vn)] = {"failed": r["failed"], "steps_launched": r["steps_launched"]}
+                continue
+            w = r["wall"][3]
+            errs[str(vn)] = {"CD": abs(r["wall"][1] - cd_ref) / abs(cd_ref), "p_w": _l1(w[:, 7], W[:, 7]),
+                             "tau_w": _l1(w[:, 8:11], W[:, 8:11]), "q_n": _l1(w[:, 11], W[:, 11]),
+                             "steps": r["steps"], "seconds": r["seconds"]}
         out[tag] = errs
     return out
 
@@ -739,6 +788,8 @@ def main():
                     help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
     ap.add_argument("--refined-study", action="store_true",
                     help="add the refined-vs-uniform velocity-grid study on the Ma-5 cylinder (about 2 minutes)")
+    ap.add_argument("--sphere-vmesh-study", action="store_true",
+                    help="add the uniform-vs-refined velocity-grid study on the Section 4 sphere (about 10 minutes)")
     ap.add_argument("--slip-study", action="store_true",
                     help="add the wall-slip comparison of the upwind weights, uniform weights and the naive "
                          "extrapolation on the Ma-5 cylinder (about a minute)")
@@ -846,6 +897,8 @@ def main():
     if args.refined_study:
         line["refined_study"] = refined_study([24, 32, 48], 120, 96, 12.0, 3.0, 1.0,
                                               shapes=[(3.0, 1.0), (2.0, 1.5), (1.0, 1.5)])
+    if args.sphere_vmesh_study:
+        line["sphere_vmesh_study"] = sphere_vmesh_study(48, [16, 24, 32], 48, 8.0, 2.0, 1.5)
     if args.slip_study:
         line["slip_study"] = slip_study(256, 12.0)
     if args.cavity_study:

@@ -51,6 +51,13 @@
  * of its normalised cumulative */
 #define OR_RULE_REFINED 3
 
+/* node weights of the mapped grids (stretched and refined): the width of
+ * the node's dual cell, or (reading R36) the derivative of the map at the
+ * node times the width of its u-cell, the midpoint rule of the integral
+ * in u; cut cells keep their incident fraction of the dual cell */
+#define OR_WEIGHTS_CELL 0
+#define OR_WEIGHTS_JACOBIAN 1
+
 #define OR_FLAG_NO_CUTCELL 1u
 #define OR_FLAG_NO_UPWIND 2u
 /* semi-implicit collision (reading R30): explicit transport, then the
@@ -98,6 +105,7 @@ typedef struct {
     double Uw[3], Ow[3];
     /* OR_RULE_REFINED: amplitude A, width w and second centre c per axis */
     double vref_amp, vref_width, vref_centre[3];
+    int vweights; /* OR_WEIGHTS_*: mapped grids only */
 } or_case;
 
 typedef struct {
@@ -323,7 +331,7 @@ static double refine_inverse(double u, double V, double A, double w, const doubl
 
 /* nodes, weights and dual cells [e0, e1] of one axis */
 static void velocity_axis(int N, double lo, double hi, int rule, double beta, double *x, double *w, double *e0,
-                          double *e1, double *d, double ramp, double rwidth, double rcentre)
+                          double *e1, double *d, double ramp, double rwidth, double rcentre, int jac)
 {
     if (rule == OR_RULE_REFINED) {
         /* node i at u = (2i + 1 - N)/N, its dual cell between the images of
@@ -349,7 +357,18 @@ static void velocity_axis(int N, double lo, double hi, int rule, double beta, do
                 x[m / 2] = v;
             }
         }
-        for (int i = 0; i < N; ++i) w[i] = e1[i] - e0[i];
+        /* Jacobian weights: the normalised cumulative maps x(u) to u, so
+         * x'(u) = total / (2 rho(x)) and the u-cell is 2/N wide */
+        const double total = refine_cum(V, V, ramp, rwidth, cs, nc);
+        for (int i = 0; i < N; ++i) {
+            if (jac) {
+                double rho = 1.0;
+                for (int c = 0; c < nc; ++c) rho += ramp * exp(-((x[i] - cs[c]) / rwidth) * ((x[i] - cs[c]) / rwidth));
+                w[i] = total / ((double)N * rho);
+            } else {
+                w[i] = e1[i] - e0[i];
+            }
+        }
         *d = 0.0;
         return;
     }
@@ -361,7 +380,11 @@ static void velocity_axis(int N, double lo, double hi, int rule, double beta, do
             x[i] = stretch_map(V, beta, 2 * i + 1 - N, N);
             e0[i] = stretch_map(V, beta, 2 * i - N, N);
             e1[i] = stretch_map(V, beta, 2 * i + 2 - N, N);
-            w[i] = e1[i] - e0[i];
+            /* Jacobian weights: x'(u) = V beta cosh(beta u) / sinh(beta) */
+            if (jac)
+                w[i] = V * beta * cosh(beta * ((double)(2 * i + 1 - N) / (double)N)) / sinh(beta) * (2.0 / (double)N);
+            else
+                w[i] = e1[i] - e0[i];
         }
         *d = 0.0;
         return;
@@ -496,6 +519,12 @@ static void build_cut_sets(const or_state *s, const double n[3], unsigned char *
                 wg[k] = clip_area(e0[0], e1[0], e0[1], e1[1], n[0], n[1], 0.0);
             else
                 wg[k] = clip_volume(e0, e1, n);
+            if (s->c.vweights == OR_WEIGHTS_JACOBIAN) {
+                /* the incident fraction of the dual cell, of the node's weight */
+                double vol = 1.0;
+                for (int a = 0; a < D; ++a) vol *= e1[a] - e0[a];
+                wg[k] = wg[k] / vol * s->w[k];
+            }
         }
     }
 }
@@ -665,6 +694,9 @@ void *or_create(const or_case *cs, int *err)
             if (!(cs->vref_amp >= 0.0) || !(cs->vref_width > 0.0) || cs->vlo[a] != -cs->vhi[a] ||
                 !(fabs(cs->vref_centre[a]) < cs->vhi[a]))
                 *err = 1;
+    if (cs->vweights != OR_WEIGHTS_CELL &&
+        !(cs->vweights == OR_WEIGHTS_JACOBIAN && (cs->vrule == OR_RULE_STRETCHED || cs->vrule == OR_RULE_REFINED)))
+        *err = 1;
     if (cs->vrule == OR_RULE_REFINED && cs->outer == OR_SPECULAR)
         for (int a = 0; a < D; ++a)
             if (cs->vref_centre[a] != 0.0) *err = 1; /* mirrored nodes must be nodes */
@@ -675,7 +707,8 @@ void *or_create(const or_case *cs, int *err)
         s->ed0[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
         s->ed1[a] = (double *)malloc(sizeof(double) * cs->vn[a]);
         velocity_axis(cs->vn[a], cs->vlo[a], cs->vhi[a], cs->vrule, cs->vstretch, s->xi1[a], s->w1[a], s->ed0[a],
-                      s->ed1[a], &s->dxi[a], cs->vref_amp, cs->vref_width, cs->vref_centre[a]);
+                      s->ed1[a], &s->dxi[a], cs->vref_amp, cs->vref_width, cs->vref_centre[a],
+                      cs->vweights == OR_WEIGHTS_JACOBIAN);
         s->maxabs[a] = 0.0;
         for (int i = 0; i < cs->vn[a]; ++i)
             if (fabs(s->xi1[a][i]) > s->maxabs[a]) s->maxabs[a] = fabs(s->xi1[a][i]);

@@ -18,6 +18,7 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
 RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2, "refined": 3}
+WEIGHTS = {"cell": 0, "jacobian": 1}
 # "f32_absolute" selects how the library stores FP32 values; the FP64 oracle
 # has no such choice and ignores it
 FLAGS = {"no_cutcell": 1, "no_upwind": 2, "implicit": 4, "face_limit": 8, "naive": 16, "no_aux": 32,
@@ -45,7 +46,8 @@ class _Case(ctypes.Structure):
                 ("Tw", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
                 ("avhs", ctypes.c_double), ("flags", ctypes.c_int), ("lid_u", ctypes.c_double),
                 ("vstretch", ctypes.c_double), ("Uw", ctypes.c_double * 3), ("Ow", ctypes.c_double * 3),
-                ("vref_amp", ctypes.c_double), ("vref_width", ctypes.c_double), ("vref_centre", ctypes.c_double * 3)]
+                ("vref_amp", ctypes.c_double), ("vref_width", ctypes.c_double), ("vref_centre", ctypes.c_double * 3),
+                ("vweights", ctypes.c_int)]
 
 
 _lib = None
@@ -139,6 +141,7 @@ def _case_struct(case):
     rc = case.get("vref_centre", (0.0, 0.0, 0.0))
     for a in range(3):
         c.vref_centre[a] = rc[a] if a < len(rc) else 0.0
+    c.vweights = WEIGHTS[case.get("vweights", "cell")]
     return c
 
 

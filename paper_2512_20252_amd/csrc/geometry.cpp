@@ -277,7 +277,17 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
                 g.xa[a][i] = map(2 * i + 1 - N);
                 g.ea0[a][i] = map(2 * i - N);
                 g.ea1[a][i] = map(2 * i + 2 - N);
-                g.wa[a][i] = g.ea1[a][i] - g.ea0[a][i];
+                if (p.vweights) {
+                    // the map's derivative total / (2 rho(x)) times the u-cell width 2/N
+                    double rho = 1.0;
+                    for (int c = 0; c < nc; ++c) {
+                        const double z = (g.xa[a][i] - cen[c]) / w;
+                        rho += A * std::exp(-z * z);
+                    }
+                    g.wa[a][i] = total / ((double)N * rho);
+                } else {
+                    g.wa[a][i] = g.ea1[a][i] - g.ea0[a][i];
+                }
             }
             continue;
         }
@@ -289,7 +299,10 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
                 g.xa[a][i] = map(2 * i + 1 - N);
                 g.ea0[a][i] = map(2 * i - N);
                 g.ea1[a][i] = map(2 * i + 2 - N);
-                g.wa[a][i] = g.ea1[a][i] - g.ea0[a][i];
+                // Jacobian weights: V beta cosh(beta u) / sinh(beta) times 2/N
+                g.wa[a][i] = p.vweights ? V * beta * std::cosh(beta * ((double)(2 * i + 1 - N) / (double)N)) /
+                                              std::sinh(beta) * (2.0 / (double)N)
+                                        : g.ea1[a][i] - g.ea0[a][i];
             }
             continue;
         }
@@ -491,6 +504,12 @@ int build_geometry(const Problem &p, Geometry &g, std::string &err)
             } else {
                 g.cls[o] = dn <= 0.0 ? VC_CUT_G : VC_CUT_S;
                 g.wg[o] = incident_measure(D, e0, e1, n);
+                if (p.vweights) {
+                    // the incident fraction of the dual cell, of the node's weight
+                    double vol = 1.0;
+                    for (int a = 0; a < D; ++a) vol *= e1[a] - e0[a];
+                    g.wg[o] = g.wg[o] / vol * g.w[k];
+                }
             }
         }
     }

@@ -26,6 +26,7 @@ struct Problem {
     int rule = 0;
     double vstretch = 0;
     double vref_amp = 0, vref_width = 1, vref_centre[3] = {0, 0, 0};  // refined rule
+    int vweights = 0;  // 1: Jacobian weights of the mapped rules
     int gkind = 0;
     double gcen[3] = {0, 0, 0}, gsize[3] = {0, 0, 0}, aoa = 0;
     uint32_t flags = 0;

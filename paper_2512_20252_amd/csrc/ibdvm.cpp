@@ -152,6 +152,10 @@ ibdvm_status validate(const ibdvm_grid *grid, const ibdvm_vgrid *vg, const ibdvm
         return fail(IBDVM_E_INVALID_ARG, "stretch must be in (0, 20]");
     p.rule = vg->rule;
     p.vstretch = vg->rule == IBDVM_RULE_STRETCHED ? vg->stretch : 0.0;
+    if (vg->weights != IBDVM_WEIGHTS_CELL &&
+        !(vg->weights == IBDVM_WEIGHTS_JACOBIAN && (vg->rule == IBDVM_RULE_STRETCHED || vg->rule == IBDVM_RULE_REFINED)))
+        return fail(IBDVM_E_INVALID_ARG, "Jacobian weights need a stretched or refined velocity grid");
+    p.vweights = vg->weights;
     int k = geom->kind;
     bool ok2 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_CIRCLE || k == IBDVM_GEOM_ELLIPSE || k == IBDVM_GEOM_AIRFOIL;
     bool ok3 = k == IBDVM_GEOM_NONE || k == IBDVM_GEOM_SPHERE;

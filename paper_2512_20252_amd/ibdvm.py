@@ -18,6 +18,7 @@ OK, E_INVALID_ARG, E_GEOMETRY, E_NO_MEMORY, E_DEVICE, E_UNSTABLE, E_UNSUPPORTED,
 GEOMETRY = {"none": 0, "circle": 1, "ellipse": 2, "airfoil": 3, "sphere": 4}
 OUTER = {"freestream": 0, "periodic": 1, "walls": 2, "specular": 3}
 RULE = {"midpoint": 0, "trapezoid": 1, "stretched": 2, "refined": 3}
+WEIGHTS = {"cell": 0, "jacobian": 1}
 PRECISION = {"f64": 0, "f32": 1}
 FLAGS = {"no_cutcell": 1 << 0, "no_upwind": 1 << 1, "implicit": 1 << 2, "face_limit": 1 << 3, "naive": 1 << 4,
          "no_aux": 1 << 5, "f32_absolute": 1 << 6, "host_only": 1 << 8}
@@ -33,7 +34,7 @@ class Grid(ctypes.Structure):
 class VGrid(ctypes.Structure):
     _fields_ = [("n", c_int32 * 3), ("lo", c_double * 3), ("hi", c_double * 3), ("rule", c_int32),
                 ("stretch", c_double), ("refine_amp", c_double), ("refine_width", c_double),
-                ("refine_centre", c_double * 3)]
+                ("refine_centre", c_double * 3), ("weights", c_int32)]
 
 
 class Geom(ctypes.Structure):
@@ -171,6 +172,7 @@ def structs(case, precision="f64", flags=(), workspace=0, nbytes=0, stream=0):
     rc = case.get("vref_centre", (0.0, 0.0, 0.0))
     for a in range(3):
         v.refine_centre[a] = rc[a] if a < len(rc) else 0.0
+    v.weights = WEIGHTS[case.get("vweights", "cell")]
     ge = Geom()
     ge.kind = GEOMETRY[case.get("geometry", "none")]
     cen, size = case.get("center", (0, 0, 0)), case.get("size", (0, 0, 0))

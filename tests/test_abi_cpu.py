@@ -52,6 +52,13 @@ GEOMS = {
     "refined_2d_sym": lambda: dict(cases.cylinder_small(), rule="refined", vref_amp=2.0, vref_width=1.3, vn=(19, 19)),
     "refined_3d": lambda: dict(cases.sphere(n=20, vn=9), rule="refined", vref_amp=2.0, vref_width=1.1,
                                vref_centre=(1.3, 0.0, 0.0)),
+    # Jacobian weights of the mapped grids (R36): cut measures scale with the node weight
+    "refined_2d_jac": lambda: dict(cases.cylinder_small(), rule="refined", vref_amp=3.0, vref_width=0.9,
+                                   vref_centre=(0.45, 0.0, 0.0), vn=(21, 18), vweights="jacobian"),
+    "refined_3d_jac": lambda: dict(cases.sphere(n=20, vn=9), rule="refined", vref_amp=2.0, vref_width=1.1,
+                                   vref_centre=(1.3, 0.0, 0.0), vweights="jacobian"),
+    "stretched_2d_jac": lambda: dict(cases.cylinder_small(), rule="stretched", vstretch=1.5, vn=(17, 14),
+                                     vweights="jacobian"),
     # the no-donor-slope ablation: every pair without an auxiliary cell (R10)
     "no_aux": lambda: dict(cases.cylinder_small(), flags=("no_aux",)),
 }
@@ -103,6 +110,7 @@ def test_argument_validation():
     _expect(ibdvm.E_INVALID_ARG, mk(vn=(257, 16)))
     _expect(ibdvm.E_INVALID_ARG, mk(rule="stretched", vstretch=0.0))
     _expect(ibdvm.E_INVALID_ARG, mk(rule="stretched", vstretch=25.0))
+    _expect(ibdvm.E_INVALID_ARG, mk(vweights="jacobian"))  # a uniform rule has no map
     ibdvm.Solver(dict(base, vn=(256, 4)), host_only=True)
     _expect(ibdvm.E_INVALID_ARG, mk(geometry="sphere"))
     _expect(ibdvm.E_GEOMETRY, mk(size=(0.9, 0.0, 0.0)))

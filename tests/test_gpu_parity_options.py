@@ -216,13 +216,16 @@ def test_specular_and_moving_wall_in_batches(torch_cuda):
 REFINED = dict(rule="refined", vref_amp=3.0, vref_width=0.9, vref_centre=(0.45, 0.0, 0.0), vn=(21, 18))
 
 
-@pytest.mark.parametrize("precision,tile", [("f64", (2, 4, 64)), ("f64", (1, 8, 5)), ("f32", (2, 4, 32))])
-def test_refined_velocity_grid_agrees_with_oracle(oracle_mod, torch_cuda, precision, tile):
+@pytest.mark.parametrize("precision,tile,weights", [("f64", (2, 4, 64), "cell"), ("f64", (1, 8, 5), "cell"),
+                                                    ("f32", (2, 4, 32), "cell"), ("f64", (2, 4, 64), "jacobian"),
+                                                    ("f32", (2, 4, 32), "jacobian")])
+def test_refined_velocity_grid_agrees_with_oracle(oracle_mod, torch_cuda, precision, tile, weights):
     """The locally refined velocity grid (R35, second centre on x) on the
     32^2 cylinder with partial accommodation (the specular part
-    interpolates on the non-uniform nodes): ghost values, state, moments
-    and C_D agree with the oracle."""
-    c = cases.case(**dict(cases.cylinder_small(), alpha=0.7, **REFINED))
+    interpolates on the non-uniform nodes), with dual-cell weights and with
+    the map's derivative as weight (R36): ghost values, state, moments and
+    C_D agree with the oracle."""
+    c = cases.case(**dict(cases.cylinder_small(), alpha=0.7, vweights=weights, **REFINED))
     o, s = _pair(oracle_mod, c, precision=precision, tile=tile)
     if precision == "f64":
         ws, od = s.wall_state(), o.fill_debug()
@@ -243,11 +246,13 @@ def test_refined_velocity_grid_agrees_with_oracle(oracle_mod, torch_cuda, precis
         assert abs(cdg - cdo) <= 1e-4
 
 
-def test_refined_velocity_grid_3d(oracle_mod, torch_cuda):
+@pytest.mark.parametrize("weights", ["cell", "jacobian"])
+def test_refined_velocity_grid_3d(oracle_mod, torch_cuda, weights):
     """The refined grid in 3D (centres 0 and 1.3 on x) on a sphere with
-    alpha = 0.8 (trilinear mirror interpolation on non-uniform nodes)."""
+    alpha = 0.8 (trilinear mirror interpolation on non-uniform nodes), with
+    either weighting."""
     c = cases.case(**dict(cases.sphere(n=20, vn=9), alpha=0.8, rule="refined", vref_amp=2.0, vref_width=1.1,
-                          vref_centre=(1.3, 0.0, 0.0)))
+                          vref_centre=(1.3, 0.0, 0.0), vweights=weights))
     o, s = _pair(oracle_mod, c, tile=(1, 16, 9))
     o.step(4)
     s.step(4)
