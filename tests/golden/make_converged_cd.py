@@ -38,14 +38,16 @@ def run_case(seed):
         _, cd, cl, _ = o.forces()
         change = abs(cd - prev) / abs(cd) if prev is not None else None
         prev = cd
+        if steps % 2000 == 0:
+            print(f"Kn {Kn} Ma {Ma}: {steps} steps, C_D {cd:.8f}, relative change {change:.2e}", flush=True)
         if change is not None and change < RTOL:
             break
     m = o.moments()
     ok = np.isfinite(m[:, 0])
-    row = {"Kn": Kn, "Ma": Ma, "seed": seed, "steps": steps, "converged": change is not None and change < RTOL,
-           "C_D": cd, "C_L": cl, "last_block_rel_change": change,
-           "rho_l2": float(np.linalg.norm(m[ok, 0])), "T_l2": float(np.linalg.norm(m[ok, 4])),
-           "time": o.clock()["time"]}
+    row = {"Kn": float(Kn), "Ma": float(Ma), "seed": int(seed), "steps": int(steps),
+           "converged": bool(change is not None and change < RTOL), "C_D": float(cd), "C_L": float(cl),
+           "last_block_rel_change": float(change), "rho_l2": float(np.linalg.norm(m[ok, 0])),
+           "T_l2": float(np.linalg.norm(m[ok, 4])), "time": float(o.clock()["time"])}
     print(row, flush=True)
     return row
 
@@ -60,8 +62,9 @@ def main():
            "case": {"n": N, "vn": VN, "domain": [-8.0, 8.0], "radius": 0.5, "velocity_box": [-6.0, 6.0],
                     "noise_amp": 1e-3, "block": BLOCK, "rel_tol": RTOL, "cap": CAP},
            "rows": rows}
-    with open(OUT, "w") as fh:
+    with open(OUT + ".tmp", "w") as fh:
         json.dump(doc, fh, indent=1)
+    os.replace(OUT + ".tmp", OUT)
 
 
 if __name__ == "__main__":
