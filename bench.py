@@ -629,7 +629,7 @@ def fixed_cd_error(block=100):
     """FP32 storage against FP64 at a fixed C_D error: the cylinder's Kn x Ma
     sweep at the 64^2 x 24^2 reduction, each case run on the GPU in both
     forms for the step count at which the FP64 oracle's C_D had converged
-    (|dC_D| < 1e-6 |C_D| per 100 steps, or its 20000-step cap), against the
+    (|dC_D| < 1e-6 |C_D| per 100 steps, or its 10000-step cap), against the
     oracle's C_D stored in tests/golden by a script that runs only the
     oracle."""
     import torch

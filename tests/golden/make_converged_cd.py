@@ -3,7 +3,7 @@ drag and lift of the 2D cylinder at the 64^2 x 24^2 reduction of the
 256^2 x 48^2 workload (domain [-8,8]^2, radius 0.5, velocity grid on
 [-6,6]^2) for Kn in {0.01, 0.1, 1} x Ma in {0.3, 2}, each from the seed
 perturbation of its case index, run until C_D changes by less than 1e-6
-relative over 100 steps (or 20000 steps).
+relative over 100 steps (or 10000 steps).
 
 Calls only the CPU oracle and the seeded case definitions; the six cases
 run in parallel processes of one OpenMP thread each.  Run from the
@@ -17,7 +17,7 @@ import sys
 import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
-N, VN, BLOCK, RTOL, CAP = 64, 24, 100, 1e-6, 20000
+N, VN, BLOCK, RTOL, CAP = 64, 24, 100, 1e-6, 10000
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "converged_cd_cylinder_64x64_v24x24.json")
 
 
