@@ -90,6 +90,30 @@ def noise(c, seed=0):
     return tuple(rng.uniform(-1.0, 1.0, size=shape) for _ in range(na))
 
 
+def splitmix64_uniform(seed, start, count):
+    """Uniform values in [-1, 1) from SplitMix64 (Steele, Lea and Flood,
+    OOPSLA 2014): output j of the generator seeded with `seed` is the
+    finaliser applied to seed + j * 0x9e3779b97f4a7c15, j = start + 1 ...
+    start + count; the top 53 bits, scaled by 2^-52, minus 1.  The library
+    draws the perturbation of its device-side initial state (and of served
+    requests) from the same published generator, with j - 1 running over
+    (array, cell, node) in storage order."""
+    z = np.uint64(seed) + (np.arange(start, start + count, dtype=np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -52 - 1.0
+
+
+def hashed_noise(c, seed):
+    """The perturbation fields of a seeded device-side start (one per
+    distribution array, shape (cells, velocity nodes)): SplitMix64 values
+    with the array index running first, then cell, then node."""
+    n = n_cells(c) * n_vel(c)
+    na = 2 if c["dim"] == 2 else 1
+    return tuple(splitmix64_uniform(seed, A * n, n).reshape(n_cells(c), n_vel(c)) for A in range(na))
+
+
 def serving_requests(n=128, seed=0):
     """Seeded stream of 2D solve requests of mixed sizes on [-4,4]^2: grid
     N in {64, 96, ..., 384}, velocity grid N_xi in {16, 24, ..., 56} on

@@ -205,3 +205,19 @@ def test_server_cancel_queued_requests_host_only():
     assert sorted(r["id"] for r in res) == sorted(ids)
     assert all(r["status"] == ibdvm.E_CANCELLED and r["steps"] == 0 for r in res)
     srv.close()
+
+
+def test_splitmix64_published_outputs():
+    """The seeded-input module's SplitMix64 against the generator's published
+    first outputs for seed 0 (0xe220a8397b1dcdaf, 0x6e789e6aa1b965f4): the
+    top 53 bits survive the scaling to [-1, 1) exactly.  hashed_noise runs
+    the index over arrays first, then cells, then nodes."""
+    u = cases.splitmix64_uniform(0, 0, 2)
+    bits = ((u + 1.0) * 2.0 ** 52).astype(np.uint64)
+    assert int(bits[0]) == 0xE220A8397B1DCDAF >> 11 and int(bits[1]) == 0x6E789E6AA1B965F4 >> 11
+    c = cases.cylinder_small()
+    h, b = cases.hashed_noise(c, 9)
+    n = h.size
+    assert h.shape == (1024, 256) and np.array_equal(b.reshape(-1), cases.splitmix64_uniform(9, n, n))
+    assert np.array_equal(h[3, 5:7], cases.splitmix64_uniform(9, 3 * 256 + 5, 2))
+    assert -1.0 <= min(h.min(), b.min()) and max(h.max(), b.max()) < 1.0
