@@ -229,3 +229,37 @@ def test_full_size_sphere_near_body_window(oracle_mod, torch_cuda, precision, ti
         assert abs(cdg - cdo) <= 1e-4
     del s
     torch_cuda.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("leg", ["cavity", "implicit"])
+def test_bench_size_cavity_and_implicit_legs(oracle_mod, torch_cuda, leg):
+    """The benchmark's other 2D legs at their own sizes and tiles against the
+    oracle: the 256^2 x 100^2 lid-driven cavity from rest (3 steps, tile
+    (2,4,64), both storage forms) and the 256^2 x 48^2 cylinder at Kn 2e-4
+    with the semi-implicit collision from the seed-0 perturbation (5 steps,
+    tile (2,4,32), FP64).  FP64 within 1e-12 of each field's scale, FP32
+    storage within 1e-5 relative L2."""
+    if leg == "cavity":
+        c, steps, u, runs = cases.cavity(n=256, vn=100), 3, None, (("f64", (2, 4, 64)), ("f32", (2, 4, 64)))
+    else:
+        c = cases.case(**dict(cases.cylinder_256(Kn=2e-4, Ma=0.3), flags=("implicit",)))
+        steps, u, runs = 5, cases.noise(c, 0), (("f64", (2, 4, 32)),)
+    amp = 1e-3 if u is not None else 0.0
+    o = oracle_mod.Oracle(c)
+    o.init_freestream(u, amp)
+    o.step(steps)
+    mo = o.moments()
+    del o
+    for prec, tile in runs:
+        s = ibdvm.Solver(c, precision=prec, stream=torch_cuda.cuda.Stream())
+        s.set_tile(*tile)
+        s.init_freestream(u, amp)
+        s.step(steps)
+        mg = s.moments()
+        if prec == "f64":
+            _moments64(mg, mo)
+        else:
+            e = _fields32(mg, mo)
+            assert max(e.values()) <= 1e-5, e
+        del s
+        torch_cuda.cuda.empty_cache()
