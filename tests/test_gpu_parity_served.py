@@ -97,3 +97,23 @@ def test_served_solves_match_oracle(oracle_mod, torch_cuda, precision, fuse_belo
             for j in (0, 1, 2, 4):
                 assert np.linalg.norm(mg[ok, j] - mo[ok, j]) / np.linalg.norm(mo[ok, j]) <= 1e-5, j
             assert abs(r["C_D"] - cdo) <= 1e-4
+
+
+@pytest.mark.parametrize("tile", [(1, 8, 64), (2, 4, 32)])
+def test_long_run_unstable_request_steps_match_oracle(oracle_mod, torch_cuda, tile):
+    """Request 52 of the 128-request serving stream (a centred 384^2 circle
+    at Ma 1.30, Kn 1.9e-3, alpha 0.54, 24^2 nodes), which becomes
+    non-physical after about 5000 steps in both storage forms: its first
+    steps from the served start agree with the oracle's to 1e-12 (FP64), so
+    the library computes the oracle's step on this configuration."""
+    reqs, _ = cases.serving_requests(128, 0)
+    c = reqs[52]
+    o = _oracle(oracle_mod, c, 52, 3)
+    s = ibdvm.Solver(c, precision="f64", stream=torch_cuda.cuda.Stream())
+    s.set_tile(*tile)
+    s.init_freestream_hashed(52, AMP)
+    s.step(3)
+    _moments_close(s.moments(), o.moments(), TOL64)
+    _, cdo, _, _ = o.forces()
+    assert abs(s.surface_forces()[1] - cdo) <= TOL64 * abs(cdo)
+    s.close()
