@@ -318,12 +318,10 @@ class Solver:
         return r[:5], float(r[5])
 
     def wall_state(self):
-        n = max(self.npairs, 1) * self.NV
         ghost = np.empty((self.NA, max(self.npairs, 1), self.NV))
         face = np.empty_like(ghost)
         rhow = np.empty(max(self.npairs, 1))
         check(lib().ibdvm_wall_state(self._h, _dp(ghost), _dp(face), _dp(rhow)))
-        del n
         return {"ghost": ghost[:, : self.npairs], "face": face[:, : self.npairs], "rhow": rhow[: self.npairs]}
 
     def profile(self, enable=True):

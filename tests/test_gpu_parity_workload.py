@@ -183,7 +183,7 @@ def test_converged_cd_against_oracle(torch_cuda, row):
         s = ibdvm.Solver(c, precision=prec)
         s.init_freestream(u, 1e-3)
         s.step(row["steps"])
-        _, cd, cl, _ = s.surface_forces()
+        _, cd, _, _ = s.surface_forces()
         if prec == "f64":
             assert abs(cd - row["C_D"]) <= 1e-10 * abs(row["C_D"]), (cd, row["C_D"])
         else:
