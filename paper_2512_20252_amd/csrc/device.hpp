@@ -28,6 +28,11 @@ constexpr int kQWords = 10;
 // convergence residual: conservative variables rho, rho U[3], rho E; per
 // moment-finish workgroup the sums of squared changes, then of magnitudes
 constexpr int kResVars = 5;
+// cells per moment-finish workgroup: the explicit instance finishes four
+// per wavefront (16 lanes each), the instance that can relax one per
+// wavefront
+constexpr int kFinCells = 16;
+constexpr int kFinCellsRelax = 4;
 // per pair: momentum flux through the face F[3], then at the wall point p_w,
 // tau_w[3], q_n, and the raw moments of the wall distribution: sum w f,
 // sum w xi f [3], sum w (|xi|^2 h + b) (3D: |xi|^2 f)

@@ -87,7 +87,7 @@ Layout make_layout(const ibdvm::Geometry &g, int NA, int precision, const ibdvm:
     L.rhow = take(np * 8);
     L.fillpart = take(np * ((g.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk) * 2 * 8);
     L.pforce = take(np * ibdvm::kForceWords * 8);
-    L.respart = take((size_t)((g.Nc + 3) / 4) * 2 * ibdvm::kResVars * 8);
+    L.respart = take((size_t)((g.Nc + ibdvm::kFinCellsRelax - 1) / ibdvm::kFinCellsRelax) * 2 * ibdvm::kResVars * 8);
     L.wallT = take(p.outer == IBDVM_OUTER_WALLS || p.outer == IBDVM_OUTER_SPECULAR
                        ? (size_t)NA * 2 * (p.n[0] + p.n[1]) * g.NV * es
                        : 0);
@@ -204,6 +204,7 @@ struct ibdvm_ctx {
     int cur = 0;
     long long step = 0;
     bool pending = false;
+    int fin_cells = ibdvm::kFinCells;  // cells per workgroup of the last moment finish (its residual partials)
     bool res_valid = false;  // a step has run since the state was set: residual partials hold its change
     double Uinf = 0, mu0 = 0, Lref = 1;
     ibdvm::Tile tile{1, 8, 64};
@@ -304,6 +305,12 @@ ibdvm_status put_dev(ibdvm_ctx *c)
     return IBDVM_OK;
 }
 
+// cells per workgroup of the finish instance a context's own launches take
+int own_fin_cells(const ibdvm_ctx *c)
+{
+    return (c->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION) ? ibdvm::kFinCellsRelax : ibdvm::kFinCells;
+}
+
 ibdvm_status one_step(ibdvm_ctx *c)
 {
     const int slot = (int)(c->step & 1);
@@ -314,7 +321,9 @@ ibdvm_status one_step(ibdvm_ctx *c)
         // ghost fill reads it
         HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, false, true, c->stream));
         c->pending = false;
+        c->fin_cells = own_fin_cells(c);
     }
+    if (c->pending) c->fin_cells = own_fin_cells(c);
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, slot, true, c->pending, c->stream));
     HIP_CHECK(ibdvm::launch_wall_fill(c->dev, c->precision, c->cur, c->stream));
     if ((st = mark(c, 1)) || (st = mark(c, 0))) return st;
@@ -335,6 +344,7 @@ ibdvm_status finish_pending(ibdvm_ctx *c)
     if (!c->pending) return IBDVM_OK;
     HIP_CHECK(ibdvm::launch_fill_fin(c->dev, c->precision, c->cur, (int)(c->step & 1), false, true, c->stream));
     c->pending = false;
+    c->fin_cells = own_fin_cells(c);
     return IBDVM_OK;
 }
 
@@ -373,12 +383,16 @@ ibdvm_status fused_fill(ibdvm_ctx *const *cs, int n, bool fill, hipStream_t stre
                 ibdvm::BatchArgs fin{}, spec{}, ghost{};
                 fin.n = spec.n = ghost.n = m;
                 bool implicit = false;
+                for (int q = 0; q < m; ++q)
+                    implicit = implicit || (grp[b + q]->pending && (grp[b + q]->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION));
+                // one finish instance serves the batch: the one that can relax if any member needs it
+                const int cpb = implicit ? ibdvm::kFinCellsRelax : ibdvm::kFinCells;
                 for (int q = 0; q < m; ++q) {
-                    const ibdvm_ctx *c = grp[b + q];
-                    implicit = implicit || (c->pending && (c->prob.flags & IBDVM_FLAG_IMPLICIT_COLLISION));
+                    ibdvm_ctx *c = grp[b + q];
                     const int nfc = (c->geo.NV + ibdvm::kFillChunk - 1) / ibdvm::kFillChunk;
                     const int nfill = fill ? c->dev.npairs * nfc : 0;
-                    const int nfin = c->pending ? (c->geo.Nc + 3) / 4 : 0;
+                    const int nfin = c->pending ? (c->geo.Nc + cpb - 1) / cpb : 0;
+                    if (c->pending) c->fin_cells = cpb;
                     for (ibdvm::BatchArgs *a : {&fin, &spec, &ghost}) {
                         batch_entry(*a, q, c);
                         a->nfill[q] = nfill;
@@ -1010,7 +1024,7 @@ ibdvm_status ibdvm_residual(ibdvm_ctx *c, double res[6])
     HIP_CHECK(hipSetDevice(c->device));
     if ((st = finish_pending(c))) return st;
     constexpr int R = ibdvm::kResVars;
-    const size_t nb = (size_t)((c->geo.Nc + 3) / 4);
+    const size_t nb = (size_t)((c->geo.Nc + c->fin_cells - 1) / c->fin_cells);
     std::vector<double> part(nb * 2 * R);
     HIP_CHECK(hipMemcpyAsync(part.data(), c->dev.respart, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
     if ((st = sync_and_check(c))) return st;

@@ -485,11 +485,8 @@ __device__ void relax_cell(const DR &d, int cur, int c, double rho, const double
     for (int j = 0; j < PW; ++j) S[j] = wave_sum(acc[j]);
 }
 
-// IMPL: the instance that can take the semi-implicit branch (its relaxation
-// pass more than doubles the registers of the finish, so the explicit
-// instance leaves it out and runs at about twice the occupancy)
-template <int D, typename TS, bool IMPL, typename DR>
-__device__ void fin_cells(const DR &d, int cur, int slot, int blk)
+template <int D, typename TS, typename DR>
+__device__ void fin_cells_relax(const DR &d, int cur, int slot, int blk)
 {
     constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -507,7 +504,7 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
     // the flag word, the cell record and the partial records are read
     // together (in bounds for every c < Nc), so the wavefront waits for
     // one round trip to memory instead of three
-    const int c = blk * 4 + wv;
+    const int c = blk * kFinCellsRelax + wv;
     const bool cin = c < d.Nc;
     const size_t cs = cin ? (size_t)c : 0;
     const int fl = d.cflag[cs];
@@ -553,7 +550,7 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
         // semi-implicit collision: the new heat flux in closed form, then
         // the backward-Euler relaxation of the cell's transported state and
         // the relaxed state's moments
-        if (IMPL && (d.flags & kFlagImplicit)) {
+        if (d.flags & kFlagImplicit) {
             const double r = d.ctrl->dt * (0.5 * m0 * T) / (d.mu0 * pow(T, d.omega));
             for (int a = 0; a < D; ++a) q[a] /= 1.0 + d.Pr * r;
             const double Us[3] = {U[0], U[1], U[2]};
@@ -582,6 +579,106 @@ __device__ void fin_cells(const DR &d, int cur, int slot, int blk)
         d.respart[(size_t)blk * 2 * kResVars + threadIdx.x] =
             (rsum[0][threadIdx.x] + rsum[1][threadIdx.x]) + (rsum[2][threadIdx.x] + rsum[3][threadIdx.x]);
     tau_min_commit(d, slot, tmin);
+}
+
+template <int D, typename TS, typename DR>
+__device__ void fin_cells_explicit(const DR &d, int cur, int slot, int blk)
+{
+    constexpr int PW = D == 2 ? kPartialWords2 : kPartialWords3;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int grp = lane >> 4, l16 = lane & 15;
+    // convergence residual of Section 4, per conservative variable W = (rho,
+    // rho U[3], rho E) with rho E = rho |U|^2 / 2 + 3 rho T / 4: the block's
+    // sums of (W^{n+1} - W^n)^2 and of |W^{n+1}| (W^n: the parameters about
+    // to be replaced)
+    __shared__ double rsum[4][2 * kResVars];
+    double rv[2 * kResVars];
+#pragma unroll
+    for (int i = 0; i < 2 * kResVars; ++i) rv[i] = 0.0;
+    // four cells per wavefront, 16 lanes each: lane l16 of a group sums word
+    // l16 of the cell's partial records in record order (each load of the
+    // group reads one contiguous 128-byte record); the flag word, the cell
+    // record and the partial records are read together (in bounds for every
+    // c < Nc), so the wavefront waits for one round trip to memory
+    const int cw0 = blk * kFinCells + wv * 4;
+    const int c = cw0 + grp;
+    const bool cin = c < d.Nc;
+    const size_t cs = cin ? (size_t)c : 0;
+    const int fl = d.cflag[cs];
+    const double *cp = d.cellp + cs * kCellWords;
+    const double Uref[3] = {cp[CW_U], cp[CW_U + 1], cp[CW_U + 2]};
+    const double rho_old = cp[CW_RHO], T_old = cp[CW_T];
+    const double *pp = d.part + cs * d.nchunk * kPartialStride + l16;
+    const int nr = d.nchunk;
+    // the sums of the one-cell-per-wavefront finish in the same order, so
+    // both instances give the same bits: records r = 4 t + g go to group g,
+    // even t to e[g] and odd t to o[g], each in increasing t; then
+    // (A0 + A1) + (A2 + A3) with A_g = e[g] + o[g].  Eight records (two t,
+    // four g) are loaded before they are added; past the end they read as
+    // zero.
+    double e[4] = {0.0, 0.0, 0.0, 0.0}, o[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = 0; r < nr; r += 8) {
+        double v[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = r + m < nr ? pp[(r + m) * kPartialStride] : 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            e[g] += v[g];
+            o[g] += v[4 + g];
+        }
+    }
+    const double acc = ((e[0] + o[0]) + (e[1] + o[1])) + ((e[2] + o[2]) + (e[3] + o[3]));
+    double S[PW];
+#pragma unroll
+    for (int j = 0; j < PW; ++j) S[j] = __shfl(acc, (lane & 48) + j, 64);
+    const bool live = cin && !(fl & 1);
+    double m0 = 1.0, U[3] = {0.0, 0.0, 0.0}, T = 1.0, q[3] = {0.0, 0.0, 0.0};
+    if (live) moments_from_sums<D>(S, Uref, m0, U, T, q);
+    double tau = INFINITY;
+    if (live) {
+        const double Wo[kResVars] = {rho_old, rho_old * Uref[0], rho_old * Uref[1], rho_old * Uref[2],
+                                     rho_old * (0.5 * (Uref[0] * Uref[0] + Uref[1] * Uref[1] + Uref[2] * Uref[2]) +
+                                                0.75 * T_old)};
+        const double Wn[kResVars] = {m0, m0 * U[0], m0 * U[1], m0 * U[2],
+                                     m0 * (0.5 * (U[0] * U[0] + U[1] * U[1] + U[2] * U[2]) + 0.75 * T)};
+#pragma unroll
+        for (int i = 0; i < kResVars; ++i) {
+            rv[i] = (Wn[i] - Wo[i]) * (Wn[i] - Wo[i]);
+            rv[kResVars + i] = fabs(Wn[i]);
+        }
+        if (l16 == 0) tau = write_cell(d, c, m0, U, T, q, D);
+    }
+    // the wavefront's residual sums over its four cells, in a fixed order
+#pragma unroll
+    for (int i = 0; i < 2 * kResVars; ++i) {
+        double v = l16 == 0 ? rv[i] : 0.0;
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        rv[i] = v;
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 2 * kResVars; ++i) rsum[wv][i] = rv[i];
+    __syncthreads();
+    if (threadIdx.x < 2 * kResVars)
+        d.respart[(size_t)blk * 2 * kResVars + threadIdx.x] =
+            (rsum[0][threadIdx.x] + rsum[1][threadIdx.x]) + (rsum[2][threadIdx.x] + rsum[3][threadIdx.x]);
+    tau_min_commit(d, slot, tau);
+}
+
+// IMPL: the instance that can take the semi-implicit branch, one cell per
+// wavefront (its relaxation pass uses the whole wavefront per cell and more
+// than doubles the registers); the explicit instance finishes four cells
+// per wavefront at about twice the occupancy.  The cells per workgroup of
+// each instance (kFinCellsRelax, kFinCells) set the launch size and the
+// residual partials' count on the host.
+template <int D, typename TS, bool IMPL, typename DR>
+__device__ __forceinline__ void fin_cells(const DR &d, int cur, int slot, int blk)
+{
+    if constexpr (IMPL)
+        fin_cells_relax<D, TS>(d, cur, slot, blk);
+    else
+        fin_cells_explicit<D, TS>(d, cur, slot, blk);
 }
 
 template <int D, typename T, bool IMPL>
@@ -2269,9 +2366,10 @@ hipError_t launch_update3d(const Dev &d, int storage, int cur, int slot, const T
 hipError_t launch_fill_fin(const Dev &d, int storage, int cur, int slot, bool fill, bool fin, hipStream_t s)
 {
     const int nfill = fill ? d.npairs * ((d.NV + kFillChunk - 1) / kFillChunk) : 0;
-    const int nfin = fin ? (int)blocks_for(d.Nc, 4) : 0;
+    const bool relax = fin && (d.flags & kFlagImplicit);
+    const int nfin = fin ? (int)blocks_for(d.Nc, relax ? kFinCellsRelax : kFinCells) : 0;
     if (nfill + nfin == 0) return hipSuccess;
-    if (fin && (d.flags & kFlagImplicit))
+    if (relax)
         DISPATCH(d.D, storage,
                  hipLaunchKernelGGL((k_fill_fin<DD, TT, true>), dim3(nfill + nfin), dim3(256), 0, s, d, cur, slot, nfill, 1));
     else
