@@ -413,6 +413,61 @@ def _l1(a, b):
     return float(np.sum(np.abs(a - b)) / np.sum(np.abs(b)))
 
 
+def space_study(levels, nref, Kn, Ma, vn, t_end, block=500):
+    """Physical-space convergence (the order estimates of Section 3.3: wall
+    discontinuities cost O(dx^2) in the moments while dx is above about
+    lambda^2 / R_w, O(dx^(3/2)) below it): the cylinder R = 0.5 on
+    [-4,4]^2 at Kn, Ma on levels^2 cells, each run to t_end on the same
+    vn^2 velocity grid on [-6,6]^2, against an nref^2 run.  Errors: C_D
+    relative; p_w, the tangential shear tau_w . t and q_n along the wall,
+    each wall point against the reference's profile interpolated at its
+    polar angle (L1 relative); rho and T over the fluid cells, the
+    reference averaged over the (nref/n)^2 fine cells of each coarse cell
+    (blocks that touch the body in either grid left out).  Observed orders
+    are least-squares slopes against dx."""
+    import numpy as np
+    from paper_2512_20252_amd import cases
+
+    def case(n):
+        return cases.case(dim=2, n=(n, n), lo=(-4.0, -4.0), hi=(4.0, 4.0), vn=(vn, vn), vlo=(-6.0, -6.0),
+                          vhi=(6.0, 6.0), geometry="circle", size=(0.5, 0.0, 0.0), Kn=Kn, Ma=Ma)
+
+    def wall_profile(w):
+        th = np.arctan2(w[:, 1], w[:, 0])
+        tau_t = -w[:, 4] * w[:, 8] + w[:, 3] * w[:, 9]  # tau_w . t with t = (-n_y, n_x)
+        o = np.argsort(th)
+        return th[o], {"p_w": w[o, 7], "tau_w": tau_t[o], "q_n": w[o, 11]}
+
+    ref = _steady(case(nref), t_end, f"space study reference {nref}^2", block)
+    th_ref, W_ref = wall_profile(ref["wall"][3])
+    M_ref = ref["m"].reshape(nref, nref, 8)
+    out = {"workload": f"2D cylinder R=0.5 on [-4,4]^2 at Kn {Kn}, Ma {Ma}, {vn}^2 velocity nodes on [-6,6]^2, "
+                       f"cells {'/'.join(str(v) for v in levels)} squared against {nref}^2, t = {t_end}",
+           "reference": {"CD": ref["wall"][1], "steps": ref["steps"], "seconds": ref["seconds"]}, "levels": {}}
+    for n in levels:
+        r = _steady(case(n), t_end, f"space study {n}^2", block)
+        th, W = wall_profile(r["wall"][3])
+        e = {"CD": abs(r["wall"][1] - ref["wall"][1]) / abs(ref["wall"][1]), "steps": r["steps"]}
+        for k in W:
+            vref = np.interp(th, th_ref, W_ref[k], period=2 * np.pi)
+            e[k] = float(np.sum(np.abs(W[k] - vref)) / np.sum(np.abs(vref)))
+        k = nref // n
+        fine = M_ref.reshape(n, k, n, k, 8)
+        coarse = r["m"].reshape(n, n, 8)
+        ok = np.isfinite(fine[..., 0]).all(axis=(1, 3)) & np.isfinite(coarse[..., 0])
+        for j, name in ((0, "rho"), (4, "T")):
+            avg = fine[..., j].mean(axis=(1, 3))
+            e[name] = float(np.sum(np.abs(coarse[ok, j] - avg[ok])) / np.sum(np.abs(avg[ok])))
+        out["levels"][str(n)] = e
+    dx = np.array([8.0 / n for n in levels])
+    out["observed_order"] = {}
+    for q in ("CD", "p_w", "tau_w", "q_n", "rho", "T"):
+        err = np.array([out["levels"][str(n)][q] for n in levels])
+        if np.all(err > 0):
+            out["observed_order"][q] = float(np.polyfit(np.log(dx), np.log(err), 1)[0])
+    return out
+
+
 def vmesh_study(levels, nref, t_end, beta):
     """Velocity-mesh efficiency: the 32^2 cylinder (Ma 0.5, Kn 0.1) at steady
     state (t = t_end) on uniform midpoint and stretched (R31, beta) velocity
@@ -794,6 +849,9 @@ def main():
     ap.add_argument("--slip-study", action="store_true",
                     help="add the wall-slip comparison of the upwind weights, uniform weights and the naive "
                          "extrapolation on the Ma-5 cylinder (about a minute)")
+    ap.add_argument("--space-study", action="store_true",
+                    help="add the physical-space convergence study of the wall quantities on the cylinder "
+                         "(Section 3.3 order estimates; about 5 minutes)")
     ap.add_argument("--cavity-study", action="store_true",
                     help="add the cavity's velocity-space convergence study (about 4 minutes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -902,6 +960,8 @@ def main():
         line["sphere_vmesh_study"] = sphere_vmesh_study(48, [16, 24, 32], 48, 8.0, 2.0, 1.5)
     if args.slip_study:
         line["slip_study"] = slip_study(256, 12.0)
+    if args.space_study:
+        line["space_study"] = space_study([64, 128, 256], 1024, 0.1, 0.3, 24, 12.0, block=100)
     if args.cavity_study:
         line["cavity_velocity_study"] = cavity_velocity_study(64, [40, 60, 80, 100], 200, 40.0)
     if args.serving > 0:
