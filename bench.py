@@ -471,7 +471,8 @@ def space_study(levels, nref, Kn, Ma, vn, t_end, block=500):
 def vmesh_study(levels, nref, t_end, beta):
     """Velocity-mesh efficiency: the 32^2 cylinder (Ma 0.5, Kn 0.1) at steady
     state (t = t_end) on uniform midpoint and stretched (R31, beta) velocity
-    grids of levels^2 nodes on [-5,5]^2, against a uniform nref^2 reference:
+    grids of levels^2 nodes on [-5,5]^2, with dual-cell and with Jacobian
+    weights (R36), against a uniform nref^2 reference:
     relative errors of C_D and L1 errors of p_w, tau_w and q_n over the wall
     points.  Same N means the same cost per step."""
     import numpy as np
@@ -484,7 +485,8 @@ def vmesh_study(levels, nref, t_end, beta):
                        f"{'/'.join(str(v) for v in levels)} squared on [-5,5]^2, uniform midpoint and stretched "
                        f"(beta {beta}), against uniform {nref}^2, steady state (t = {t_end})",
            "reference": {"CD": cd_ref, "steps": ref["steps"], "residual": ref["residual"]}}
-    for tag, extra in (("uniform", {}), ("stretched", {"rule": "stretched", "vstretch": beta})):
+    for tag, extra in (("uniform", {}), ("stretched", {"rule": "stretched", "vstretch": beta}),
+                       ("stretched_jacobian", {"rule": "stretched", "vstretch": beta, "vweights": "jacobian"})):
         errs = {}
         for vn in levels:
             r = _steady(cases.case(**dict(base, vn=(vn, vn), **extra)), t_end, f"vmesh {tag} {vn}^2")
