@@ -829,7 +829,7 @@ def main():
                     help="relative C_D change per 100 steps below which a serving request has converged")
     ap.add_argument("--sphere", type=int, default=96, help="cells per side of the 3D sphere leg (0: skip)")
     ap.add_argument("--sphere-steps", type=int, default=10)
-    ap.add_argument("--sphere-tile", type=str, default="1,16,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
+    ap.add_argument("--sphere-tile", type=str, default="1,8,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
     ap.add_argument("--sphere-tile32", type=str, default="2,16,256", help="V,TX,LY of the FP32 3D update")
     ap.add_argument("--hypersonic-steps", type=int, default=20, help="timed steps of the hypersonic bodies leg (0: skip)")
     ap.add_argument("--cavity", type=int, default=256, help="cells per side of the lid-driven cavity leg (0: skip)")
