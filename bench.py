@@ -545,7 +545,8 @@ def sphere_vmesh_study(n, levels, nref, t_end, amp, width, block=200):
     stagnation temperature T_w = 1 + (gamma - 1) Ma^2 / 2, velocity box
     [-3 sqrt(T_w), 3 sqrt(T_w)]^3, here at Kn 0.1 on n^3 cells of [-4,4]^3
     (R = 0.5), FP32 storage of f; uniform midpoint grids of levels^3 nodes
-    and refined grids with the map's derivative as weight (R36; density
+    and refined grids with the map's derivative (R36) or the dual-cell
+    widths (R35) as weights (density
     1 + amp(exp(-(x/w)^2) + exp(-((x - U_inf)/w)^2)) on x, one bump at 0 on
     y and z), against a uniform nref^3 reference, each run to time t_end.
     Relative C_D error and L1 errors of p_w, tau_w and q_n over the wall
@@ -564,13 +565,13 @@ def sphere_vmesh_study(n, levels, nref, t_end, amp, width, block=200):
     ref = run(nref, {}, f"sphere study reference {nref}^3")
     cd_ref, W = ref["wall"][1], ref["wall"][3]
     out = {"workload": f"3D sphere R=0.5 at Ma {Ma}, Kn 0.1, T_w {Tw:.3f}, {n}^3 cells on [-4,4]^3, velocity box "
-                       f"[-{V:.3f},{V:.3f}]^3, uniform and refined (amp {amp}, width {width}, Jacobian weights) grids "
+                       f"[-{V:.3f},{V:.3f}]^3, uniform and refined (amp {amp}, width {width}, Jacobian or cell weights) grids "
                        f"of {'/'.join(str(v) for v in levels)} cubed against uniform {nref}^3, FP32 storage of f, "
                        f"t = {t_end}",
            "reference": {"CD": cd_ref, "steps": ref["steps"], "seconds": ref["seconds"]}}
-    refined = {"rule": "refined", "vref_amp": amp, "vref_width": width, "vref_centre": (uinf, 0.0, 0.0),
-               "vweights": "jacobian"}
-    for tag, extra in (("uniform", {}), ("refined_jacobian", refined)):
+    refined = {"rule": "refined", "vref_amp": amp, "vref_width": width, "vref_centre": (uinf, 0.0, 0.0)}
+    for tag, extra in (("uniform", {}), ("refined_jacobian", dict(refined, vweights="jacobian")),
+                       ("refined_cell", dict(refined, vweights="cell"))):
         errs = {}
         for vn in levels:
             r = run(vn, extra, f"sphere study {tag} {vn}^3")
