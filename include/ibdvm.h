@@ -154,7 +154,11 @@ typedef struct {
      * nodes per axis the discrete Maxwellian's density error falls from
      * 6e-3 to 1e-6, so the relaxation conserves mass that closely); cut
      * cells keep their incident fraction of the dual cell.  Must be
-     * IBDVM_WEIGHTS_CELL for the uniform rules. */
+     * IBDVM_WEIGHTS_CELL for the uniform rules.  For the mapped rules
+     * IBDVM_WEIGHTS_JACOBIAN is the better choice wherever it was
+     * measured (refined grids on a Ma-5 cylinder and a Ma-3.8 sphere,
+     * a stretched grid on a Ma-0.5 cylinder); the dual-cell default keeps
+     * the first reading of those rules. */
     int32_t weights;
 } ibdvm_vgrid;
 
