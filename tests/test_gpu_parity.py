@@ -150,6 +150,10 @@ EDGE = {
     "2d_256_axis": (cases.case(dim=2, n=(16, 14), lo=(-0.8, -0.7), hi=(0.8, 0.7), vn=(256, 6), vlo=(-6.0, -5.0),
                                vhi=(6.0, 5.0), geometry="circle", size=(0.22, 0.0, 0.0), Kn=0.2, Ma=0.8),
                     [(1, 8, 64), (2, 4, 32)]),
+    "3d_256_axis": (cases.case(dim=3, n=(12, 11, 10), lo=(-1.2, -1.1, -1.0), hi=(1.2, 1.1, 1.0), vn=(4, 3, 256),
+                               vlo=(-3.0, -3.0, -6.0), vhi=(3.0, 3.0, 6.0), geometry="sphere",
+                               size=(0.35, 0.0, 0.0), Kn=0.2, Ma=0.7),
+                    [(1, 16, 256), (2, 8, 5)]),
     # the smallest grids the library takes (4 cells per axis): smaller than
     # one tile and one segment, periodic
     "2d_tiny_periodic": (cases.case(dim=2, n=(4, 5), lo=(0.0, 0.0), hi=(1.0, 1.0), vn=(9, 7), vlo=(-3.0, -3.0),
