@@ -155,6 +155,46 @@ def run_gpu(case, precision, steps, warmup, seed=0, profile=True, tile=None):
     return out
 
 
+def shard_shapes(steps, warmup, full_rate, G=8):
+    """The per-GPU shares of the 256^2 cylinder split over G GPUs, each at
+    its real shape, for the two ways the step can be split:
+    * velocity: the 256^2 cells with 48 x 48/G velocity nodes (the midpoint
+      grid of the same box at G times the y spacing, which a share of
+      interleaved node rows has); the per-cell moment all-reduce and the
+      pairs' all-gather that complete a sharded step are not run;
+    * slab: 256 x 256/G cells around the body with the full 48^2 grid;
+      freestream rows stand in for the neighbours' halo rows, whose
+      exchange is not run.
+    Both storage forms, autotuned as the full-grid leg is; each rate per
+    update is compared with the full grid's FP64 rate."""
+    from paper_2512_20252_amd import cases
+
+    out = {"G": G, "steps": steps, "warmup": warmup}
+    shapes = {
+        "velocity": (cases.cylinder_256_velocity_shard(G=G),
+                     f"256x256 cells, 48x{48 // G} velocity nodes on [-6,6]^2 (stand-in nodes of a share's spacing)",
+                     {"allreduce_bytes_per_step": 65536 * 9 * 8}),
+        "slab": (cases.cylinder_256_slab(G=G),
+                 f"256x{256 // G} cells on [-8,8]x[-{8 / G},{8 / G}] around the body, 48x48 velocity nodes",
+                 {"halo_bytes_per_face_per_step": 2 * 256 * 2304 * 2 * 8}),
+    }
+    for name, (case, desc, comm) in shapes.items():
+        o = {"workload": f"per-GPU share of the 256x256 x 48x48 cylinder (Kn 0.1, Ma 0.3) over {G} GPUs: {desc}",
+             "not_run": "the exchange between shares", **comm}
+        for prec in ("f64", "f32"):
+            r = run_gpu(case, prec, steps, warmup)
+            upd = r["nfluid"] * r["NV"]
+            avg = r["prof"]["update_ms"] / max(r["prof"]["update_launches"], 1)
+            o[prec] = {"updates_per_s": upd * steps / (r["ms"] * 1e-3), "ms_per_step": r["ms"] / steps,
+                       "update_avg_launch_ms": avg,
+                       "hbm_frac": upd * B_ALG[(2, prec)] / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "fill_avg_launch_ms": r["prof"]["fill_ms"] / max(r["prof"]["fill_launches"], 1),
+                       "tile": list(r["tile"]), "fluid_cells": r["nfluid"], "velocity_nodes": r["NV"]}
+        o["f64_rate_vs_full_grid"] = o["f64"]["updates_per_s"] / full_rate
+        out[name] = o
+    return out
+
+
 def sphere3d(n, steps, warmup, tiles):
     """Full-distribution 3D sphere leg (R=0.5 in [-4,4]^3, n^3 cells, 24^3
     velocity nodes on [-6,6]^3, Kn 0.1, Ma 1.5): FP64 and FP32-storage update
@@ -828,6 +868,8 @@ def main():
     ap.add_argument("--serving-gap", type=float, default=0.5, help="mean arrival gap of the serving stream, seconds")
     ap.add_argument("--serving-tol", type=float, default=1e-3,
                     help="relative C_D change per 100 steps below which a serving request has converged")
+    ap.add_argument("--shard-steps", type=int, default=100,
+                    help="timed steps of the per-GPU share shapes of the 256^2 cylinder (0: skip)")
     ap.add_argument("--sphere", type=int, default=96, help="cells per side of the 3D sphere leg (0: skip)")
     ap.add_argument("--sphere-steps", type=int, default=10)
     ap.add_argument("--sphere-tile", type=str, default="1,8,256", help="V,TX,LY of the FP64 3D update ('' to autotune)")
@@ -935,6 +977,8 @@ def main():
                                   "update_GBs_alg": upd * 16 / (avg32 * 1e-3) / 1e9,
                                   "update_traffic": _traffic(workload, "f32", r32["tile"]),
                                   "alu": _alu(workload, "f32", r32["tile"], avg32)}
+    if args.shard_steps > 0:
+        line["shard_shapes"] = shard_shapes(args.shard_steps, args.warmup, value)
     if args.sphere > 0:
         parse = lambda t: tuple(int(x) for x in t.split(",")) if t else None
         line["sphere3d"] = sphere3d(args.sphere, args.sphere_steps, 2,

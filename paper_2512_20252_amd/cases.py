@@ -36,6 +36,34 @@ def cylinder_256(Kn=0.1, Ma=0.3, n=256, vn=48):
                 vhi=(6.0, 6.0), geometry="circle", size=(0.5, 0.0, 0.0), Kn=Kn, Ma=Ma)
 
 
+def cylinder_256_velocity_shard(G=8, Kn=0.1, Ma=0.3, n=256, vn=48):
+    """The per-GPU shape of the 256^2 cylinder when its vn x vn velocity grid
+    is split over G GPUs by interleaved rows (GPU g owning the nodes whose y
+    index is g modulo G): the same cells with a vn x (vn/G) midpoint grid on
+    the same box [-6,6]^2, whose y spacing is G times the full grid's like
+    that of a share.  A share's own nodes are offset from these by a
+    fraction of a spacing (the library takes velocity boxes symmetric about
+    0 only); the update does the same work for any node values.  Run alone
+    it is a coarse velocity grid of the same flow."""
+    if vn % G:
+        raise ValueError("the shard count must divide the nodes per axis")
+    return case(dim=2, n=(n, n), lo=(-8.0, -8.0), hi=(8.0, 8.0), vn=(vn, vn // G), vlo=(-6.0, -6.0),
+                vhi=(6.0, 6.0), geometry="circle", size=(0.5, 0.0, 0.0), Kn=Kn, Ma=Ma)
+
+
+def cylinder_256_slab(G=8, Kn=0.1, Ma=0.3, n=256, vn=48):
+    """The per-GPU shape of the 256^2 cylinder split over G GPUs into slabs
+    of n/G rows, for the slab that carries the body: n x n/G cells of the
+    same spacing centred on the cylinder ([-8,8] x [-8/G,8/G]), the full
+    vn x vn velocity grid, freestream rows beyond the slab where a share
+    would read its neighbours' halo rows."""
+    if n % G:
+        raise ValueError("the slab count must divide the rows")
+    h = 8.0 / G
+    return case(dim=2, n=(n, n // G), lo=(-8.0, -h), hi=(8.0, h), vn=(vn, vn), vlo=(-6.0, -6.0),
+                vhi=(6.0, 6.0), geometry="circle", size=(0.5, 0.0, 0.0), Kn=Kn, Ma=Ma)
+
+
 CYLINDER_256_SWEEP = [(Kn, Ma) for Kn in (0.01, 0.1, 1.0) for Ma in (0.3, 2.0)]
 
 

@@ -4,7 +4,9 @@ forms against the FP64 oracle over 20 steps; the FP32-storage form on
 reduced cylinder and hypersonic cases over enough steps to move C_D; fused
 serving batches against the oracle directly; and converged C_D of the
 cylinder's Kn x Ma sweep (64^2 x 24^2 reduction) against the oracle's
-converged values stored by tests/golden/make_converged_cd.py.
+converged values stored by tests/golden/make_converged_cd.py; the other
+benchmark legs at their own sizes, and the per-GPU share shapes of the
+cylinder under velocity and slab splits.
 
 Bars: FP64 within 1e-12 of the oracle relative to each field's scale; FP32
 storage within 1e-5 relative L2 on rho, U, T and q and 1e-4 on C_D.
@@ -256,6 +258,41 @@ def test_bench_size_cavity_and_implicit_legs(oracle_mod, torch_cuda, leg):
         s.set_tile(*tile)
         s.init_freestream(u, amp)
         s.step(steps)
+        mg = s.moments()
+        if prec == "f64":
+            _moments64(mg, mo)
+        else:
+            e = _fields32(mg, mo)
+            assert max(e.values()) <= 1e-5, e
+        del s
+        torch_cuda.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("shape", ["velocity", "slab"])
+def test_share_shapes_against_oracle(oracle_mod, torch_cuda, shape):
+    """The benchmark's per-GPU share shapes at their own sizes: the 256^2
+    cylinder with a 48 x 6 velocity grid, and a 256 x 32 slab around the body
+    with the 48^2 grid.  From the seed-0 perturbation, 3 steps against the
+    oracle in the tile the autotuner picks for each storage form (as the
+    benchmark does) and in the V = 1 and V = 2 forms (a 288-node grid leaves
+    part of the last node chunk empty in both).  FP64 within 1e-12 of each
+    field's scale, FP32 storage within 1e-5 relative L2."""
+    c = cases.cylinder_256_velocity_shard(G=8) if shape == "velocity" else cases.cylinder_256_slab(G=8)
+    u = cases.noise(c, 0)
+    o = oracle_mod.Oracle(c)
+    o.init_freestream(u, 1e-3)
+    o.step(3)
+    mo = o.moments()
+    del o
+    for prec, tile in (("f64", None), ("f64", (1, 4, 64)), ("f64", (2, 4, 32)), ("f32", None)):
+        s = ibdvm.Solver(c, precision=prec, stream=torch_cuda.cuda.Stream())
+        s.init_freestream(u, 1e-3)
+        if tile:
+            s.set_tile(*tile)
+        else:
+            s.autotune(reps=3)
+        print(shape, prec, "tile", s.get_tile(), flush=True)
+        s.step(3)
         mg = s.moments()
         if prec == "f64":
             _moments64(mg, mo)
