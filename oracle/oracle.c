@@ -1099,6 +1099,21 @@ static double upwind_dot(const or_state *s, const double *x, const double *rh)
     return (fabs(d) <= 1e-12 * sqrt(x2)) ? 0.0 : d;
 }
 
+/* upwind interpolation weights of the ns surface cells of pair p at node
+ * velocity x (Section 3.2.2, sign by reading R4): the squared positive part
+ * of -xi . r_hat_j, normalised; 1/N_S when every part is zero */
+static void upwind_weights(const or_state *s, const or_pair *p, const double *x, double *w)
+{
+    double m2[26], sum = 0.0;
+    for (int j = 0; j < p->ns; ++j) {
+        double d = upwind_dot(s, x, p->rh[j]);
+        double m = -d > 0.0 ? -d : 0.0;
+        m2[j] = m * m;
+        sum += m2[j];
+    }
+    for (int j = 0; j < p->ns; ++j) w[j] = (sum != 0.0) ? m2[j] / sum : 1.0 / p->ns;
+}
+
 /* ghost-cell construction for every pair (Section 3.2.1 steps 1-4 with the
  * weights of 3.2.2 and the velocity-space cut-cell correction of 3.2.3) */
 static void ib_fill(or_state *s)
@@ -1135,19 +1150,10 @@ static void ib_fill(or_state *s)
                     fgc = fdc + sdc * (ygc - ydc);
                 } else {
                 /* 2. upwind-weighted ghost interpolation (reading R4 for the sign) */
-                double m2[26], sum = 0.0;
+                double wu[26];
+                upwind_weights(s, p, x, wu);
                 for (int j = 0; j < p->ns; ++j) {
-                    double d = upwind_dot(s, x, p->rh[j]);
-                    double m = -d > 0.0 ? -d : 0.0;
-                    m2[j] = m * m;
-                    sum += m2[j];
-                }
-                for (int j = 0; j < p->ns; ++j) {
-                    double wj;
-                    if (s->c.flags & OR_FLAG_NO_UPWIND)
-                        wj = 1.0 / p->ns;
-                    else
-                        wj = (sum != 0.0) ? m2[j] / sum : 1.0 / p->ns;
+                    const double wj = (s->c.flags & OR_FLAG_NO_UPWIND) ? 1.0 / p->ns : wu[j];
                     double sr = 0.0;
                     for (int b = 0; b < D; ++b) sr += fluid_slope(s, f, p->sc[j], b, k) * p->r[j][b];
                     fgc += wj * (f[(size_t)p->sc[j] * NV + k] - sr);
@@ -1652,14 +1658,7 @@ int or_weights(void *h, int ip, int k, double *w)
 {
     or_state *s = (or_state *)h;
     const or_pair *p = &s->pairs[ip];
-    double m2[26], sum = 0.0;
-    for (int j = 0; j < p->ns; ++j) {
-        double d = upwind_dot(s, &s->xi[3 * k], p->rh[j]);
-        double m = -d > 0.0 ? -d : 0.0;
-        m2[j] = m * m;
-        sum += m2[j];
-    }
-    for (int j = 0; j < p->ns; ++j) w[j] = (sum != 0.0) ? m2[j] / sum : 1.0 / p->ns;
+    upwind_weights(s, p, &s->xi[3 * k], w);
     return p->ns;
 }
 

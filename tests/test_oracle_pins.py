@@ -385,6 +385,47 @@ def test_upwind_weights(oracle_mod):
     assert fallback_seen > 0
 
 
+def test_upwind_fallback_only_for_emitted_velocities(oracle_mod):
+    """Section 3.2.2 explains the 1/N_S case of the weights as velocities
+    emitted by the solid, whose wall values the wall Maxwellian replaces, and
+    the weighting as favouring the surface cells the particles come from.
+    So around convex bodies every (pair, node) whose weights fall back moves
+    away from the wall (xi . n_w > 0), and no velocity travelling into the
+    wall (xi . n_w < -|xi|/2) falls back.  Uniform weights over N_S >= 3
+    cells are the fallback (in 2D three distinct directions cannot share
+    one nonzero projection; on the sphere below no such tie occurs), read
+    off the weights the ghost fill uses.  The weight rule with its sign
+    flipped (the squared positive part of +xi . r_hat) makes every fallback
+    an incident velocity and fails this."""
+    geos = [
+        cases.cylinder_small(),
+        cases.case(dim=2, n=(48, 40), lo=(-1.2, -1.0), hi=(1.2, 1.0), vn=(12, 12), vlo=(-4.0, -4.0), vhi=(4.0, 4.0),
+                   geometry="ellipse", size=(0.6, 0.25, 0.0), aoa=0.3, Kn=0.1, Ma=0.5),
+        cases.case(dim=2, n=(64, 40), lo=(-0.4, -0.5), hi=(1.4, 0.5), vn=(12, 12), vlo=(-4.0, -4.0), vhi=(4.0, 4.0),
+                   geometry="airfoil", size=(1.0, 0.15, 0.0), aoa=0.1, Kn=0.1, Ma=0.5),
+        cases.case(dim=3, n=(16, 16, 16), lo=(-1.0,) * 3, hi=(1.0,) * 3, vn=(6, 6, 6), vlo=(-3.0,) * 3,
+                   vhi=(3.0,) * 3, geometry="sphere", size=(0.45, 0.0, 0.0), Kn=0.1, Ma=0.5),
+    ]
+    for c in geos:
+        o = oracle_mod.Oracle(c)
+        xi, _ = o.velocity()
+        nw = o.pair_geometry()["nw"]
+        fallbacks = incoming = 0
+        for ip in range(o.npairs):
+            for k in range(o.NV):
+                w = o.weights(ip, k)
+                if len(w) < 3:
+                    continue
+                xn = float(xi[k] @ nw[ip]) / float(np.linalg.norm(xi[k]))
+                if np.all(w == w[0]):
+                    fallbacks += 1
+                    assert xn > 0.0, (c["geometry"], ip, k, xn)
+                if xn < -0.5:
+                    incoming += 1
+                    assert not np.all(w == w[0]), (c["geometry"], ip, k, xn)
+        assert fallbacks > 0 and incoming > 0, c["geometry"]
+
+
 # ---------------------------------------------------------------- P8 rest state inside a diffuse wall
 def test_rest_state_stationary(oracle_mod):
     """A rest Maxwellian at T_w around a diffuse wall is a steady state of the
