@@ -669,56 +669,85 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     return out
 
 
-def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48):
-    """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep and
-    a sphere of sphere_n^3 cells (24^3 nodes, Kn 0.1, Ma 1.5): each case
-    from the same seeded state, in replays of a captured graph of `block`
-    steps; the FP64 form runs until C_D changes by less than rtol relative
-    over a replay (or `cap` steps), the FP32 form then runs the same number
-    of steps, so the two C_D differ by precision only; the updates/s of each
-    form over its run."""
+def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=False):
+    """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep, a
+    sphere of sphere_n^3 cells (24^3 nodes, Kn 0.1, Ma 1.5) and, with
+    `hypersonic`, the Ma-5 airfoil and ellipse at full size (512 x 384 cells,
+    64^2 nodes, FP32 storing f itself): the cylinders from the seed-0
+    perturbation, the sphere from the hashed one, the bodies from the
+    freestream, in replays of a captured graph of `block` steps; the FP64
+    form runs until C_D changes by less than rtol relative over a replay (or
+    `cap` steps), the FP32 form then runs the same number of steps, so the
+    two C_D differ by precision only; the updates/s of each form over its
+    run."""
     import torch
     from paper_2512_20252_amd import cases, ibdvm
 
-    out = {"workload": "2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2, "
-                       f"and 3D sphere on {sphere_n}^3 cells, 24^3 nodes; "
-                       f"C_D change below {rtol:g} relative per {block} steps or {cap} steps", "cases": []}
+    parts = []
+    if cases_kn_ma:
+        parts.append("2D cylinder R=0.5 on [-8,8]^2, 256x256 cells, 48x48 velocity nodes on [-6,6]^2")
+    if sphere_n:
+        parts.append(f"3D sphere on {sphere_n}^3 cells, 24^3 nodes")
+    if hypersonic:
+        parts.append("2D airfoil and ellipse at Ma 5, Kn 0.05, alpha 0.8, 512x384 cells, 64x64 nodes on [-10,10]^2")
+    out = {"workload": "; ".join(parts) + f"; C_D change below {rtol:g} relative per {block} steps or {cap} steps",
+           "cases": []}
     runs = [(f"cylinder Kn {Kn} Ma {Ma}", {"Kn": Kn, "Ma": Ma}, cases.cylinder_256(Kn=Kn, Ma=Ma))
             for Kn, Ma in cases_kn_ma]
     if sphere_n:
         runs.append((f"sphere {sphere_n}^3", {"sphere_n": sphere_n, "Kn": 0.1, "Ma": 1.5},
                      cases.sphere(n=sphere_n, vn=24)))
+    if hypersonic:
+        for body, case in zip(("airfoil", "ellipse"), cases.hypersonic_bodies(0)):
+            runs.append((f"hypersonic {body}", {"body": body, "Kn": 0.05, "Ma": 5.0, "alpha": 0.8},
+                         cases.case(**dict(case, flags=("f32_absolute",)))))
     for label, row, case in runs:
         row = dict(row)
         for prec in ("f64", "f32"):
+            if prec == "f32" and row["f64"]["failed"]:
+                break
             s = ibdvm.Solver(case, precision=prec, stream=torch.cuda.Stream())
-            if case["dim"] == 2:
+            if "body" in row:
+                s.init_freestream()
+                row[prec + "_tile"] = list(s.autotune(reps=2))
+            elif case["dim"] == 2:
                 s.init_freestream(cases.noise(case, 0), 1e-3)
                 s.set_tile(2, 4, 32)
             else:
                 s.init_freestream_hashed(0, 1e-3)  # a host array of the 3D state would be large
             g = ibdvm.Graph(s, block)
             cd_prev, change, steps, t = None, None, 0, time.perf_counter()
+            t_print = t
             limit = cap if prec == "f64" else row["f64"]["steps"]
-            while steps < limit:
-                g.launch()
-                steps += block
-                cd = s.surface_forces()[1]
-                change = abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None
-                cd_prev = cd
-                if prec == "f64" and change is not None and change < rtol:
-                    break
+            cd, failed = None, None
+            try:
+                while steps < limit:
+                    g.launch()
+                    steps += block
+                    cd = s.surface_forces()[1]
+                    change = abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None
+                    cd_prev = cd
+                    if time.perf_counter() - t_print > 30.0:
+                        t_print = time.perf_counter()
+                        print(f"precision sweep: {label} {prec}: step {steps}, C_D {cd:.8f}", file=sys.stderr,
+                              flush=True)
+                    if prec == "f64" and change is not None and change < rtol:
+                        break
+            except ibdvm.IbdvmError as e:  # the health word reported a non-physical state
+                failed = f"{e} in the replay ending at step {steps}"
             wall = time.perf_counter() - t
             # the change over the last replay, taken before cd_prev moved on
-            row[prec] = {"CD": cd, "steps": steps, "converged": change is not None and change < rtol,
-                         "last_rel_change": change, "updates_per_s": s.nfluid * s.NV * steps / wall}
-            print(f"precision sweep: {label} {prec}: C_D {cd:.8f} after {steps} steps", file=sys.stderr, flush=True)
+            row[prec] = {"CD": cd, "steps": steps, "converged": failed is None and change is not None and change < rtol,
+                         "last_rel_change": change, "updates_per_s": s.nfluid * s.NV * steps / wall, "failed": failed}
+            print(f"precision sweep: {label} {prec}: C_D {cd} after {steps} steps" + (f" ({failed})" if failed else ""),
+                  file=sys.stderr, flush=True)
             g.close()
             s.close()
             torch.cuda.empty_cache()
-        row["dCD"] = abs(row["f32"]["CD"] - row["f64"]["CD"])
-        row["dCD_rel"] = row["dCD"] / abs(row["f64"]["CD"])
-        row["ratio_f32_vs_f64"] = row["f32"]["updates_per_s"] / row["f64"]["updates_per_s"]
+        if "f32" in row and not row["f64"]["failed"] and not row["f32"]["failed"]:
+            row["dCD"] = abs(row["f32"]["CD"] - row["f64"]["CD"])
+            row["dCD_rel"] = row["dCD"] / abs(row["f64"]["CD"])
+            row["ratio_f32_vs_f64"] = row["f32"]["updates_per_s"] / row["f64"]["updates_per_s"]
         out["cases"].append(row)
     return out
 
@@ -885,6 +914,8 @@ def main():
     ap.add_argument("--precision-sweep", action="store_true",
                     help="add FP32 storage against FP64 over the cylinder's Kn x Ma sweep, run toward convergence")
     ap.add_argument("--sweep-sphere-only", action="store_true", help="run only the sphere case of the precision sweep")
+    ap.add_argument("--hypersonic-sweep", action="store_true",
+                    help="FP32 storage against FP64 on the Ma-5 airfoil and ellipse at full size, to converged C_D")
     ap.add_argument("--vmesh-study", action="store_true",
                     help="add the uniform-vs-stretched velocity-grid study on the 32^2 cylinder (about 1 minute)")
     ap.add_argument("--refined-study", action="store_true",
@@ -998,6 +1029,8 @@ def main():
     if args.precision_sweep:
         line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP if not args.sweep_sphere_only else [], 1e-5,
                                                   20000)
+    if args.hypersonic_sweep:
+        line["precision_sweep_hypersonic"] = precision_sweep([], 1e-6, 30000, sphere_n=0, hypersonic=True)
     if args.vmesh_study:
         line["vmesh_study"] = vmesh_study([8, 12, 16, 24, 32], 128, 30.0, 1.5)
     if args.refined_study:
