@@ -669,17 +669,17 @@ def cavity_velocity_study(n, levels, nref, t_end, block=1000):
     return out
 
 
-def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=False):
+def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=False, atol=None):
     """FP32 storage against FP64 over the 256^2 cylinder's Kn x Ma sweep, a
     sphere of sphere_n^3 cells (24^3 nodes, Kn 0.1, Ma 1.5) and, with
     `hypersonic`, the Ma-5 airfoil and ellipse at full size (512 x 384 cells,
     64^2 nodes, FP32 storing f itself): the cylinders from the seed-0
     perturbation, the sphere from the hashed one, the bodies from the
     freestream, in replays of a captured graph of `block` steps; the FP64
-    form runs until C_D changes by less than rtol relative over a replay (or
-    `cap` steps), the FP32 form then runs the same number of steps, so the
-    two C_D differ by precision only; the updates/s of each form over its
-    run."""
+    form runs until C_D changes by less than rtol relative (or, given atol,
+    by less than atol) over a replay, or `cap` steps, the FP32 form then
+    runs the same number of steps, so the two C_D differ by precision only;
+    the updates/s of each form over its run."""
     import torch
     from paper_2512_20252_amd import cases, ibdvm
 
@@ -690,7 +690,8 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=F
         parts.append(f"3D sphere on {sphere_n}^3 cells, 24^3 nodes")
     if hypersonic:
         parts.append("2D airfoil and ellipse at Ma 5, Kn 0.05, alpha 0.8, 512x384 cells, 64x64 nodes on [-10,10]^2")
-    out = {"workload": "; ".join(parts) + f"; C_D change below {rtol:g} relative per {block} steps or {cap} steps",
+    crit = f"{atol:g} absolute" if atol is not None else f"{rtol:g} relative"
+    out = {"workload": "; ".join(parts) + f"; C_D change below {crit} per {block} steps or {cap} steps",
            "cases": []}
     runs = [(f"cylinder Kn {Kn} Ma {Ma}", {"Kn": Kn, "Ma": Ma}, cases.cylinder_256(Kn=Kn, Ma=Ma))
             for Kn, Ma in cases_kn_ma]
@@ -701,6 +702,7 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=F
         for body, case in zip(("airfoil", "ellipse"), cases.hypersonic_bodies(0)):
             runs.append((f"hypersonic {body}", {"body": body, "Kn": 0.05, "Ma": 5.0, "alpha": 0.8},
                          cases.case(**dict(case, flags=("f32_absolute",)))))
+    tol = atol if atol is not None else rtol
     for label, row, case in runs:
         row = dict(row)
         for prec in ("f64", "f32"):
@@ -725,20 +727,21 @@ def precision_sweep(cases_kn_ma, rtol, cap, block=100, sphere_n=48, hypersonic=F
                     g.launch()
                     steps += block
                     cd = s.surface_forces()[1]
-                    change = abs(cd - cd_prev) / abs(cd) if cd_prev is not None else None
+                    change = None if cd_prev is None else (abs(cd - cd_prev) if atol is not None
+                                                           else abs(cd - cd_prev) / abs(cd))
                     cd_prev = cd
                     if time.perf_counter() - t_print > 30.0:
                         t_print = time.perf_counter()
                         print(f"precision sweep: {label} {prec}: step {steps}, C_D {cd:.8f}", file=sys.stderr,
                               flush=True)
-                    if prec == "f64" and change is not None and change < rtol:
+                    if prec == "f64" and change is not None and change < tol:
                         break
             except ibdvm.IbdvmError as e:  # the health word reported a non-physical state
                 failed = f"{e} in the replay ending at step {steps}"
             wall = time.perf_counter() - t
             # the change over the last replay, taken before cd_prev moved on
-            row[prec] = {"CD": cd, "steps": steps, "converged": failed is None and change is not None and change < rtol,
-                         "last_rel_change": change, "updates_per_s": s.nfluid * s.NV * steps / wall, "failed": failed}
+            row[prec] = {"CD": cd, "steps": steps, "converged": failed is None and change is not None and change < tol,
+                         "last_change": change, "updates_per_s": s.nfluid * s.NV * steps / wall, "failed": failed}
             print(f"precision sweep: {label} {prec}: C_D {cd} after {steps} steps" + (f" ({failed})" if failed else ""),
                   file=sys.stderr, flush=True)
             g.close()
@@ -1027,8 +1030,11 @@ def main():
             if "precision_form" in line:
                 line["precision_form"]["max_dCD_vs_oracle_converged"] = fc["max_dCD_f32_vs_oracle"]
     if args.precision_sweep:
-        line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP if not args.sweep_sphere_only else [], 1e-5,
-                                                  20000)
+        if args.sweep_sphere_only:
+            line["precision_sweep"] = precision_sweep([], 1e-5, 20000)
+        else:
+            # the cylinder's convergence criterion: C_D moves by less than 1e-6 over 100 steps
+            line["precision_sweep"] = precision_sweep(cases.CYLINDER_256_SWEEP, None, 50000, sphere_n=0, atol=1e-6)
     if args.hypersonic_sweep:
         line["precision_sweep_hypersonic"] = precision_sweep([], 1e-6, 30000, sphere_n=0, hypersonic=True)
     if args.vmesh_study:
