@@ -244,6 +244,33 @@ ibdvm_status ibdvm_set_state(ibdvm_ctx *ctx, const double *f0, const double *f1)
 /* Copies the state to host doubles.  Synchronises. */
 ibdvm_status ibdvm_get_state(ibdvm_ctx *ctx, double *f0, double *f1);
 
+/* Checkpoint and resume of the time march (Section 2.2) between steps.
+ * ibdvm_set_state starts a new march from a state: it restarts the clock
+ * and recomputes the moments with a summation order of its own.  A
+ * checkpoint record instead holds everything the next step reads: the
+ * stored state in its storage precision, the per-cell moment and
+ * equilibrium records of that state, the clock (time, step, time-step
+ * bookkeeping) and the update tile (the node-chunk width fixes the order of
+ * the moment sums).  So a context restored from it takes the same steps as
+ * the checkpointed one would have, bit for bit.
+ *   ibdvm_checkpoint_bytes: the size of a record of this context (also on
+ *     host-only contexts); state arrays dominate it.
+ *   ibdvm_checkpoint: writes the record to caller host memory of at least
+ *     that size (bytes); completes the pending moment finish; a context
+ *     whose health word reports a non-physical state is refused with
+ *     IBDVM_E_UNSTABLE and no record is written.
+ *   ibdvm_restore: loads a record into a context created with the same
+ *     grid, velocity grid, geometry, physics, options and precision (the
+ *     record carries a fingerprint of them and the sizes; a mismatch, a
+ *     truncated or foreign record gives IBDVM_E_INVALID_ARG and leaves the
+ *     context as it was), and takes the record's tile.  Graphs captured on
+ *     the context before the restore are refused afterwards if the step
+ *     parity changed (IBDVM_E_STATE), as after any odd number of steps.
+ * Both synchronise the context stream; the caller owns the record. */
+ibdvm_status ibdvm_checkpoint_bytes(const ibdvm_ctx *ctx, size_t *bytes);
+ibdvm_status ibdvm_checkpoint(ibdvm_ctx *ctx, void *record, size_t bytes);
+ibdvm_status ibdvm_restore(ibdvm_ctx *ctx, const void *record, size_t bytes);
+
 /* Enqueues nsteps forward-Euler steps on the context stream: ghost-cell
  * construction (Section 3.2), upwind MUSCL fluxes (Section 2.2) and Shakhov
  * relaxation with moments of the new state, time step

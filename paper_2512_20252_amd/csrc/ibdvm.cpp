@@ -895,6 +895,145 @@ ibdvm_status ibdvm_get_state(ibdvm_ctx *c, double *f0, double *f1)
     return sync_and_check(c);
 }
 
+namespace {
+bool tile_supported(int dim, const ibdvm::Tile &t);
+
+// checkpoint record: this header, the control block, the cell records
+// (moments, then update parameters) and the stored state arrays, each at
+// an 8-byte aligned offset in that order
+struct CkptHeader {
+    char magic[8];
+    uint64_t fingerprint;
+    int64_t Nc, NV, npairs, step;
+    int32_t dim, NA, precision, V, TX, LY;
+    uint64_t ctrl_bytes, cellp_bytes, cellq_bytes, state_bytes;
+};
+constexpr char kCkptMagic[8] = {'I', 'B', 'D', 'V', 'M', 'C', 'K', '1'};
+
+// FNV-1a over the values that define a solve: a record restores only into
+// a context of the same problem, physics and storage precision (each value
+// hashed by its own bytes, arrays whole: no padding enters)
+void fnv(uint64_t &h, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+}
+
+uint64_t fingerprint(const ibdvm_ctx *c)
+{
+    const ibdvm::Problem &p = c->prob;
+    uint64_t h = 14695981039346656037ull;
+#define IBDVM_FP(x) fnv(h, &(x), sizeof(x))
+    IBDVM_FP(p.dim), IBDVM_FP(p.n), IBDVM_FP(p.lo), IBDVM_FP(p.hi), IBDVM_FP(p.outer), IBDVM_FP(p.lid_u);
+    IBDVM_FP(p.vn), IBDVM_FP(p.vlo), IBDVM_FP(p.vhi), IBDVM_FP(p.rule), IBDVM_FP(p.vstretch), IBDVM_FP(p.vref_amp);
+    IBDVM_FP(p.vref_width), IBDVM_FP(p.vref_centre), IBDVM_FP(p.vweights), IBDVM_FP(p.gkind), IBDVM_FP(p.gcen);
+    IBDVM_FP(p.gsize), IBDVM_FP(p.aoa), IBDVM_FP(p.flags), IBDVM_FP(p.Uw), IBDVM_FP(p.Ow);
+    IBDVM_FP(c->Kn), IBDVM_FP(c->Ma), IBDVM_FP(c->Pr), IBDVM_FP(c->gam), IBDVM_FP(c->alpha), IBDVM_FP(c->Tw);
+    IBDVM_FP(c->cfl), IBDVM_FP(c->omega), IBDVM_FP(c->avhs), IBDVM_FP(c->precision), IBDVM_FP(c->NA);
+#undef IBDVM_FP
+    return h;
+}
+
+size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+struct CkptSizes {
+    size_t ctrl, cellp, cellq, state, total;
+};
+
+CkptSizes ckpt_sizes(const ibdvm_ctx *c)
+{
+    CkptSizes z;
+    z.ctrl = sizeof(ibdvm::Ctrl);
+    z.cellp = (size_t)c->geo.Nc * ibdvm::kCellWords * 8;
+    z.cellq = (size_t)c->geo.Nc * ibdvm::kQWords * 8;
+    z.state = c->L.state_bytes;
+    z.total = align8(sizeof(CkptHeader)) + align8(z.ctrl) + align8(z.cellp) + align8(z.cellq) + (size_t)c->NA * align8(z.state);
+    return z;
+}
+}  // namespace
+
+ibdvm_status ibdvm_checkpoint_bytes(const ibdvm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(IBDVM_E_INVALID_ARG, "null argument");
+    *bytes = ckpt_sizes(c).total;
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_checkpoint(ibdvm_ctx *c, void *record, size_t bytes)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!record) return fail(IBDVM_E_INVALID_ARG, "null record");
+    const CkptSizes z = ckpt_sizes(c);
+    if (bytes < z.total) return fail(IBDVM_E_INVALID_ARG, "checkpoint record smaller than ibdvm_checkpoint_bytes");
+    HIP_CHECK(hipSetDevice(c->device));
+    // the cell records of the current state are complete once its moment
+    // finish has run; a non-physical state is not checkpointed
+    if ((st = finish_pending(c)) || (st = sync_and_check(c))) return st;
+    char *out = (char *)record;
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, sizeof(h.magic));
+    h.fingerprint = fingerprint(c);
+    h.Nc = c->geo.Nc, h.NV = c->geo.NV, h.npairs = (int64_t)c->geo.pairs.size(), h.step = c->step;
+    h.dim = c->prob.dim, h.NA = c->NA, h.precision = c->precision;
+    h.V = c->tile.V, h.TX = c->tile.TX, h.LY = c->tile.LY;
+    h.ctrl_bytes = z.ctrl, h.cellp_bytes = z.cellp, h.cellq_bytes = z.cellq, h.state_bytes = z.state;
+    std::memcpy(out, &h, sizeof(h));
+    size_t off = align8(sizeof(CkptHeader));
+    auto get = [&](size_t dev_off, size_t n) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(out + off, c->ws + dev_off, n, hipMemcpyDeviceToHost, c->stream);
+        off += align8(n);
+        return e;
+    };
+    HIP_CHECK(get(c->L.ctrl, z.ctrl));
+    HIP_CHECK(get(c->L.cellp, z.cellp));
+    HIP_CHECK(get(c->L.cellq, z.cellq));
+    for (int A = 0; A < c->NA; ++A) HIP_CHECK(get(c->L.f[c->cur][A], z.state));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    return IBDVM_OK;
+}
+
+ibdvm_status ibdvm_restore(ibdvm_ctx *c, const void *record, size_t bytes)
+{
+    ibdvm_status st = require_device(c);
+    if (st) return st;
+    if (!record) return fail(IBDVM_E_INVALID_ARG, "null record");
+    const CkptSizes z = ckpt_sizes(c);
+    if (bytes < sizeof(CkptHeader)) return fail(IBDVM_E_INVALID_ARG, "checkpoint record too short");
+    CkptHeader h;
+    std::memcpy(&h, record, sizeof(h));
+    if (std::memcmp(h.magic, kCkptMagic, sizeof(h.magic)) != 0) return fail(IBDVM_E_INVALID_ARG, "not a checkpoint record");
+    if (h.fingerprint != fingerprint(c) || h.Nc != c->geo.Nc || h.NV != c->geo.NV ||
+        h.npairs != (int64_t)c->geo.pairs.size() || h.dim != c->prob.dim || h.NA != c->NA || h.precision != c->precision ||
+        h.ctrl_bytes != z.ctrl || h.cellp_bytes != z.cellp || h.cellq_bytes != z.cellq || h.state_bytes != z.state)
+        return fail(IBDVM_E_INVALID_ARG, "checkpoint of a different problem, precision or size");
+    if (bytes < z.total) return fail(IBDVM_E_INVALID_ARG, "checkpoint record truncated");
+    const ibdvm::Tile t{h.V, h.TX, h.LY};
+    if (!tile_supported(c->prob.dim, t) || h.step < 0) return fail(IBDVM_E_INVALID_ARG, "corrupt checkpoint header");
+    HIP_CHECK(hipSetDevice(c->device));
+    // nothing of the context's own may still be writing these buffers
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    const char *in = (const char *)record;
+    size_t off = align8(sizeof(CkptHeader));
+    auto put = [&](size_t dev_off, size_t n) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(c->ws + dev_off, in + off, n, hipMemcpyHostToDevice, c->stream);
+        off += align8(n);
+        return e;
+    };
+    HIP_CHECK(put(c->L.ctrl, z.ctrl));
+    HIP_CHECK(put(c->L.cellp, z.cellp));
+    HIP_CHECK(put(c->L.cellq, z.cellq));
+    for (int A = 0; A < c->NA; ++A) HIP_CHECK(put(c->L.f[c->cur][A], z.state));
+    c->step = h.step;
+    c->pending = false;
+    c->res_valid = false;
+    c->fin_cells = own_fin_cells(c);
+    c->tile = t;
+    c->dev.nchunk = (c->geo.NV + 64 * t.V - 1) / (64 * t.V);
+    if ((st = put_dev(c))) return st;
+    return sync_and_check(c);
+}
+
 ibdvm_status ibdvm_step(ibdvm_ctx *c, int32_t nsteps)
 {
     ibdvm_status st = require_device(c);

@@ -74,7 +74,7 @@ EXPORTS = ["ibdvm_footprint", "ibdvm_create", "ibdvm_destroy", "ibdvm_info", "ib
            "ibdvm_graph_destroy", "ibdvm_server_create", "ibdvm_server_submit", "ibdvm_server_poll",
            "ibdvm_server_info", "ibdvm_server_clock", "ibdvm_server_error", "ibdvm_server_destroy", "ibdvm_set_stream",
            "ibdvm_server_set_fusion", "ibdvm_residual", "ibdvm_server_cancel", "ibdvm_stream_copy",
-           "ibdvm_surface_forces_static"]
+           "ibdvm_surface_forces_static", "ibdvm_checkpoint_bytes", "ibdvm_checkpoint", "ibdvm_restore"]
 _NOT_STATUS = ("ibdvm_destroy", "ibdvm_last_error", "ibdvm_graph_destroy", "ibdvm_server_clock",
                "ibdvm_server_error", "ibdvm_server_destroy")
 
@@ -129,6 +129,9 @@ def lib():
         L.ibdvm_server_cancel.argtypes = [c_void_p, ctypes.c_int64]
         L.ibdvm_stream_copy.argtypes = [c_void_p, c_void_p, c_size_t, c_void_p]
         L.ibdvm_surface_forces_static.argtypes = [c_void_p, c_void_p, c_int32]
+        L.ibdvm_checkpoint_bytes.argtypes = [c_void_p, P(c_size_t)]
+        L.ibdvm_checkpoint.argtypes = [c_void_p, c_void_p, c_size_t]
+        L.ibdvm_restore.argtypes = [c_void_p, c_void_p, c_size_t]
         L.ibdvm_server_clock.argtypes = [c_void_p]
         L.ibdvm_server_clock.restype = c_double
         L.ibdvm_server_error.argtypes = [c_void_p]
@@ -273,6 +276,19 @@ class Solver:
         f1 = np.empty((self.Nc, self.NV)) if self.NA == 2 else None
         check(lib().ibdvm_get_state(self._h, _dp(f0), _dp(f1)))
         return (f0, f1) if self.NA == 2 else (f0,)
+
+    def checkpoint(self):
+        """A checkpoint record of the solve (host bytes): ibdvm_checkpoint."""
+        n = c_size_t()
+        check(lib().ibdvm_checkpoint_bytes(self._h, ctypes.byref(n)))
+        rec = np.empty(n.value, dtype=np.uint8)
+        check(lib().ibdvm_checkpoint(self._h, rec.ctypes.data_as(c_void_p), n.value))
+        return rec
+
+    def restore(self, record):
+        """Resume from a checkpoint record: ibdvm_restore."""
+        rec = np.ascontiguousarray(record, dtype=np.uint8)
+        check(lib().ibdvm_restore(self._h, rec.ctypes.data_as(c_void_p), rec.size))
 
     def step(self, n=1):
         check(lib().ibdvm_step(self._h, int(n)))

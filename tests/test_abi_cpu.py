@@ -121,6 +121,23 @@ def test_argument_validation():
     ibdvm.Solver(cases.cavity(n=32, vn=12), host_only=True)
 
 
+def test_checkpoint_size_and_host_only_refusal():
+    """The checkpoint record's size is known on a host-only context (header,
+    control block, the two cell records and the stored state arrays in the
+    storage precision); writing or loading one needs device state."""
+    for prec, es in (("f64", 8), ("f32", 4)):
+        c = cases.cylinder_small()
+        s = ibdvm.Solver(c, precision=prec, host_only=True)
+        n = ctypes.c_size_t()
+        assert ibdvm.lib().ibdvm_checkpoint_bytes(s._h, ctypes.byref(n)) == ibdvm.OK
+        state = 2 * cases.n_cells(c) * cases.n_vel(c) * es
+        assert state < n.value < state + cases.n_cells(c) * 26 * 8 + 4096
+        _expect(ibdvm.E_STATE, s.checkpoint)
+        _expect(ibdvm.E_STATE, lambda: s.restore(np.zeros(n.value, dtype=np.uint8)))
+    assert ibdvm.lib().ibdvm_checkpoint_bytes(None, ctypes.byref(n)) == ibdvm.E_INVALID_ARG
+    assert ibdvm.lib().ibdvm_checkpoint_bytes(s._h, None) == ibdvm.E_INVALID_ARG
+
+
 def test_walls_footprint_holds_ghost_rows():
     """Outer walls add 2 (nx + ny) ghost rows per array to the workspace."""
     c = cases.cavity(n=40, vn=16)
