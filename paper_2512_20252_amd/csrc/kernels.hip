@@ -1296,7 +1296,12 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
         T(&hnext)[2][V] = HH[(S + 1) & 1];
         const int c = i + nx * j;
 
-        // prefetch: own column row j+3, halo column row j+1
+        // prefetch: own column row j+3, halo column row j+1.  The loads are
+        // issued at a raised wavefront priority: the three wavefronts of a
+        // SIMD compete for issue, and a wavefront that reaches its loads
+        // then gets them in flight ahead of the others' arithmetic (the
+        // FP64 update runs 1-2 % faster; the results do not change)
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int A = 0; A < 2; ++A) {
             const brsrc r3 = mk_rsrc(rowp(A, fcol[A], cfs, cxw, ie, j + 3), rowb);
@@ -1307,6 +1312,7 @@ __device__ __forceinline__ void update2d_tile(const DR &d, int cur, int slot, in
                 hnext[A][v] = bld(rh, koff[v], T());
             }
         }
+        __builtin_amdgcn_s_setprio(0);
 
         // stage row j
 #pragma unroll
