@@ -25,6 +25,7 @@ SPECS = {
     "2d-implicit": (dict(cases.cylinder_small(), Kn=0.002, flags=("implicit",)), "f64", (2, 4, 32), (1, 8, 16)),
     "2d-cavity-f32": (cases.cavity(n=24, vn=12), "f32", (2, 4, 8), (1, 8, 64)),
     "3d-f64": (cases.sphere(n=14, vn=6), "f64", (1, 8, 256), (2, 16, 256)),
+    "3d-f32-alpha0.8": (dict(cases.sphere(n=14, vn=6), alpha=0.8), "f32", (2, 16, 256), (1, 8, 5)),
 }
 
 
